@@ -1,0 +1,162 @@
+"""Oracle for the FFT stencil solver: plain, slow, obviously correct CPU code.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+benchmark's CPU-baseline leg may import this package.  The product library
+(``paper_2105_06676_amd``) never imports it and shares no code with it.
+
+Contents
+--------
+``periodic(a, coeffs, T)``
+    T sweeps of the periodic nested loop in FP64 (C, ``loops.c``): the plain
+    definition ``a_T = S^T a_0`` of the paper's periodic problem (Sec. 3, the
+    periodic looping algorithm; d-D form in the appendix on d-D grids).
+``aperiodic(a, coeffs, T)``
+    The aperiodic nested loop with a fixed r-wide frame (Sec. 2 aperiodic looping
+    algorithm; Sec. 4 for what StencilFFT-A must reproduce).
+``symbol(coeffs, dims)``
+    Step 1(i) of the periodic algorithm written literally: build the first column
+    ``s`` of the circulant matrix and take its N-point DFT (appendix, eigenvalue-FFT
+    relation).  numpy's FFT serves as the DFT primitive.
+``symbol_power(lam, T)``
+    Step 2: ``lam**T`` by binary repeated squaring (Sec. 3, repeated squaring),
+    carried out in 60-digit decimal arithmetic so that the FP64 GPU value can be
+    judged against a reference far more accurate than itself.
+``dist(shape_interior)``
+    Distance of every interior cell to the fixed frame, 1 + min over faces
+    (Sec. 4's region-of-influence notation).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from decimal import Decimal, getcontext
+from typing import Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "loops.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile ``loops.c`` into ``liboracle.so`` (gcc, OpenMP, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O3", "-march=native", "-ffp-contract=off", "-fno-fast-math",
+               "-fopenmp", "-shared", "-fPIC", "-o", tmp, _SRC]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        for name in ("oracle_periodic", "oracle_aperiodic"):
+            f = getattr(lib, name)
+            f.restype = ctypes.c_int
+            f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                          ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
+        lib.oracle_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def threads() -> int:
+    return int(_load().oracle_threads())
+
+
+def _check_coeffs(coeffs: np.ndarray, ndim: int) -> int:
+    c = np.asarray(coeffs)
+    if c.ndim != ndim or len(set(c.shape)) != 1 or c.shape[0] % 2 != 1:
+        raise ValueError(f"coefficients must be (2r+1,)*{ndim}, got {c.shape}")
+    return (c.shape[0] - 1) // 2
+
+
+def periodic(a: np.ndarray, coeffs: np.ndarray, T: int, nthreads: int = 0) -> np.ndarray:
+    """``a_T`` after T periodic sweeps; input is widened to float64 (exact for float32)."""
+    x = np.ascontiguousarray(a, dtype=np.float64).copy()
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    r = _check_coeffs(c, x.ndim)
+    dims = (ctypes.c_int64 * x.ndim)(*x.shape)
+    rc = _load().oracle_periodic(x.ctypes.data, x.ndim, dims, c.ctypes.data, r, int(T), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"oracle_periodic failed ({rc})")
+    return x
+
+
+def aperiodic(a: np.ndarray, coeffs: np.ndarray, T: int, nthreads: int = 0) -> np.ndarray:
+    """``a`` has extents n_i + 2r; the r-wide frame is fixed; the interior evolves T steps."""
+    x = np.ascontiguousarray(a, dtype=np.float64).copy()
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    r = _check_coeffs(c, x.ndim)
+    interior = [s - 2 * r for s in x.shape]
+    if min(interior) < 1:
+        raise ValueError("interior extents must be >= 1")
+    dims = (ctypes.c_int64 * x.ndim)(*interior)
+    rc = _load().oracle_aperiodic(x.ctypes.data, x.ndim, dims, c.ctypes.data, r, int(T), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"oracle_aperiodic failed ({rc})")
+    return x
+
+
+def first_column(coeffs: np.ndarray, dims: Sequence[int]) -> np.ndarray:
+    """First column ``s[m] = S[m, 0]`` of the circulant stencil matrix.
+
+    Row 0 of ``S`` updates cell 0 from neighbour ``(0 + o) mod n`` with weight
+    ``c[o]``, so ``S[0, o mod n] += c[o]``; circulance ``S[i, j] = s[i - j]`` (Sec. 3)
+    then gives ``s[(-o) mod n] += c[o]`` (offsets alias modulo n for tiny grids)."""
+    c = np.asarray(coeffs, dtype=np.float64)
+    d = c.ndim
+    r = (c.shape[0] - 1) // 2
+    s = np.zeros(tuple(dims), dtype=np.float64)
+    for idx in np.ndindex(*c.shape):
+        o = [k - r for k in idx]
+        pos = tuple((-oi) % n for oi, n in zip(o, dims))
+        s[pos] += c[idx]
+    return s
+
+
+def symbol(coeffs: np.ndarray, dims: Sequence[int]) -> np.ndarray:
+    """``Lambda = F s``: unnormalised forward DFT (exponent -2 pi i) of the first column."""
+    return np.fft.fftn(first_column(coeffs, dims))
+
+
+def symbol_power(lam: np.ndarray, T: int, digits: int = 60) -> np.ndarray:
+    """``lam**T`` elementwise by binary repeated squaring in ``digits``-digit decimals.
+
+    The FP64 inputs are taken as exact; only the powering is done here.  Slow: meant
+    for a few thousand elements."""
+    getcontext().prec = digits
+    flat = np.asarray(lam, dtype=np.complex128).ravel()
+    out = np.empty_like(flat)
+    for i, z in enumerate(flat):
+        vr, vi = Decimal(1), Decimal(0)
+        sr, si = Decimal(float(z.real)), Decimal(float(z.imag))
+        R = int(T)
+        while R > 0:
+            if R & 1:
+                vr, vi = vr * sr - vi * si, vr * si + vi * sr
+            R >>= 1
+            if R:
+                sr, si = sr * sr - si * si, 2 * sr * si
+        out[i] = complex(float(vr), float(vi))
+    return out.reshape(np.shape(lam))
+
+
+def dist(interior: Sequence[int]) -> np.ndarray:
+    """``1 + min over faces`` of the index distance of each interior cell to the frame."""
+    d = None
+    for ax, n in enumerate(interior):
+        i = np.arange(n)
+        di = np.minimum(i + 1, n - i)
+        shape = [1] * len(interior)
+        shape[ax] = n
+        di = di.reshape(shape)
+        d = di if d is None else np.minimum(d, di)
+    return np.broadcast_to(d, tuple(interior)).copy()

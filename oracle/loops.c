@@ -1,0 +1,139 @@
+/*
+ * Plain FP64 stencil loops: the oracle for the FFT stencil solver.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or call
+ * this file; only the test suite, the smoke check and the benchmark's CPU-baseline
+ * leg use it.  It shares no code, header or table with the HIP library.
+ *
+ * What it computes is the plain definition of the result, not the FFT algorithm:
+ *
+ *  - periodic:  T sweeps of the nested-loop periodic update (the periodic looping
+ *    algorithm of the paper's looping-code figure, extended to d dimensions as in
+ *    the appendix on d-D grids): every cell i gets
+ *        b[i] = sum over offsets o in [-r, r]^d, row-major order, of c[o] * a[(i + o) mod n]
+ *    accumulated in double from +0.0, multiply then add (build with
+ *    -ffp-contract=off so no fused multiply-add changes the rounding);
+ *
+ *  - aperiodic: the same on an array whose extents are n_i + 2r; the outer r-wide
+ *    frame holds fixed (Dirichlet) boundary values and is copied unchanged each step;
+ *    interior cells use the same sum without the modulo (the aperiodic looping
+ *    algorithm of the same figure, with r boundary cells on each side).
+ *
+ * Coefficients are a (2r+1)^d row-major array; c[o] multiplies the neighbour at
+ * offset +o (the periodic loop's S[i, (i + j) % N] convention).  Sweeps are double
+ * buffered; OpenMP splits the outermost spatial index, which does not change any
+ * result because each cell is computed by one thread in a fixed order.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static int64_t wrap(int64_t i, int64_t n) {
+    int64_t m = i % n;
+    return m < 0 ? m + n : m;
+}
+
+/* Expand (ndim, dims, r) to three axes; missing leading axes have extent 1 and radius 0. */
+static void expand3(int ndim, const int64_t* dims, int r, int64_t n[3], int rr[3]) {
+    for (int k = 0; k < 3; ++k) { n[k] = 1; rr[k] = 0; }
+    for (int k = 0; k < ndim; ++k) { n[3 - ndim + k] = dims[k]; rr[3 - ndim + k] = r; }
+}
+
+int oracle_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* a: prod(dims) doubles, overwritten with the state after T periodic sweeps. */
+int oracle_periodic(double* a, int ndim, const int64_t* dims, const double* coeffs,
+                    int r, int64_t T, int nthreads) {
+    if (ndim < 1 || ndim > 3 || r < 0 || T < 0 || !a || !dims || !coeffs) return -1;
+    int64_t n[3]; int rr[3];
+    expand3(ndim, dims, r, n, rr);
+    for (int k = 0; k < 3; ++k) if (n[k] < 1) return -1;
+    const int64_t N = n[0] * n[1] * n[2];
+    const int w0 = 2 * rr[0] + 1, w1 = 2 * rr[1] + 1, w2 = 2 * rr[2] + 1;
+    double* b = (double*)malloc(sizeof(double) * (size_t)N);
+    if (!b) return -3;
+    double* src = a;
+    double* dst = b;
+    if (nthreads <= 0) nthreads = oracle_threads();
+    for (int64_t t = 0; t < T; ++t) {
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+        for (int64_t i0 = 0; i0 < n[0]; ++i0) {
+            for (int64_t i1 = 0; i1 < n[1]; ++i1) {
+                for (int64_t i2 = 0; i2 < n[2]; ++i2) {
+                    double acc = 0.0;
+                    for (int o0 = -rr[0]; o0 <= rr[0]; ++o0) {
+                        const int64_t j0 = wrap(i0 + o0, n[0]);
+                        for (int o1 = -rr[1]; o1 <= rr[1]; ++o1) {
+                            const int64_t j1 = wrap(i1 + o1, n[1]);
+                            for (int o2 = -rr[2]; o2 <= rr[2]; ++o2) {
+                                const int64_t j2 = wrap(i2 + o2, n[2]);
+                                const double c = coeffs[((o0 + rr[0]) * w1 + (o1 + rr[1])) * w2 + (o2 + rr[2])];
+                                const double prod = c * src[(j0 * n[1] + j1) * n[2] + j2];
+                                acc = acc + prod;
+                            }
+                        }
+                    }
+                    dst[(i0 * n[1] + i1) * n[2] + i2] = acc;
+                }
+            }
+        }
+        double* tmp = src; src = dst; dst = tmp;
+    }
+    (void)w0;
+    if (src != a) memcpy(a, src, sizeof(double) * (size_t)N);
+    free(b);
+    return 0;
+}
+
+/* a: prod(dims[k] + 2r) doubles (interior plus an r-wide frame on every side);
+ * the frame is left unchanged and the interior evolves T steps. */
+int oracle_aperiodic(double* a, int ndim, const int64_t* dims, const double* coeffs,
+                     int r, int64_t T, int nthreads) {
+    if (ndim < 1 || ndim > 3 || r < 0 || T < 0 || !a || !dims || !coeffs) return -1;
+    int64_t n[3]; int rr[3];
+    expand3(ndim, dims, r, n, rr);
+    for (int k = 0; k < 3; ++k) if (n[k] < 1) return -1;
+    int64_t s[3]; /* storage extents */
+    for (int k = 0; k < 3; ++k) s[k] = n[k] + 2 * rr[k];
+    const int64_t S = s[0] * s[1] * s[2];
+    const int w1 = 2 * rr[1] + 1, w2 = 2 * rr[2] + 1;
+    double* b = (double*)malloc(sizeof(double) * (size_t)S);
+    if (!b) return -3;
+    memcpy(b, a, sizeof(double) * (size_t)S); /* frame values in both buffers */
+    double* src = a;
+    double* dst = b;
+    if (nthreads <= 0) nthreads = oracle_threads();
+    for (int64_t t = 0; t < T; ++t) {
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+        for (int64_t i0 = rr[0]; i0 < rr[0] + n[0]; ++i0) {
+            for (int64_t i1 = rr[1]; i1 < rr[1] + n[1]; ++i1) {
+                for (int64_t i2 = rr[2]; i2 < rr[2] + n[2]; ++i2) {
+                    double acc = 0.0;
+                    for (int o0 = -rr[0]; o0 <= rr[0]; ++o0) {
+                        for (int o1 = -rr[1]; o1 <= rr[1]; ++o1) {
+                            for (int o2 = -rr[2]; o2 <= rr[2]; ++o2) {
+                                const double c = coeffs[((o0 + rr[0]) * w1 + (o1 + rr[1])) * w2 + (o2 + rr[2])];
+                                const double prod = c * src[((i0 + o0) * s[1] + (i1 + o1)) * s[2] + (i2 + o2)];
+                                acc = acc + prod;
+                            }
+                        }
+                    }
+                    dst[(i0 * s[1] + i1) * s[2] + i2] = acc;
+                }
+            }
+        }
+        double* tmp = src; src = dst; dst = tmp;
+    }
+    if (src != a) memcpy(a, src, sizeof(double) * (size_t)S);
+    free(b);
+    return 0;
+}
