@@ -1,0 +1,196 @@
+/*
+ * stencil_fft.h -- C ABI of the MI355X (gfx950) FFT stencil solver.
+ *
+ * The library evolves a grid T timesteps under a linear, constant-coefficient
+ * stencil in time independent of T up to a log T factor, by the method of
+ * Ahmad et al., "Fast Stencil Computations using Fast Fourier Transforms"
+ * (SPAA 2021):
+ *
+ *   periodic  (Sec. 3, algorithm StencilFFT-P, Eq. "final_data"):
+ *             a_T = F^-1 Lambda^T F a_0, with Lambda = F s the DFT of the first
+ *             column s of the circulant stencil matrix (appendix, eigenvalue-FFT
+ *             relation), Lambda^T by binary repeated squaring (Step 2), the
+ *             product (Step 3) and the inverse transform (Step 4);
+ *   aperiodic (Sec. 4, StencilFFT-A with RecursiveBoundary): the periodic solve
+ *             on the interior plus a divide-and-conquer over time for the cells
+ *             within radius*T of a fixed boundary frame.
+ *
+ * Every function is extern "C"; no C++ exception crosses the ABI.  All functions
+ * return SFFT_OK (0) or a negative error code; stencil_fft_last_error() then
+ * returns a message for the calling thread.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  grid    DEVICE pointer (e.g. torch.Tensor.data_ptr()) to a dense row-major
+ *          array of float (SFFT_F32) or double (SFFT_F64); dims[0] is the slowest
+ *          axis.  Overwritten in place with the result.  The caller owns it and
+ *          must keep it alive and untouched until the work enqueued on `stream`
+ *          has completed.
+ *  dims    HOST pointer to ndim extents (ndim in 1..3, every extent >= 1).
+ *  coeffs  HOST pointer to (2*radius+1)^ndim doubles, row-major over the offsets
+ *          o_0..o_{ndim-1} in [-radius, radius]; coeffs[o] multiplies the
+ *          neighbour a[(i + o) mod dims] when cell i is updated (the periodic
+ *          looping algorithm's S[i, (i+j) % N] convention, Sec. 2).  Copied
+ *          before the call returns.  Always FP64: the symbol and its power are
+ *          evaluated in FP64 whatever the grid's dtype.
+ *  T       number of timesteps, >= 0; T == 0 leaves the grid unchanged.
+ *  stream  hipStream_t to enqueue on (NULL = the null stream).  Calls return
+ *          once the work is enqueued; synchronise the stream to read results.
+ *
+ * Errors: SFFT_EINVAL (null pointer, ndim outside 1..3, an extent < 1,
+ * radius < 0, T < 0, a non-finite coefficient, an unknown dtype);
+ * SFFT_EUNSUPPORTED (a shape the FFT planner cannot handle, e.g. a periodic
+ * extent with a prime factor above 7); SFFT_ENOMEM (device workspace);
+ * SFFT_EHIP (a HIP runtime error; the grid is then unspecified).  When
+ * validation fails the grid is untouched.
+ *
+ * The library owns its device workspace, FFT plans and twiddle/phase tables,
+ * kept in an implicit per-device context and released at process exit.
+ * Workspace is per (device, stream): calls on one stream are ordered by the
+ * stream; calls on different streams of one device may run concurrently.
+ */
+#ifndef STENCIL_FFT_H
+#define STENCIL_FFT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { SFFT_F32 = 0, SFFT_F64 = 1 } sfft_dtype;
+
+enum {
+    SFFT_OK = 0,
+    SFFT_EINVAL = -1,
+    SFFT_EUNSUPPORTED = -2,
+    SFFT_ENOMEM = -3,
+    SFFT_EHIP = -4,
+    SFFT_EBUSY = -5,
+    SFFT_ENOTFOUND = -6
+};
+
+/*
+ * Periodic stencil solve (Sec. 3, StencilFFT-P; d-D form in the appendix on
+ * d-D grids).  grid holds prod(dims) cells; on return (once the stream has run)
+ * it holds a_T = S^T a_0 with periodic wrap on every axis.  Extents smaller than
+ * 2*radius+1 are legal; offsets then alias modulo the extent exactly as the
+ * periodic loop's modulo does.  Every extent must be 7-smooth (2^a 3^b 5^c 7^d).
+ * Accuracy: relative L2 error against the exact result about 1e-6 (F32) and
+ * 1e-14 (F64) for stable stencils; the symbol power is always FP64.
+ */
+int stencil_fft_periodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims,
+                         const double* coeffs, int radius, int64_t T, void* stream);
+
+/*
+ * Aperiodic stencil solve with a fixed (Dirichlet) boundary (Sec. 4,
+ * StencilFFT-A and RecursiveBoundary).  grid has extents dims[i] + 2*radius: the
+ * outer radius-wide frame holds the boundary values, is only read and is left
+ * unchanged; the inner prod(dims) cells are evolved T steps, each step reading
+ * frame cells where the stencil reaches them (the aperiodic looping algorithm of
+ * Sec. 2 with radius boundary cells on each side).  Interior extents need not
+ * be 7-smooth (FFT sub-problems are zero-padded where the method allows it).
+ */
+int stencil_fft_aperiodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims,
+                          const double* coeffs, int radius, int64_t T, void* stream);
+
+/* Message describing the last failing call on this thread ("" if none).  The
+ * pointer stays valid until the thread's next call into the library. */
+const char* stencil_fft_last_error(void);
+
+/*
+ * Symbol and its power (Sec. 3 Steps 1(i) and 2) on their own, for inspection
+ * and testing.  out: DEVICE pointer to prod(dims) interleaved (re, im) double
+ * pairs in natural frequency order (row-major over k_0..k_{ndim-1}); entry k
+ * receives lambda(k)^T with lambda(k) = sum_o coeffs[o] exp(+2 pi i sum_a o_a k_a / dims[a])
+ * (= (F s)[k], s the first column of the stencil matrix).  Same validation as
+ * stencil_fft_periodic.
+ */
+int stencil_fft_symbol_power(double* out, int ndim, const int64_t* dims, const double* coeffs,
+                             int radius, int64_t T, void* stream);
+
+/* One problem of a batch or a serving request.  Unused dims entries are ignored. */
+typedef struct {
+    void* grid;            /* DEVICE pointer, as for the single-problem calls        */
+    sfft_dtype dtype;
+    int ndim;
+    int64_t dims[3];
+    const double* coeffs;  /* HOST pointer, (2*radius+1)^ndim doubles, copied       */
+    int radius;
+    int64_t T;
+    int aperiodic;         /* 0: periodic (dims = grid extents); 1: aperiodic       */
+} sfft_problem;
+
+/*
+ * Solve n independent problems of uneven shapes, dtypes and T, enqueued on one
+ * stream.  Periodic problems are packed into persistent batched launches: one
+ * launch per pass index runs the tiles of every problem's pass of that index.
+ * Aperiodic problems are solved one after another on the same stream.
+ * Validation covers every problem before anything is enqueued: on error nothing
+ * runs and the message names the offending problem index.
+ */
+int stencil_fft_batch(const sfft_problem* probs, int n, void* stream);
+
+/*
+ * Serving loop (continuous batching).  A server owns a worker thread, a set of
+ * HIP streams and an HBM budget for workspace.  submit() never blocks: it
+ * copies the request (coefficients included) and returns a ticket, or
+ * SFFT_EINVAL / SFFT_EUNSUPPORTED for an invalid request, or SFFT_ENOMEM if the
+ * request's own workspace exceeds the whole budget.  The worker admits queued
+ * requests in arrival order while a slot is free and their workspace fits the
+ * remaining budget, packs the admitted ones into batched launches on a free
+ * stream, and releases slot and budget when that stream's work completes, so
+ * requests that arrive while others run join the next launch.  The grid of a
+ * request must stay alive until poll() reports it done.
+ *  create:  device = HIP device ordinal; hbm_budget_bytes = workspace budget
+ *           (0 = 32 GiB); max_slots = requests in flight at most (0 = 64).
+ *  poll:    *done = 1 once the result is in the grid, else 0; SFFT_ENOTFOUND
+ *           for an unknown ticket; a failed request reports its error code.
+ *  wait:    blocks until the ticket is done.
+ *  stats:   JSON text (admitted, completed, launches, peak budget use) into buf.
+ *  destroy: drains outstanding work, then frees everything.
+ */
+typedef struct sfft_server sfft_server;
+int sfft_server_create(sfft_server** out, int device, uint64_t hbm_budget_bytes, int max_slots);
+int sfft_server_submit(sfft_server* s, const sfft_problem* p, uint64_t* ticket);
+int sfft_server_poll(sfft_server* s, uint64_t ticket, int* done);
+int sfft_server_wait(sfft_server* s, uint64_t ticket);
+int sfft_server_stats(sfft_server* s, char* buf, int64_t cap);
+void sfft_server_destroy(sfft_server* s);
+
+/*
+ * Tunables (process-wide).  Names:
+ *   "aperiodic_cutoff"  RecursiveBoundary recurses while T > cutoff; the base
+ *                       case loops T' <= cutoff steps (default chosen per shape
+ *                       when 0).
+ *   "col_max"           longest sub-transform a strided pass performs (power of
+ *                       two, 16..1024; default 0 = per-dtype choice).
+ * Returns SFFT_EINVAL for an unknown name or an out-of-range value.
+ */
+int stencil_fft_set_option(const char* name, int64_t value);
+
+/*
+ * Per-kernel timing with HIP events recorded on the launch stream around every
+ * kernel the library enqueues.  enable != 0 clears and starts collection; 0
+ * stops it.  read() writes JSON {"kernels": {name: {"launches": n, "ms": total,
+ * "bytes": algorithmic bytes}}} into buf (cap bytes) after synchronising the
+ * streams that were used; returns the length or a negative error.
+ */
+int stencil_fft_profile(int enable);
+int stencil_fft_profile_read(char* buf, int64_t cap);
+
+/*
+ * The pass schedule the planner picks for a periodic problem, as JSON (passes,
+ * kinds, sub-lengths, radices, tile shapes, algorithmic bytes per pass).
+ * Host-only: needs no GPU.
+ */
+int stencil_fft_plan_describe(int ndim, const int64_t* dims, sfft_dtype dtype, char* buf, int64_t cap);
+
+/* Library version string. */
+const char* stencil_fft_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STENCIL_FFT_H */

@@ -1,0 +1,254 @@
+"""ctypes binding of libstencilfft.so: argument marshalling only."""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libstencilfft.so")
+
+if not os.path.exists(library_path):
+    raise ImportError(
+        f"{library_path} is missing: build it with `python -m paper_2105_06676_amd.build` "
+        "(the solver has no CPU fallback)")
+
+# torch is imported first so that its HIP runtime is the one in the process: the
+# library then binds to that same runtime (by soname) instead of loading a second
+# copy, which would not share devices, streams or allocations with torch.
+import torch  # noqa: E402,F401
+
+lib = ctypes.CDLL(library_path)
+
+SFFT_F32, SFFT_F64 = 0, 1
+ERRORS = {0: "OK", -1: "EINVAL", -2: "EUNSUPPORTED", -3: "ENOMEM", -4: "EHIP", -5: "EBUSY", -6: "ENOTFOUND"}
+
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dp = ctypes.POINTER(ctypes.c_double)
+_vp = ctypes.c_void_p
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("grid", _vp), ("dtype", ctypes.c_int), ("ndim", ctypes.c_int),
+                ("dims", ctypes.c_int64 * 3), ("coeffs", _dp), ("radius", ctypes.c_int),
+                ("T", ctypes.c_int64), ("aperiodic", ctypes.c_int)]
+
+
+def _sig(name, res, args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_periodic = _sig("stencil_fft_periodic", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
+_aperiodic = _sig("stencil_fft_aperiodic", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
+_last_error = _sig("stencil_fft_last_error", ctypes.c_char_p, [])
+_symbol_power = _sig("stencil_fft_symbol_power", ctypes.c_int, [_vp, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
+_batch = _sig("stencil_fft_batch", ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, _vp])
+_set_option = _sig("stencil_fft_set_option", ctypes.c_int, [ctypes.c_char_p, ctypes.c_int64])
+_profile = _sig("stencil_fft_profile", ctypes.c_int, [ctypes.c_int])
+_profile_read = _sig("stencil_fft_profile_read", ctypes.c_int, [ctypes.c_char_p, ctypes.c_int64])
+_plan_describe = _sig("stencil_fft_plan_describe", ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_char_p, ctypes.c_int64])
+_version = _sig("stencil_fft_version", ctypes.c_char_p, [])
+_srv_create = _sig("sfft_server_create", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_uint64, ctypes.c_int])
+_srv_submit = _sig("sfft_server_submit", ctypes.c_int, [_vp, ctypes.POINTER(_Problem), ctypes.POINTER(ctypes.c_uint64)])
+_srv_poll = _sig("sfft_server_poll", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)])
+_srv_wait = _sig("sfft_server_wait", ctypes.c_int, [_vp, ctypes.c_uint64])
+_srv_stats = _sig("sfft_server_stats", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int64])
+_srv_destroy = _sig("sfft_server_destroy", None, [_vp])
+
+
+class SfftError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise SfftError(rc, _last_error().decode())
+    return rc
+
+
+def version() -> str:
+    return _version().decode()
+
+
+def _coeffs(coeffs, ndim: int):
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    if c.ndim != ndim or len(set(c.shape)) != 1 or c.shape[0] % 2 != 1:
+        raise ValueError(f"coefficients must have shape (2r+1,)*{ndim}, got {c.shape}")
+    return c, (c.shape[0] - 1) // 2
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float32:
+        return SFFT_F32
+    if t.dtype == torch.float64:
+        return SFFT_F64
+    raise TypeError(f"grid dtype must be float32 or float64, got {t.dtype}")
+
+
+def _stream(t, stream):
+    import torch
+    if stream is not None:
+        return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _check_grid(t):
+    if not t.is_cuda:
+        raise ValueError("grid must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("grid must be contiguous")
+
+
+def periodic(grid, coeffs, T: int, stream=None):
+    """Evolve ``grid`` (CUDA tensor, float32/float64, 1-3 dims) T steps in place
+    under the periodic stencil ``coeffs`` ((2r+1,)*ndim array, c[o] multiplies a[i+o])."""
+    import torch
+    _check_grid(grid)
+    c, r = _coeffs(coeffs, grid.dim())
+    dims = (ctypes.c_int64 * grid.dim())(*grid.shape)
+    with torch.cuda.device(grid.device):
+        _check(_periodic(grid.data_ptr(), _dtype_code(grid), grid.dim(), dims,
+                         c.ctypes.data_as(_dp), r, int(T), _stream(grid, stream)))
+    return grid
+
+
+def aperiodic(grid, coeffs, T: int, stream=None):
+    """Evolve the interior of ``grid`` T steps in place; the outer r-wide frame holds
+    fixed boundary values (grid extents are interior extents + 2r)."""
+    import torch
+    _check_grid(grid)
+    c, r = _coeffs(coeffs, grid.dim())
+    interior = [s - 2 * r for s in grid.shape]
+    dims = (ctypes.c_int64 * grid.dim())(*interior)
+    with torch.cuda.device(grid.device):
+        _check(_aperiodic(grid.data_ptr(), _dtype_code(grid), grid.dim(), dims,
+                          c.ctypes.data_as(_dp), r, int(T), _stream(grid, stream)))
+    return grid
+
+
+def symbol_power(out, dims: Sequence[int], coeffs, T: int, stream=None):
+    """Write lambda(k)^T (complex128, natural order, shape ``dims``) into ``out``."""
+    import torch
+    _check_grid(out)
+    if out.dtype != torch.complex128 or tuple(out.shape) != tuple(dims):
+        raise ValueError("out must be a complex128 tensor of shape dims")
+    c, r = _coeffs(coeffs, len(dims))
+    d = (ctypes.c_int64 * len(dims))(*dims)
+    with torch.cuda.device(out.device):
+        _check(_symbol_power(out.data_ptr(), len(dims), d, c.ctypes.data_as(_dp), r, int(T), _stream(out, stream)))
+    return out
+
+
+def _problem(grid, coeffs, T, aperiodic_: bool, keep):
+    _check_grid(grid)
+    c, r = _coeffs(coeffs, grid.dim())
+    keep.append(c)
+    p = _Problem()
+    p.grid = grid.data_ptr()
+    p.dtype = _dtype_code(grid)
+    p.ndim = grid.dim()
+    ext = [s - 2 * r for s in grid.shape] if aperiodic_ else list(grid.shape)
+    for a in range(3):
+        p.dims[a] = ext[a] if a < grid.dim() else 1
+    p.coeffs = c.ctypes.data_as(_dp)
+    p.radius = r
+    p.T = int(T)
+    p.aperiodic = 1 if aperiodic_ else 0
+    return p
+
+
+def batch(problems, stream=None):
+    """Solve a list of ``(grid, coeffs, T)`` or ``(grid, coeffs, T, aperiodic)`` in
+    batched launches on one stream."""
+    import torch
+    keep = []
+    arr = (_Problem * len(problems))()
+    dev = None
+    for i, pr in enumerate(problems):
+        grid, coeffs, T = pr[0], pr[1], pr[2]
+        ap = bool(pr[3]) if len(pr) > 3 else False
+        arr[i] = _problem(grid, coeffs, T, ap, keep)
+        dev = grid.device
+    if not problems:
+        return
+    with torch.cuda.device(dev):
+        _check(_batch(arr, len(problems), _stream(problems[0][0], stream)))
+
+
+class Server:
+    """Continuous-batching stencil server (one per device)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0, max_slots: int = 0):
+        self._h = _vp()
+        _check(_srv_create(ctypes.byref(self._h), int(device), int(hbm_budget_bytes), int(max_slots)))
+        self._keep = {}
+
+    def submit(self, grid, coeffs, T: int, aperiodic_: bool = False) -> int:
+        keep = []
+        p = _problem(grid, coeffs, T, aperiodic_, keep)
+        t = ctypes.c_uint64()
+        _check(_srv_submit(self._h, ctypes.byref(p), ctypes.byref(t)))
+        self._keep[t.value] = (grid, keep)
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        done = ctypes.c_int()
+        _check(_srv_poll(self._h, ticket, ctypes.byref(done)))
+        if done.value:
+            self._keep.pop(ticket, None)
+        return bool(done.value)
+
+    def wait(self, ticket: int):
+        _check(_srv_wait(self._h, ticket))
+        self._keep.pop(ticket, None)
+
+    def stats(self) -> dict:
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(_srv_stats(self._h, buf, len(buf)))
+        return json.loads(buf.value.decode())
+
+    def close(self):
+        if self._h:
+            _srv_destroy(self._h)
+            self._h = _vp()
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def set_option(name: str, value: int):
+    _check(_set_option(name.encode(), int(value)))
+
+
+def profile_start():
+    _check(_profile(1))
+
+
+def profile_stop():
+    _check(_profile(0))
+
+
+def profile_read() -> dict:
+    buf = ctypes.create_string_buffer(1 << 20)
+    _check(_profile_read(buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def plan_describe(dims: Sequence[int], dtype: str = "f32") -> dict:
+    d = (ctypes.c_int64 * len(dims))(*dims)
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(_plan_describe(len(dims), d, SFFT_F64 if dtype == "f64" else SFFT_F32, buf, len(buf)))
+    return json.loads(buf.value.decode())

@@ -1,0 +1,185 @@
+// C ABI entry points (declared in include/stencil_fft.h).
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "../../include/stencil_fft.h"
+#include "sfft_kernels.h"
+#include "sfft_runtime.h"
+
+namespace sfft {
+const char* last_error_cstr();
+void profile_enable(bool on);
+std::string profile_json();
+void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
+                     hipStream_t st);
+}  // namespace sfft
+
+using namespace sfft;
+
+namespace {
+
+template <typename F>
+int guarded(F&& f) {
+    clear_last_error();
+    try {
+        f();
+        return SFFT_OK;
+    } catch (const Error& e) {
+        set_last_error(e.what());
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_last_error("host allocation failed");
+        return SFFT_ENOMEM;
+    } catch (const std::exception& e) {
+        set_last_error(e.what());
+        return SFFT_EINVAL;
+    }
+}
+
+void validate(const void* ptr, int dtype, int ndim, const int64_t* dims, const double* coeffs, int radius,
+              int64_t T) {
+    if (!ptr) throw Error(SFFT_EINVAL, "grid pointer is null");
+    if (dtype != SFFT_F32 && dtype != SFFT_F64) throw Error(SFFT_EINVAL, "unknown dtype");
+    if (ndim < 1 || ndim > 3) throw Error(SFFT_EINVAL, "ndim must be 1, 2 or 3");
+    if (!dims) throw Error(SFFT_EINVAL, "dims pointer is null");
+    for (int a = 0; a < ndim; ++a)
+        if (dims[a] < 1) throw Error(SFFT_EINVAL, "extents must be >= 1");
+    if (radius < 0) throw Error(SFFT_EINVAL, "radius must be >= 0");
+    if (radius > kMaxR) throw Error(SFFT_EUNSUPPORTED, "radius above 2 is not supported");
+    if (T < 0) throw Error(SFFT_EINVAL, "T must be >= 0");
+    if (!coeffs) throw Error(SFFT_EINVAL, "coeffs pointer is null");
+    int nc = 1;
+    for (int a = 0; a < ndim; ++a) nc *= 2 * radius + 1;
+    for (int i = 0; i < nc; ++i)
+        if (!std::isfinite(coeffs[i])) throw Error(SFFT_EINVAL, "coefficient " + std::to_string(i) + " is not finite");
+}
+
+}  // namespace
+
+namespace sfft {
+
+// Periodic solve of B dense grids of `dims` stored back to back.
+void solve_periodic_dense(void* grid, bool f64, int d, const int64_t* dims, int64_t B, const double* coeffs, int r,
+                          int64_t T, hipStream_t st) {
+    DevCtx& ctx = device_ctx();
+    auto plan = ctx.plan(d, dims, B, f64);
+    void* ws = ctx.workspace(st, (size_t)plan->s.spec_elems * (f64 ? 16 : 8));
+    SymParams sp = plan->s.sym;
+    double N = 1.0;
+    for (int a = 0; a < d; ++a) N *= (double)dims[a];
+    fill_symbol(sp, coeffs, r, d, T, 1.0 / N);
+    RealView v = dense_view(grid, d, dims);
+    KeepRule keep;
+    std::memset(&keep, 0, sizeof(keep));
+    run_plan(*plan, ws, v, v, keep, sp, st);
+}
+
+}  // namespace sfft
+
+extern "C" {
+
+const char* stencil_fft_version(void) { return "stencil_fft 0.1 (gfx950)"; }
+
+const char* stencil_fft_last_error(void) { return last_error_cstr(); }
+
+int stencil_fft_periodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims, const double* coeffs,
+                         int radius, int64_t T, void* stream) {
+    return guarded([&] {
+        validate(grid, dtype, ndim, dims, coeffs, radius, T);
+        for (int a = 0; a < ndim; ++a)
+            if (!is_7smooth(dims[a]))
+                throw Error(SFFT_EUNSUPPORTED, "extent " + std::to_string(dims[a]) + " has a prime factor above 7");
+        if (T == 0) return;
+        solve_periodic_dense(grid, dtype == SFFT_F64, ndim, dims, 1, coeffs, radius, T, (hipStream_t)stream);
+    });
+}
+
+int stencil_fft_aperiodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims, const double* coeffs,
+                          int radius, int64_t T, void* stream) {
+    return guarded([&] {
+        validate(grid, dtype, ndim, dims, coeffs, radius, T);
+        if (T == 0) return;
+        solve_aperiodic(grid, dtype == SFFT_F64, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
+    });
+}
+
+int stencil_fft_symbol_power(double* out, int ndim, const int64_t* dims, const double* coeffs, int radius,
+                             int64_t T, void* stream) {
+    return guarded([&] {
+        validate(out, SFFT_F64, ndim, dims, coeffs, radius, T);
+        DevCtx& ctx = device_ctx();
+        SymParams sp;
+        std::memset(&sp, 0, sizeof(sp));
+        sp.d = ndim;
+        int64_t total = 1;
+        for (int a = 0; a < 3; ++a) {
+            sp.n[a] = a < ndim ? dims[a] : 1;
+            sp.nlev[a] = 1;
+            sp.sub[a][0] = sp.n[a];
+            sp.sdim[a] = sp.n[a];
+        }
+        for (int a = 0; a < ndim; ++a) {
+            total *= dims[a];
+            sp.eph[a] = ctx.phase_table(dims[a]);
+        }
+        fill_symbol(sp, coeffs, radius, ndim, T, 1.0);
+        check_hip(launch_symbol_power((double2*)out, sp, total, (hipStream_t)stream), "symbol power launch");
+    });
+}
+
+int stencil_fft_set_option(const char* name, int64_t value) {
+    return guarded([&] {
+        if (!name) throw Error(SFFT_EINVAL, "option name is null");
+        const std::string n(name);
+        if (n == "col_max") {
+            if (value != 0 && (value < 16 || value > 1024 || (value & (value - 1))))
+                throw Error(SFFT_EINVAL, "col_max must be 0 or a power of two in 16..1024");
+            tunables().col_max = (int)value;
+        } else if (n == "aperiodic_cutoff") {
+            if (value < 0 || value > (1 << 20)) throw Error(SFFT_EINVAL, "aperiodic_cutoff out of range");
+            tunables().aperiodic_cutoff = (int)value;
+        } else {
+            throw Error(SFFT_EINVAL, "unknown option '" + n + "'");
+        }
+    });
+}
+
+int stencil_fft_profile(int enable) {
+    return guarded([&] { profile_enable(enable != 0); });
+}
+
+int stencil_fft_profile_read(char* buf, int64_t cap) {
+    std::string s;
+    const int rc = guarded([&] {
+        if (!buf || cap < 1) throw Error(SFFT_EINVAL, "buffer is null or empty");
+        s = profile_json();
+    });
+    if (rc) return rc;
+    const int64_t n = std::min<int64_t>((int64_t)s.size(), cap - 1);
+    std::memcpy(buf, s.data(), (size_t)n);
+    buf[n] = 0;
+    return (int)n;
+}
+
+int stencil_fft_plan_describe(int ndim, const int64_t* dims, sfft_dtype dtype, char* buf, int64_t cap) {
+    std::string s;
+    const int rc = guarded([&] {
+        if (!buf || cap < 1 || !dims) throw Error(SFFT_EINVAL, "null argument");
+        if (dtype != SFFT_F32 && dtype != SFFT_F64) throw Error(SFFT_EINVAL, "unknown dtype");
+        Schedule sch;
+        std::string why;
+        const int r = build_schedule(ndim, dims, 1, dtype == SFFT_F64, &sch, &why);
+        if (r) throw Error(r == -1 ? SFFT_EINVAL : SFFT_EUNSUPPORTED, why);
+        s = describe_schedule(sch);
+    });
+    if (rc) return rc;
+    if ((int64_t)s.size() >= cap) {
+        set_last_error("buffer too small");
+        return SFFT_EINVAL;
+    }
+    std::memcpy(buf, s.data(), s.size() + 1);
+    return (int)s.size();
+}
+
+}  // extern "C"

@@ -1,0 +1,416 @@
+// Device building blocks: complex arithmetic, small DFT butterflies, LDS
+// Stockham stages, twiddle lookups and the FP64 symbol / symbol-power code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "sfft_types.h"
+
+namespace sfft {
+
+template <typename R>
+struct cx {
+    R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// a * conj(b)
+template <typename R>
+__device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {
+    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+}
+template <typename R>
+__device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.x, -a.y}; }
+template <typename R>
+__device__ __forceinline__ cx<R> scale(cx<R> a, R s) { return {a.x * s, a.y * s}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename R, bool INV>
+__device__ __forceinline__ cx<R> rot90(cx<R> a) {
+    return INV ? cx<R>{-a.y, a.x} : cx<R>{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers: X[k] = sum_t v[t] exp(-+2 pi i t k / RAD)
+// (minus sign forward, plus sign inverse).
+// ---------------------------------------------------------------------------
+
+template <int RAD>
+struct RootTab;  // cos(2 pi m / RAD), sin(2 pi m / RAD), m = 0..RAD-1
+template <>
+struct RootTab<3> {
+    static constexpr double c[3] = {1.0, -0.5, -0.5};
+    static constexpr double s[3] = {0.0, 0.8660254037844386, -0.8660254037844386};
+};
+template <>
+struct RootTab<5> {
+    static constexpr double c[5] = {1.0, 0.30901699437494745, -0.8090169943749475,
+                                    -0.8090169943749475, 0.30901699437494745};
+    static constexpr double s[5] = {0.0, 0.9510565162951535, 0.5877852522924731,
+                                    -0.5877852522924731, -0.9510565162951535};
+};
+template <>
+struct RootTab<7> {
+    static constexpr double c[7] = {1.0, 0.6234898018587335, -0.2225209339563144, -0.9009688679024191,
+                                    -0.9009688679024191, -0.2225209339563144, 0.6234898018587335};
+    static constexpr double s[7] = {0.0, 0.7818314824680298, 0.9749279121818236, 0.4338837391175581,
+                                    -0.4338837391175581, -0.9749279121818236, -0.7818314824680298};
+};
+
+template <typename R, bool INV>
+__device__ __forceinline__ void dft2(cx<R>* v) {
+    cx<R> a = v[0], b = v[1];
+    v[0] = a + b;
+    v[1] = a - b;
+}
+
+template <typename R, bool INV>
+__device__ __forceinline__ void dft4(cx<R>& v0, cx<R>& v1, cx<R>& v2, cx<R>& v3) {
+    cx<R> t0 = v0 + v2, t1 = v0 - v2, t2 = v1 + v3, t3 = rot90<R, INV>(v1 - v3);
+    v0 = t0 + t2;
+    v2 = t0 - t2;
+    v1 = t1 + t3;
+    v3 = t1 - t3;
+}
+
+template <typename R, bool INV>
+__device__ __forceinline__ void dft8(cx<R>* v) {
+    constexpr R h = R(0.7071067811865476);
+    cx<R> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    cx<R> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4<R, INV>(e0, e1, e2, e3);
+    dft4<R, INV>(o0, o1, o2, o3);
+    // twiddles w^k, w = exp(-+ 2 pi i / 8)
+    cx<R> w1 = INV ? cx<R>{h * (o1.x - o1.y), h * (o1.x + o1.y)} : cx<R>{h * (o1.x + o1.y), h * (o1.y - o1.x)};
+    cx<R> w2 = rot90<R, INV>(o2);
+    cx<R> w3 = INV ? cx<R>{-h * (o3.x + o3.y), h * (o3.x - o3.y)} : cx<R>{h * (o3.y - o3.x), -h * (o3.x + o3.y)};
+    v[0] = e0 + o0;
+    v[4] = e0 - o0;
+    v[1] = e1 + w1;
+    v[5] = e1 - w1;
+    v[2] = e2 + w2;
+    v[6] = e2 - w2;
+    v[3] = e3 + w3;
+    v[7] = e3 - w3;
+}
+
+// Odd radix by the symmetric pairing of t and RAD - t.
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void dft_odd(cx<R>* v) {
+    constexpr int H = (RAD - 1) / 2;
+    cx<R> a[H], b[H];
+#pragma unroll
+    for (int j = 1; j <= H; ++j) {
+        a[j - 1] = v[j] + v[RAD - j];
+        b[j - 1] = v[j] - v[RAD - j];
+    }
+    cx<R> out[RAD];
+    cx<R> s0 = v[0];
+#pragma unroll
+    for (int j = 0; j < H; ++j) s0 = s0 + a[j];
+    out[0] = s0;
+#pragma unroll
+    for (int k = 1; k <= H; ++k) {
+        cx<R> re = v[0];
+        cx<R> im = {R(0), R(0)};
+#pragma unroll
+        for (int j = 1; j <= H; ++j) {
+            const R cc = R(RootTab<RAD>::c[(j * k) % RAD]);
+            const R ss = R(RootTab<RAD>::s[(j * k) % RAD]);
+            re = re + scale(a[j - 1], cc);
+            im = im + scale(b[j - 1], ss);
+        }
+        // forward: X_k = re - i im, X_{RAD-k} = re + i im
+        cx<R> r90 = rot90<R, INV>(im);
+        out[k] = re + r90;
+        out[RAD - k] = re - r90;
+    }
+#pragma unroll
+    for (int k = 0; k < RAD; ++k) v[k] = out[k];
+}
+
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void dft(cx<R>* v) {
+    if constexpr (RAD == 2) dft2<R, INV>(v);
+    else if constexpr (RAD == 4) dft4<R, INV>(v[0], v[1], v[2], v[3]);
+    else if constexpr (RAD == 8) dft8<R, INV>(v);
+    else dft_odd<R, RAD, INV>(v);
+}
+
+// ---------------------------------------------------------------------------
+// One Stockham radix-RAD stage over every transform of an LDS tile.
+// Transform `tr` element `e` lives at lds[tr * ts + e * es].  With Ns the product
+// of the radices already applied, butterfly j reads elements j + t * L/RAD,
+// multiplies by exp(-+2 pi i t (j mod Ns) / (Ns RAD)), runs a RAD-point DFT and
+// writes element (j / Ns) * Ns * RAD + (j mod Ns) + t * Ns (self-sorting order).
+// TFAST: consecutive threads take consecutive transforms (column tiles);
+// otherwise consecutive butterflies of one transform (row tiles).
+// ---------------------------------------------------------------------------
+template <typename R, int RAD, bool INV, bool TFAST>
+__device__ __forceinline__ void stage(cx<R>* lds, int L, int ntrans, int ts, int es, int Ns,
+                                      const cx<R>* __restrict__ tab, int tmul) {
+    const int nb = L / RAD;
+    const int total = nb * ntrans;
+    constexpr int MAXIT = (kTileElems + RAD * kThreads - 1) / (RAD * kThreads);
+    cx<R> v[MAXIT][RAD];
+    const int step = (L / (Ns * RAD)) * tmul;
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int e = threadIdx.x + it * kThreads;
+        if (e < total) {
+            int tr, j;
+            if (TFAST) { tr = e % ntrans; j = e / ntrans; }
+            else { j = e % nb; tr = e / nb; }
+            const cx<R>* base = lds + tr * ts;
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) v[it][t] = base[(j + t * nb) * es];
+            const int k = j % Ns;
+            if (Ns > 1 && k != 0) {
+                const cx<R> w = tab[k * step];
+                cx<R> wt = w;
+#pragma unroll
+                for (int t = 1; t < RAD; ++t) {
+                    v[it][t] = INV ? cmulc(v[it][t], wt) : cmul(v[it][t], wt);
+                    if (t + 1 < RAD) wt = cmul(wt, w);
+                }
+            }
+            dft<R, RAD, INV>(v[it]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it) {
+        const int e = threadIdx.x + it * kThreads;
+        if (e < total) {
+            int tr, j;
+            if (TFAST) { tr = e % ntrans; j = e / ntrans; }
+            else { j = e % nb; tr = e / nb; }
+            cx<R>* base = lds + tr * ts;
+            const int k = j % Ns;
+            const int dst = (j / Ns) * Ns * RAD + k;
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) base[(dst + t * Ns) * es] = v[it][t];
+        }
+    }
+    __syncthreads();
+}
+
+// Full transform of length L (radix list in the pass descriptor) on every
+// transform of the tile.
+template <typename R, bool INV, bool TFAST>
+__device__ void tile_fft(cx<R>* lds, const PassDesc& pd, int ntrans, int ts, int es) {
+    const cx<R>* tab = (const cx<R>*)pd.st_tab;
+    int Ns = 1;
+    for (int s = 0; s < pd.nst; ++s) {
+        switch (pd.radix[s]) {
+            case 2: stage<R, 2, INV, TFAST>(lds, pd.L, ntrans, ts, es, Ns, tab, pd.st_mul); break;
+            case 3: stage<R, 3, INV, TFAST>(lds, pd.L, ntrans, ts, es, Ns, tab, pd.st_mul); break;
+            case 4: stage<R, 4, INV, TFAST>(lds, pd.L, ntrans, ts, es, Ns, tab, pd.st_mul); break;
+            case 5: stage<R, 5, INV, TFAST>(lds, pd.L, ntrans, ts, es, Ns, tab, pd.st_mul); break;
+            case 7: stage<R, 7, INV, TFAST>(lds, pd.L, ntrans, ts, es, Ns, tab, pd.st_mul); break;
+            default: stage<R, 8, INV, TFAST>(lds, pd.L, ntrans, ts, es, Ns, tab, pd.st_mul); break;
+        }
+        Ns *= pd.radix[s];
+    }
+}
+
+// Twiddle between sub-transforms, exp(-2 pi i e / tw_n) from a two-level table.
+template <typename R>
+__device__ __forceinline__ cx<R> step_twiddle(const PassDesc& pd, int64_t e) {
+    const cx<R>* lo = (const cx<R>*)pd.tw_lo;
+    const cx<R>* hi = (const cx<R>*)pd.tw_hi;
+    const int64_t q = e / pd.tw_B;
+    const int64_t l = e - q * pd.tw_B;
+    cx<R> w = lo[l];
+    if (q) w = cmul(w, hi[q]);
+    return w;
+}
+
+// ---------------------------------------------------------------------------
+// Region bookkeeping for the last pass: may local cell (b, i) be stored?
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool keep_cell(const KeepRule& kr, int d, int64_t b, const int64_t* i) {
+    if (!kr.enabled) return true;
+    int64_t dist = INT64_MAX;
+    int64_t fd[6];
+    for (int a = 0; a < d; ++a) {
+        const int64_t g = kr.gorg[a] + b * kr.gbstep[a] + i[a];
+        fd[2 * a] = g + 1;
+        fd[2 * a + 1] = kr.gdim[a] - g;
+        dist = min(dist, min(fd[2 * a], fd[2 * a + 1]));
+    }
+    if (!(dist > kr.lo && dist <= kr.hi)) return false;
+    if (kr.face_axis < 0) return true;
+    int first = 0;
+    for (int f = 0; f < 2 * d; ++f) {
+        if (fd[f] == dist) { first = f; break; }
+    }
+    if (first / 2 != kr.face_axis) return false;
+    const int side = kr.face_side == 2 ? (int)b : kr.face_side;
+    if (side < 0) return true;
+    return (first & 1) == side;
+}
+
+// ---------------------------------------------------------------------------
+// Symbol and symbol power, always FP64.
+//
+// lambda(k) = sum_o c[o] prod_a exp(2 pi i o_a k_a / n_a) (= (F s)[k], the DFT of
+// the circulant matrix's first column; appendix, eigenvalue-FFT relation).  It is
+// carried as mu = 1 - lambda so that modes with lambda close to 1, which
+// dominate long runs, keep their relative accuracy: with E_a(m) = exp(2 pi i m /
+// n_a) - 1 tabulated,
+//   lambda = sum(c) + sum_{o0} D[o0] + sum_{o0} E_0(o0 k0) G[o0]
+//   G[o0] = sum_{o'} c[o0, o'] prod_{a>0} (1 + E_a(o_a k_a))
+//   D[o0] = sum_{o'} c[o0, o'] (prod_{a>0} (1 + E_a(o_a k_a)) - 1)
+// so mu = (1 - sum c) - sum D - sum_{o0} E_0 G with no cancellation.
+// ---------------------------------------------------------------------------
+struct dcx {
+    double x, y;
+};
+__device__ __forceinline__ dcx dmul(dcx a, dcx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ dcx dadd(dcx a, dcx b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ dcx dsub(dcx a, dcx b) { return {a.x - b.x, a.y - b.y}; }
+
+__device__ __forceinline__ int64_t pos_to_freq(const SymParams& sp, int a, int64_t p) {
+    const int nl = sp.nlev[a];
+    if (nl <= 1) return p;
+    if (nl == 2) {
+        const int64_t s0 = sp.sub[a][0], s1 = sp.sub[a][1];
+        const int64_t d0 = p / s1, d1 = p - d0 * s1;
+        return d0 + s0 * d1;
+    }
+    const int64_t s0 = sp.sub[a][0], s1 = sp.sub[a][1], s2 = sp.sub[a][2];
+    const int64_t d0 = p / (s1 * s2);
+    const int64_t rem = p - d0 * s1 * s2;
+    const int64_t d1 = rem / s2, d2 = rem - d1 * s2;
+    return d0 + s0 * (d1 + s1 * d2);
+}
+
+// E_a((o * k) mod n_a) for offset o in [-r, r]
+__device__ __forceinline__ dcx eph(const SymParams& sp, int a, int o, int64_t k) {
+    const int64_t n = sp.n[a];
+    int64_t m = ((int64_t)(o < 0 ? -o : o) * k) % n;
+    const dcx* t = (const dcx*)sp.eph[a];
+    dcx e = t[m];
+    if (o < 0) e.y = -e.y;  // E(-m) = conj(E(m))
+    return e;
+}
+
+// Per-column part: G[o0] and K = (1 - sum c) - sum D for the axis-1..d-1 frequencies f.
+__device__ inline void symbol_column(const SymParams& sp, const int64_t* f, dcx* G, dcx* K) {
+    const int r = sp.r, w = 2 * r + 1;
+    dcx dsum = {0.0, 0.0};
+    for (int o0 = -r; o0 <= r; ++o0) {
+        dcx g = {0.0, 0.0}, dd = {0.0, 0.0};
+        if (sp.d == 1) {
+            g.x = sp.c[o0 + r];
+        } else if (sp.d == 2) {
+            for (int o1 = -r; o1 <= r; ++o1) {
+                const double c = sp.c[(o0 + r) * w + (o1 + r)];
+                const dcx p = eph(sp, 1, o1, f[1]);
+                g = dadd(g, dcx{c * (1.0 + p.x), c * p.y});
+                dd = dadd(dd, dcx{c * p.x, c * p.y});
+            }
+        } else {
+            for (int o1 = -r; o1 <= r; ++o1) {
+                const dcx e1 = eph(sp, 1, o1, f[1]);
+                for (int o2 = -r; o2 <= r; ++o2) {
+                    const double c = sp.c[((o0 + r) * w + (o1 + r)) * w + (o2 + r)];
+                    const dcx e2 = eph(sp, 2, o2, f[2]);
+                    const dcx p = dadd(dadd(e1, e2), dmul(e1, e2));
+                    g = dadd(g, dcx{c * (1.0 + p.x), c * p.y});
+                    dd = dadd(dd, dcx{c * p.x, c * p.y});
+                }
+            }
+        }
+        G[o0 + r] = g;
+        dsum = dadd(dsum, dd);
+    }
+    *K = dcx{sp.one_minus_sum - dsum.x, -dsum.y};
+}
+
+__device__ __forceinline__ dcx symbol_mu(const SymParams& sp, const dcx* G, dcx K, int64_t f0) {
+    dcx mu = K;
+    for (int o0 = -sp.r; o0 <= sp.r; ++o0) {
+        if (o0 == 0) continue;
+        mu = dsub(mu, dmul(eph(sp, 0, o0, f0), G[o0 + sp.r]));
+    }
+    return mu;
+}
+
+// (1 - mu)^T by binary repeated squaring (Sec. 3 Step 2), in deviation form:
+// a factor 1 - m squares to 1 - (2m - m^2) and (1 - v)(1 - m) = 1 - (v + m - vm);
+// a factor leaves the deviation form once |m| > 1/2, where plain products are
+// just as accurate.
+__device__ inline dcx power_complex(dcx mu, int64_t T) {
+    bool sq_dev = true, v_dev = true;
+    dcx sq = mu, v = {0.0, 0.0};
+    if (mu.x * mu.x + mu.y * mu.y > 0.25) { sq = dcx{1.0 - mu.x, -mu.y}; sq_dev = false; }
+    int64_t R = T;
+    while (R > 0) {
+        if (R & 1) {
+            if (v_dev && sq_dev) {
+                v = dsub(dadd(v, sq), dmul(v, sq));
+            } else {
+                const dcx a = v_dev ? dcx{1.0 - v.x, -v.y} : v;
+                const dcx b = sq_dev ? dcx{1.0 - sq.x, -sq.y} : sq;
+                v = dmul(a, b);
+                v_dev = false;
+            }
+        }
+        R >>= 1;
+        if (R) {
+            if (sq_dev) {
+                sq = dsub(dcx{2.0 * sq.x, 2.0 * sq.y}, dmul(sq, sq));
+                if (sq.x * sq.x + sq.y * sq.y > 0.25) { sq = dcx{1.0 - sq.x, -sq.y}; sq_dev = false; }
+            } else {
+                sq = dmul(sq, sq);
+            }
+        }
+    }
+    return v_dev ? dcx{1.0 - v.x, -v.y} : v;
+}
+
+__device__ inline double power_real(double mu, int64_t T) {
+    bool sq_dev = true, v_dev = true;
+    double sq = mu, v = 0.0;
+    if (fabs(mu) > 0.5) { sq = 1.0 - mu; sq_dev = false; }
+    int64_t R = T;
+    while (R > 0) {
+        if (R & 1) {
+            if (v_dev && sq_dev) {
+                v = (v + sq) - v * sq;
+            } else {
+                v = (v_dev ? 1.0 - v : v) * (sq_dev ? 1.0 - sq : sq);
+                v_dev = false;
+            }
+        }
+        R >>= 1;
+        if (R) {
+            if (sq_dev) {
+                sq = 2.0 * sq - sq * sq;
+                if (fabs(sq) > 0.5) { sq = 1.0 - sq; sq_dev = false; }
+            } else {
+                sq = sq * sq;
+            }
+        }
+    }
+    return v_dev ? 1.0 - v : v;
+}
+
+// lambda^T * scale for a mode, from its per-column part and axis-0 frequency.
+__device__ __forceinline__ dcx symbol_power_at(const SymParams& sp, const dcx* G, dcx K, int64_t f0) {
+    const dcx mu = symbol_mu(sp, G, K, f0);
+    if (sp.real_sym) return dcx{power_real(mu.x, sp.T) * sp.scale, 0.0};
+    const dcx v = power_complex(mu, sp.T);
+    return dcx{v.x * sp.scale, v.y * sp.scale};
+}
+
+}  // namespace sfft

@@ -1,0 +1,391 @@
+// HIP kernels of the FFT stencil solver (gfx950).
+//
+//  k_row  : transforms along the contiguous axis, whole rows staged in LDS.
+//           Forward real-to-complex (first pass), inverse complex-to-real (last
+//           pass), complex-to-complex (middle of a split 1-D problem), or the
+//           whole periodic solve of a 1-D row in one launch.
+//  k_col  : transforms along a strided axis on a tile of W adjacent columns,
+//           forward / inverse with the twiddle of a split axis, or the fused
+//           middle pass: forward transform, multiply by lambda^T / N (FP64 symbol
+//           and repeated squaring), inverse transform.
+//  table kernels: FP64 twiddles exp(-2 pi i m / N) and symbol phases
+//           exp(2 pi i m / n) - 1 from sincospi with exact integer reduction.
+//  k_symbol_power: lambda(k)^T in natural order (inspection entry point).
+#include <hip/hip_runtime.h>
+
+#include "sfft_device.h"
+#include "sfft_kernels.h"
+
+namespace sfft {
+
+__device__ __forceinline__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
+
+// (b, i_0 .. i_{d-2}) of row `row` of a row pass; rows are ordered [B][n_0]..[n_{d-2}].
+__device__ __forceinline__ int64_t row_coords(const PassDesc& pd, int64_t row, int64_t* i) {
+    int64_t rem = row;
+    for (int a = pd.d - 2; a >= 0; --a) {
+        const int64_t q = rem / pd.rdims[a];
+        i[a] = rem - q * pd.rdims[a];
+        rem = q;
+    }
+    return rem;
+}
+
+__device__ __forceinline__ bool prefix_inside(const PassDesc& pd, const int64_t* i) {
+    for (int a = 0; a < pd.d - 1; ++a)
+        if (i[a] >= pd.rv.ext[a]) return false;
+    return true;
+}
+
+__device__ __forceinline__ int64_t prefix_offset(const PassDesc& pd, int64_t b, const int64_t* i) {
+    int64_t off = b * pd.rv.boff;
+    for (int a = 0; a < pd.d - 1; ++a) off += i[a] * pd.rv.stride[a];
+    return off;
+}
+
+// ---------------------------------------------------------------------------
+// Row pass
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ void r2c_untangle(cx<R>* lds, int nrows, int LS, int L, const cx<R>* tab) {
+    // X[k] = (Z[k] + conj Z[L-k]) / 2 - i w^k (Z[k] - conj Z[L-k]) / 2, w = exp(-2 pi i / 2L)
+    // tab holds exp(-2 pi i m / 2L).
+    const int per = L / 2 + 1;
+    for (int e = threadIdx.x; e < nrows * per; e += kThreads) {
+        const int rr = e / per, k = e - rr * per;
+        cx<R>* row = lds + rr * LS;
+        const int kk = (L - k) % L;
+        const cx<R> zk = row[k], zm = row[kk];
+        if (k == 0) {
+            row[0] = cx<R>{zk.x + zk.y, R(0)};
+            row[L] = cx<R>{zk.x - zk.y, R(0)};
+            continue;
+        }
+        {
+            const cx<R> e = scale(zk + conj(zm), R(0.5));
+            const cx<R> o = scale(zk - conj(zm), R(0.5));
+            const cx<R> w = tab[k];
+            const cx<R> t = cmul(w, o);
+            row[k] = cx<R>{e.x + t.y, e.y - t.x};  // e - i t
+        }
+        if (kk != k) {
+            const cx<R> e = scale(zm + conj(zk), R(0.5));
+            const cx<R> o = scale(zm - conj(zk), R(0.5));
+            const cx<R> w = tab[kk];
+            const cx<R> t = cmul(w, o);
+            row[kk] = cx<R>{e.x + t.y, e.y - t.x};
+        }
+    }
+}
+
+template <typename R>
+__device__ void c2r_tangle(cx<R>* lds, int nrows, int LS, int L, const cx<R>* tab) {
+    // Z'[k] = (X[k] + conj X[L-k]) + i conj(w^k) (X[k] - conj X[L-k]), w as above.
+    const int per = L / 2 + 1;
+    for (int e = threadIdx.x; e < nrows * per; e += kThreads) {
+        const int rr = e / per, k = e - rr * per;
+        cx<R>* row = lds + rr * LS;
+        const int kk = L - k;
+        const cx<R> xk = row[k], xm = row[kk];
+        {
+            const cx<R> e = xk + conj(xm);
+            const cx<R> o = cmulc(xk - conj(xm), tab[k]);
+            row[k] = cx<R>{e.x - o.y, e.y + o.x};  // e + i o
+        }
+        if (k != 0 && kk != k) {
+            const cx<R> e = xm + conj(xk);
+            const cx<R> o = cmulc(xm - conj(xk), tab[kk]);
+            row[kk] = cx<R>{e.x - o.y, e.y + o.x};
+        }
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_row(PassDesc pd, SymParams sp) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
+    const int L = pd.L;
+    const int LS = pd.lds_stride;
+    const int64_t row0 = (int64_t)blockIdx.x * pd.W;
+    const int nrows = (int)imin64(pd.W, pd.outer - row0);
+    const cx<R>* buf = (const cx<R>*)pd.buf;
+    const R* rin = (const R*)pd.rv.ptr;
+    const cx<R>* htab = (const cx<R>*)pd.st_tab;  // exp(-2 pi i m / (L * st_mul))
+
+    // ---- load
+    if (pd.in_real) {
+        const int64_t sl = pd.rv.stride[pd.d - 1];
+        const int64_t el = pd.rv.ext[pd.d - 1];
+        for (int e = threadIdx.x; e < nrows * L; e += kThreads) {
+            const int rr = e / L, m = e - rr * L;
+            int64_t idx[3];
+            const int64_t b = row_coords(pd, row0 + rr, idx);
+            cx<R> v = {R(0), R(0)};
+            if (prefix_inside(pd, idx)) {
+                const int64_t base = prefix_offset(pd, b, idx);
+                if (pd.rowtrans == RT_HALF) {
+                    if (2 * m < el) v.x = rin[base + (int64_t)(2 * m) * sl];
+                    if (2 * m + 1 < el) v.y = rin[base + (int64_t)(2 * m + 1) * sl];
+                } else {
+                    if (m < el) v.x = rin[base + (int64_t)m * sl];
+                }
+            }
+            lds[rr * LS + m] = v;
+        }
+    } else {
+        const int cnt = pd.rowtrans == RT_HALF ? L + 1 : L;
+        for (int e = threadIdx.x; e < nrows * cnt; e += kThreads) {
+            const int rr = e / cnt, m = e - rr * cnt;
+            const cx<R>* src = buf + (row0 + rr) * pd.ostride;
+            cx<R> v;
+            if (pd.rowtrans == RT_ODD && m >= pd.hcount) v = conj(src[L - m]);
+            else v = src[m];
+            lds[rr * LS + m] = v;
+        }
+    }
+    __syncthreads();
+
+    const bool half = pd.rowtrans == RT_HALF;
+    if (pd.mode == MODE_INV && half) {
+        c2r_tangle<R>(lds, nrows, LS, L, htab);
+        __syncthreads();
+    }
+    if (pd.mode != MODE_INV) {
+        tile_fft<R, false, false>(lds, pd, nrows, LS, 1);
+        if (half) {
+            r2c_untangle<R>(lds, nrows, LS, L, htab);
+            __syncthreads();
+        }
+    }
+    if (pd.mode == MODE_MID) {
+        // 1-D problems: axis 0 is the only axis, G[o] = c[o], K = 1 - sum c.
+        dcx G[2 * kMaxR + 1];
+        for (int o = 0; o < 2 * sp.r + 1; ++o) G[o] = dcx{sp.c[o], 0.0};
+        const dcx K = {sp.one_minus_sum, 0.0};
+        const int cnt = half ? L + 1 : L;
+        for (int e = threadIdx.x; e < nrows * cnt; e += kThreads) {
+            const int rr = e / cnt, k = e - rr * cnt;
+            const int64_t p0 = ((row0 + rr) % pd.q_mod) * L + k;
+            const int64_t f0 = pos_to_freq(sp, 0, p0);
+            const dcx v = symbol_power_at(sp, G, K, f0);
+            cx<R>& x = lds[rr * LS + k];
+            x = cmul(x, cx<R>{R(v.x), R(v.y)});
+        }
+        __syncthreads();
+        if (half) {
+            c2r_tangle<R>(lds, nrows, LS, L, htab);
+            __syncthreads();
+        }
+    }
+    if (pd.mode != MODE_FWD) tile_fft<R, true, false>(lds, pd, nrows, LS, 1);
+
+    // ---- store
+    if (pd.out_real) {
+        R* rout = (R*)pd.rv.ptr;
+        const int64_t sl = pd.rv.stride[pd.d - 1];
+        const int64_t el = pd.rv.ext[pd.d - 1];
+        const int per = half ? 2 * L : L;
+        for (int e = threadIdx.x; e < nrows * per; e += kThreads) {
+            const int rr = e / per, m = e - rr * per;
+            if (m >= el) continue;
+            int64_t idx[3];
+            const int64_t b = row_coords(pd, row0 + rr, idx);
+            if (!prefix_inside(pd, idx)) continue;
+            idx[pd.d - 1] = m;
+            if (!keep_cell(pd.keep, pd.d, b, idx)) continue;
+            const cx<R> z = lds[rr * LS + (half ? (m >> 1) : m)];
+            rout[prefix_offset(pd, b, idx) + (int64_t)m * sl] = half ? ((m & 1) ? z.y : z.x) : z.x;
+        }
+    } else {
+        cx<R>* dst = (cx<R>*)pd.buf;
+        const int cnt = pd.rowtrans == RT_C2C ? L : pd.hcount;
+        for (int e = threadIdx.x; e < nrows * cnt; e += kThreads) {
+            const int rr = e / cnt, m = e - rr * cnt;
+            dst[(row0 + rr) * pd.ostride + m] = lds[rr * LS + m];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_col(PassDesc pd, SymParams sp) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
+    const int L = pd.L, W = pd.W;
+    const int64_t tile = blockIdx.x;
+    const int64_t o = tile / pd.tiles_inner;
+    const int64_t c0 = (tile - o * pd.tiles_inner) * W;
+    const int wc = (int)imin64(W, pd.inner - c0);
+    const cx<R>* buf = (const cx<R>*)pd.buf;
+    // valid columns: inside inner and, when the last axis is padded, inside hcount
+    auto col_valid = [&](int64_t c) -> bool {
+        if (c - c0 >= wc) return false;
+        if (pd.cpitch > 0 && (c % pd.cpitch) >= pd.hcount) return false;
+        return true;
+    };
+
+    // ---- load (inverse passes multiply by the conjugate split twiddle first)
+    for (int e = threadIdx.x; e < L * W; e += kThreads) {
+        const int k = e / W, cc = e - k * W;
+        const int64_t c = c0 + cc;
+        cx<R> v = {R(0), R(0)};
+        if (col_valid(c)) {
+            if (pd.in_real) {
+                const int64_t m = (int64_t)k * pd.kstride + c;
+                if (m < pd.rv.ext[0]) v.x = ((const R*)pd.rv.ptr)[o * pd.rv.boff + m * pd.rv.stride[0]];
+            } else {
+                v = buf[o * pd.ostride + (int64_t)k * pd.kstride + c];
+            }
+            if (pd.mode == MODE_INV && pd.tw) v = cmulc(v, step_twiddle<R>(pd, (int64_t)k * (c / pd.tw_div)));
+        }
+        lds[k * W + cc] = v;
+    }
+    __syncthreads();
+
+    if (pd.mode != MODE_INV) tile_fft<R, false, true>(lds, pd, W, 1, W);
+
+    if (pd.mode == MODE_MID) {
+        __shared__ dcx Gs[64][2 * kMaxR + 1];
+        __shared__ dcx Ks[64];
+        __shared__ int Vs[64];
+        // per-column part of the symbol (axes 1..d-1 fixed along a column)
+        for (int cc = threadIdx.x; cc < W; cc += kThreads) {
+            const int64_t c = c0 + cc;
+            int valid = col_valid(c) ? 1 : 0;
+            int64_t f[3] = {0, 0, 0};
+            if (valid) {
+                int64_t rem = c;
+                for (int a = sp.d - 1; a >= 1; --a) {
+                    const int64_t q = rem / sp.sdim[a];
+                    const int64_t p = rem - q * sp.sdim[a];
+                    rem = q;
+                    f[a] = pos_to_freq(sp, a, p);
+                }
+            }
+            dcx K;
+            symbol_column(sp, f, Gs[cc], &K);
+            Ks[cc] = K;
+            Vs[cc] = valid;
+        }
+        __syncthreads();
+        const int64_t qpre = (o % pd.q_mod) * L;
+        for (int e = threadIdx.x; e < L * W; e += kThreads) {
+            const int k = e / W, cc = e - k * W;
+            if (!Vs[cc]) continue;
+            const int64_t f0 = pos_to_freq(sp, 0, qpre + k);
+            const dcx v = symbol_power_at(sp, Gs[cc], Ks[cc], f0);
+            cx<R>& x = lds[k * W + cc];
+            x = cmul(x, cx<R>{R(v.x), R(v.y)});
+        }
+        __syncthreads();
+    }
+
+    if (pd.mode != MODE_FWD) tile_fft<R, true, true>(lds, pd, W, 1, W);
+
+    // ---- store (forward passes multiply by the split twiddle last)
+    for (int e = threadIdx.x; e < L * W; e += kThreads) {
+        const int k = e / W, cc = e - k * W;
+        const int64_t c = c0 + cc;
+        if (!col_valid(c)) continue;
+        cx<R> v = lds[k * W + cc];
+        if (pd.mode == MODE_FWD && pd.tw) v = cmul(v, step_twiddle<R>(pd, (int64_t)k * (c / pd.tw_div)));
+        if (pd.out_real) {
+            const int64_t m = (int64_t)k * pd.kstride + c;
+            if (m >= pd.rv.ext[0]) continue;
+            int64_t idx[3] = {m, 0, 0};
+            if (!keep_cell(pd.keep, 1, o, idx)) continue;
+            ((R*)pd.rv.ptr)[o * pd.rv.boff + m * pd.rv.stride[0]] = v.x;
+        } else {
+            ((cx<R>*)pd.buf)[o * pd.ostride + (int64_t)k * pd.kstride + c] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Tables
+// ---------------------------------------------------------------------------
+__global__ void k_twiddle_table(double2* t64, float2* t32, int64_t N, int64_t count, int64_t mult) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    int64_t e = (i * mult) % N;
+    if (2 * e > N) e -= N;
+    double s, c;
+    sincospi(2.0 * (double)e / (double)N, &s, &c);
+    t64[i] = make_double2(c, -s);
+    t32[i] = make_float2((float)c, (float)-s);
+}
+
+__global__ void k_phase_table(double2* E, int64_t n) {
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    int64_t mm = m;
+    if (2 * mm > n) mm -= n;
+    const double h = sinpi((double)mm / (double)n);
+    const double s = sinpi(2.0 * (double)mm / (double)n);
+    E[m] = make_double2(-2.0 * h * h, s);
+}
+
+// lambda(k)^T in natural order over the full spectrum (row-major k).
+__global__ void k_symbol_power(double2* out, SymParams sp, int64_t total) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int64_t f[3] = {0, 0, 0};
+    int64_t rem = idx;
+    for (int a = sp.d - 1; a >= 0; --a) {
+        const int64_t q = rem / sp.n[a];
+        f[a] = rem - q * sp.n[a];
+        rem = q;
+    }
+    dcx G[2 * kMaxR + 1];
+    dcx K;
+    symbol_column(sp, f, G, &K);
+    const dcx v = symbol_power_at(sp, G, K, f[0]);
+    out[idx] = make_double2(v.x, v.y);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch helpers
+// ---------------------------------------------------------------------------
+template <typename R>
+static hipError_t launch_pass_t(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st) {
+    if (pd.kind == PASS_ROW)
+        hipLaunchKernelGGL(k_row<R>, dim3((unsigned)pd.ntiles), dim3(kThreads), lds, st, pd, sp);
+    else
+        hipLaunchKernelGGL(k_col<R>, dim3((unsigned)pd.ntiles), dim3(kThreads), lds, st, pd, sp);
+    return hipGetLastError();
+}
+
+hipError_t launch_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t lds, hipStream_t st) {
+    return f64 ? launch_pass_t<double>(pd, sp, lds, st) : launch_pass_t<float>(pd, sp, lds, st);
+}
+
+hipError_t set_kernel_lds_limits(size_t bytes) {
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void*)k_row<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_row<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_col<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_col<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    return hipSuccess;
+}
+
+hipError_t launch_twiddle_table(double2* t64, float2* t32, int64_t N, int64_t count, int64_t mult, hipStream_t st) {
+    const int bs = 256;
+    hipLaunchKernelGGL(k_twiddle_table, dim3((unsigned)((count + bs - 1) / bs)), dim3(bs), 0, st, t64, t32, N, count, mult);
+    return hipGetLastError();
+}
+
+hipError_t launch_phase_table(double2* E, int64_t n, hipStream_t st) {
+    const int bs = 256;
+    hipLaunchKernelGGL(k_phase_table, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, E, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_symbol_power(double2* out, const SymParams& sp, int64_t total, hipStream_t st) {
+    const int bs = 256;
+    hipLaunchKernelGGL(k_symbol_power, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, out, sp, total);
+    return hipGetLastError();
+}
+
+}  // namespace sfft

@@ -1,0 +1,364 @@
+// Pass schedule of a periodic solve (Sec. 3, StencilFFT-P; d-D form in the
+// appendix on d-D grids).
+//
+// d >= 2:  row R2C along the last (contiguous) axis, column passes along axes
+//          d-2 .. 1, column passes along axis 0 whose last sub-transform is the
+//          fused middle pass (forward, lambda^T / N, inverse), then the inverse
+//          passes in reverse order and a row C2R.
+// d == 1:  one fused row pass when the row fits in LDS; otherwise the axis is
+//          split n = s_0 [* s_1] * s_row: column sub-passes over the leading
+//          factors, a complex row middle pass over s_row, and back.
+// A strided axis longer than col_max is split into up to three factors; the
+// forward output stays in digit-reversed order (no transposes).
+#include "sfft_plan.h"
+
+#include <algorithm>
+#include <cstring>
+#include <sstream>
+
+namespace sfft {
+
+Tunables& tunables() {
+    static Tunables t;
+    return t;
+}
+
+bool is_7smooth(int64_t n) {
+    if (n < 1) return false;
+    for (int64_t p : {2, 3, 5, 7})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+static bool radix_list(int64_t L, int* out, int* nst) {
+    std::vector<int> r;
+    int64_t n = L;
+    while (n % 8 == 0) { r.push_back(8); n /= 8; }
+    if (n % 4 == 0) { r.push_back(4); n /= 4; }
+    if (n % 2 == 0) { r.push_back(2); n /= 2; }
+    for (int p : {7, 5, 3})
+        while (n % p == 0) { r.push_back(p); n /= p; }
+    if (n != 1 || (int)r.size() > kMaxStages) return false;
+    *nst = (int)r.size();
+    for (size_t i = 0; i < r.size(); ++i) out[i] = r[i];
+    return true;
+}
+
+// Split n (7-smooth) into 1..3 factors, each <= cap, as balanced as possible.
+static bool split_axis(int64_t n, int64_t cap, std::vector<int64_t>* out) {
+    out->clear();
+    if (n <= cap) { out->push_back(n); return true; }
+    int64_t best = 0, b0 = 0;
+    for (int64_t s0 = 2; s0 <= cap && s0 < n; ++s0) {
+        if (n % s0) continue;
+        const int64_t s1 = n / s0;
+        if (s1 > cap) continue;
+        const int64_t score = std::min(s0, s1);
+        if (score > best) { best = score; b0 = s0; }
+    }
+    if (b0) { out->push_back(b0); out->push_back(n / b0); return true; }
+    int64_t bs = 0, c0 = 0, c1 = 0;
+    for (int64_t s0 = 2; s0 <= cap && s0 < n; ++s0) {
+        if (n % s0) continue;
+        const int64_t rest = n / s0;
+        for (int64_t s1 = 2; s1 <= cap && s1 < rest; ++s1) {
+            if (rest % s1) continue;
+            const int64_t s2 = rest / s1;
+            if (s2 > cap) continue;
+            const int64_t score = std::min(s0, std::min(s1, s2));
+            if (score > bs) { bs = score; c0 = s0; c1 = s1; }
+        }
+    }
+    if (!c0) return false;
+    out->push_back(c0);
+    out->push_back(c1);
+    out->push_back(n / (c0 * c1));
+    return true;
+}
+
+static int64_t pow2_floor(int64_t x) {
+    int64_t p = 1;
+    while (p * 2 <= x) p *= 2;
+    return p;
+}
+
+struct Ctx {
+    bool f64;
+    int64_t esz;      // bytes per real
+    int64_t csz;      // bytes per complex
+    int64_t budget;   // complex elements per tile
+};
+
+static PassPlan make_row(const Ctx& c, int64_t rows, int L, int rowtrans, int mode, int nreal, int hcount,
+                         int64_t ostride) {
+    PassPlan p;
+    PassDesc& pd = p.pd;
+    std::memset(&pd, 0, sizeof(pd));
+    pd.kind = PASS_ROW;
+    pd.mode = mode;
+    pd.rowtrans = rowtrans;
+    pd.L = L;
+    pd.nreal = nreal;
+    pd.hcount = hcount;
+    pd.outer = rows;
+    pd.inner = 1;
+    pd.ostride = ostride;
+    pd.kstride = 1;
+    pd.q_mod = 1;
+    pd.lds_stride = rowtrans == RT_HALF ? L + 1 : L;
+    int64_t W = std::max<int64_t>(1, c.budget / pd.lds_stride);
+    W = std::min<int64_t>(W, rows);
+    pd.W = (int)W;
+    pd.ntiles = (rows + W - 1) / W;
+    pd.tiles_inner = 1;
+    radix_list(L, pd.radix, &pd.nst);
+    if (rowtrans == RT_HALF) {
+        p.stage_tab = {2 * (int64_t)L, 2 * (int64_t)L, 1};
+        pd.st_mul = 2;
+    } else {
+        p.stage_tab = {L, L, 1};
+        pd.st_mul = 1;
+    }
+    p.lds_bytes = (size_t)W * pd.lds_stride * c.csz;
+    return p;
+}
+
+static PassPlan make_col(const Ctx& c, int64_t outer, int L, int64_t inner, int mode, int64_t tw_n, int64_t tw_div,
+                         int64_t Wcap) {
+    PassPlan p;
+    PassDesc& pd = p.pd;
+    std::memset(&pd, 0, sizeof(pd));
+    pd.kind = PASS_COL;
+    pd.mode = mode;
+    pd.L = L;
+    pd.outer = outer;
+    pd.inner = inner;
+    pd.kstride = inner;
+    pd.ostride = (int64_t)L * inner;
+    pd.q_mod = 1;
+    int64_t W = pow2_floor(std::max<int64_t>(1, c.budget / L));
+    if (Wcap > 0) W = std::min(W, Wcap);
+    if (W > inner) W = inner;
+    pd.W = (int)W;
+    pd.tiles_inner = (inner + W - 1) / W;
+    pd.ntiles = outer * pd.tiles_inner;
+    radix_list(L, pd.radix, &pd.nst);
+    p.stage_tab = {L, L, 1};
+    pd.st_mul = 1;
+    if (tw_n > 0) {
+        pd.tw = 1;
+        pd.tw_n = tw_n;
+        pd.tw_div = tw_div;
+        pd.tw_B = (int)std::min<int64_t>(tw_n, 1024);
+        p.has_tw = true;
+        p.tw_lo = {tw_n, pd.tw_B, 1};
+        p.tw_hi = {tw_n, (tw_n + pd.tw_B - 1) / pd.tw_B, pd.tw_B};
+    }
+    p.lds_bytes = (size_t)L * W * c.csz;
+    return p;
+}
+
+static void col_bytes(const Ctx& c, PassPlan& p, int64_t hcount) {
+    const PassDesc& pd = p.pd;
+    int64_t valid = pd.inner;
+    if (pd.cpitch > 0) valid = pd.inner / pd.cpitch * hcount;
+    const int64_t elems = pd.outer * pd.L * valid;
+    p.model_bytes = elems * ((pd.in_real ? c.esz : c.csz) + (pd.out_real ? c.esz : c.csz));
+}
+
+int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* S, std::string* why) {
+    *S = Schedule();
+    S->d = d;
+    S->B = B;
+    S->f64 = f64;
+    if (d < 1 || d > 3 || B < 1) { *why = "ndim must be 1..3"; return -1; }
+    for (int a = 0; a < d; ++a) {
+        S->dims[a] = dims[a];
+        if (dims[a] < 1) { *why = "extents must be >= 1"; return -1; }
+        if (!is_7smooth(dims[a])) {
+            *why = "extent " + std::to_string(dims[a]) + " has a prime factor above 7";
+            return -2;
+        }
+    }
+    Ctx c{f64, f64 ? 8 : 4, f64 ? 16 : 8, f64 ? 4096 : 8192};
+    const int64_t col_max = tunables().col_max ? tunables().col_max : 512;
+    const int64_t row_max = f64 ? 4096 : 8192;   // complex points of a row middle pass
+    const int64_t row_single = 8192;             // complex points of one LDS row (any pass)
+    SymParams& sp = S->sym;
+    std::memset(&sp, 0, sizeof(sp));
+    sp.d = d;
+    for (int a = 0; a < 3; ++a) sp.n[a] = a < d ? dims[a] : 1;
+
+    if (d == 1) {
+        const int64_t n = dims[0];
+        const bool half = (n % 2) == 0;
+        const int64_t L = half ? n / 2 : n;
+        if (L <= row_single) {
+            PassPlan p = make_row(c, B, (int)L, half ? RT_HALF : RT_ODD, MODE_MID, (int)n, (int)(n / 2 + 1), 0);
+            p.pd.in_real = p.pd.out_real = 1;
+            p.model_bytes = B * 2 * n * c.esz;
+            p.name = "row_mid_real";
+            S->passes.push_back(p);
+            sp.nlev[0] = 1;
+            sp.sub[0][0] = n;
+            sp.sdim[0] = n;
+            S->spec_elems = 0;
+        } else {
+            int64_t nr = 0;
+            for (int64_t s = std::min(n, row_max); s >= 2; --s)
+                if (n % s == 0) { nr = s; break; }
+            std::vector<int64_t> lev;
+            if (!nr || !split_axis(n / nr, col_max, &lev) || lev.size() > 2) {
+                *why = "1-D extent " + std::to_string(n) + " cannot be split into supported factors";
+                return -2;
+            }
+            lev.push_back(nr);
+            const int nl = (int)lev.size();
+            sp.nlev[0] = nl;
+            for (int i = 0; i < nl; ++i) sp.sub[0][i] = lev[i];
+            sp.sdim[0] = n;
+            S->spec_elems = B * n;
+            int64_t pre = 1;
+            for (int l = 0; l < nl - 1; ++l) {
+                int64_t post = 1;
+                for (int i = l + 1; i < nl; ++i) post *= lev[i];
+                PassPlan p = make_col(c, B * pre, (int)lev[l], post, MODE_FWD, lev[l] * post, 1, 0);
+                if (l == 0) p.pd.in_real = 1;
+                col_bytes(c, p, 0);
+                p.name = l == 0 ? "col_fwd_real" : "col_fwd";
+                S->passes.push_back(p);
+                pre *= lev[l];
+            }
+            PassPlan m = make_row(c, B * pre, (int)nr, RT_C2C, MODE_MID, 0, 0, nr);
+            m.pd.q_mod = pre;
+            m.model_bytes = B * n * 2 * c.csz;
+            m.name = "row_mid_c2c";
+            S->passes.push_back(m);
+            for (int l = nl - 2; l >= 0; --l) {
+                pre /= lev[l];
+                int64_t post = 1;
+                for (int i = l + 1; i < nl; ++i) post *= lev[i];
+                PassPlan p = make_col(c, B * pre, (int)lev[l], post, MODE_INV, lev[l] * post, 1, 0);
+                if (l == 0) p.pd.out_real = 1;
+                col_bytes(c, p, 0);
+                p.name = l == 0 ? "col_inv_real" : "col_inv";
+                S->passes.push_back(p);
+            }
+        }
+    } else {
+        const int64_t nl = dims[d - 1];
+        const bool half = (nl % 2) == 0;
+        const int64_t L = half ? nl / 2 : nl;
+        if (L > row_single) {
+            *why = "last extent " + std::to_string(nl) + " exceeds one LDS row";
+            return -2;
+        }
+        const int64_t h = nl / 2 + 1;
+        const int64_t P = (h + 15) / 16 * 16;
+        for (int a = 0; a < d - 1; ++a) sp.sdim[a] = dims[a];
+        sp.sdim[d - 1] = P;
+        sp.hcount = h;
+        sp.nlev[d - 1] = 1;
+        sp.sub[d - 1][0] = nl;
+        int64_t rows = B;
+        for (int a = 0; a < d - 1; ++a) rows *= dims[a];
+        S->spec_elems = rows * P;
+
+        std::vector<std::vector<int64_t>> lev(d);
+        for (int a = 0; a < d - 1; ++a) {
+            if (!split_axis(dims[a], col_max, &lev[a])) {
+                *why = "extent " + std::to_string(dims[a]) + " cannot be split into supported factors";
+                return -2;
+            }
+            sp.nlev[a] = (int)lev[a].size();
+            for (size_t i = 0; i < lev[a].size(); ++i) sp.sub[a][i] = lev[a][i];
+        }
+
+        PassPlan r0 = make_row(c, rows, (int)L, half ? RT_HALF : RT_ODD, MODE_FWD, (int)nl, (int)h, P);
+        r0.pd.in_real = 1;
+        r0.model_bytes = rows * (nl * c.esz + h * c.csz);
+        r0.name = "row_fwd_r2c";
+        S->passes.push_back(r0);
+
+        auto outer_of = [&](int a) {
+            int64_t o = B;
+            for (int b = 0; b < a; ++b) o *= sp.sdim[b];
+            return o;
+        };
+        auto inner_of = [&](int a) {
+            int64_t i = 1;
+            for (int b = a + 1; b < d; ++b) i *= sp.sdim[b];
+            return i;
+        };
+        auto level_pass = [&](int a, int l, int mode) {
+            const auto& s = lev[a];
+            const int nlv = (int)s.size();
+            int64_t pre = 1, post = 1;
+            for (int i = 0; i < l; ++i) pre *= s[i];
+            for (int i = l + 1; i < nlv; ++i) post *= s[i];
+            const bool tw = (mode != MODE_MID) && (l < nlv - 1);
+            PassPlan p = make_col(c, outer_of(a) * pre, (int)s[l], post * inner_of(a), mode,
+                                  tw ? s[l] * post : 0, inner_of(a), mode == MODE_MID ? 64 : 0);
+            p.pd.cpitch = P;
+            p.pd.hcount = (int)h;
+            if (mode == MODE_MID) p.pd.q_mod = pre;
+            col_bytes(c, p, h);
+            p.name = mode == MODE_MID ? "col_mid" : (mode == MODE_FWD ? "col_fwd" : "col_inv");
+            return p;
+        };
+        for (int a = d - 2; a >= 1; --a) {
+            if (dims[a] == 1) continue;
+            for (int l = 0; l < (int)lev[a].size(); ++l) S->passes.push_back(level_pass(a, l, MODE_FWD));
+        }
+        const int n0 = (int)lev[0].size();
+        for (int l = 0; l < n0 - 1; ++l) S->passes.push_back(level_pass(0, l, MODE_FWD));
+        S->passes.push_back(level_pass(0, n0 - 1, MODE_MID));
+        for (int l = n0 - 2; l >= 0; --l) S->passes.push_back(level_pass(0, l, MODE_INV));
+        for (int a = 1; a <= d - 2; ++a) {
+            if (dims[a] == 1) continue;
+            for (int l = (int)lev[a].size() - 1; l >= 0; --l) S->passes.push_back(level_pass(a, l, MODE_INV));
+        }
+        PassPlan r1 = make_row(c, rows, (int)L, half ? RT_HALF : RT_ODD, MODE_INV, (int)nl, (int)h, P);
+        r1.pd.out_real = 1;
+        r1.model_bytes = rows * (nl * c.esz + h * c.csz);
+        r1.name = "row_inv_c2r";
+        S->passes.push_back(r1);
+    }
+    for (auto& p : S->passes) {
+        p.pd.d = d;
+        p.pd.B = B;
+        for (int a = 0; a < 3; ++a) p.pd.rdims[a] = a < d ? dims[a] : 1;
+        S->model_bytes += p.model_bytes;
+    }
+    return 0;
+}
+
+std::string describe_schedule(const Schedule& s) {
+    std::ostringstream o;
+    o << "{\"ndim\": " << s.d << ", \"dims\": [";
+    for (int a = 0; a < s.d; ++a) o << (a ? ", " : "") << s.dims[a];
+    o << "], \"batch\": " << s.B << ", \"dtype\": \"" << (s.f64 ? "f64" : "f32") << "\""
+      << ", \"spectrum_elems\": " << s.spec_elems << ", \"model_bytes\": " << s.model_bytes << ", \"passes\": [";
+    for (size_t i = 0; i < s.passes.size(); ++i) {
+        const PassPlan& p = s.passes[i];
+        const PassDesc& pd = p.pd;
+        o << (i ? ", " : "") << "{\"name\": \"" << p.name << "\", \"kind\": \""
+          << (pd.kind == PASS_ROW ? "row" : "col") << "\", \"mode\": \""
+          << (pd.mode == MODE_FWD ? "fwd" : pd.mode == MODE_INV ? "inv" : "mid") << "\", \"L\": " << pd.L
+          << ", \"W\": " << pd.W << ", \"outer\": " << pd.outer << ", \"inner\": " << pd.inner
+          << ", \"tiles\": " << pd.ntiles << ", \"twiddle\": " << pd.tw << ", \"lds_bytes\": " << p.lds_bytes
+          << ", \"model_bytes\": " << p.model_bytes << ", \"radices\": [";
+        for (int k = 0; k < pd.nst; ++k) o << (k ? ", " : "") << pd.radix[k];
+        o << "]}";
+    }
+    o << "], \"levels\": [";
+    for (int a = 0; a < s.d; ++a) {
+        o << (a ? ", " : "") << "[";
+        for (int l = 0; l < s.sym.nlev[a]; ++l) o << (l ? ", " : "") << s.sym.sub[a][l];
+        o << "]";
+    }
+    o << "]}";
+    return o.str();
+}
+
+}  // namespace sfft

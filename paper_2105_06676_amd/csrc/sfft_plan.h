@@ -1,0 +1,55 @@
+// Host-side pass schedule for one periodic problem shape (no GPU needed).
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "sfft_types.h"
+
+namespace sfft {
+
+// A device table the schedule needs: exp(-2 pi i (m * mult) / N) for m < count.
+struct TwiddleReq {
+    int64_t N, count, mult;
+    bool operator<(const TwiddleReq& o) const {
+        if (N != o.N) return N < o.N;
+        if (count != o.count) return count < o.count;
+        return mult < o.mult;
+    }
+};
+
+struct PassPlan {
+    PassDesc pd;              // table pointers, buffer and views unset
+    TwiddleReq stage_tab;     // stage twiddles
+    bool has_tw = false;
+    TwiddleReq tw_lo, tw_hi;  // split twiddles
+    size_t lds_bytes = 0;
+    int64_t model_bytes = 0;  // algorithmic HBM bytes (read + write) of one launch
+    std::string name;         // kernel family for profiling
+};
+
+struct Schedule {
+    int d = 0;
+    int64_t dims[3] = {1, 1, 1};
+    int64_t B = 1;
+    bool f64 = false;
+    std::vector<PassPlan> passes;
+    int64_t spec_elems = 0;   // complex elements of the spectrum workspace
+    SymParams sym{};          // geometry part (n, nlev, sub, sdim, hcount)
+    int64_t model_bytes = 0;  // sum over passes
+};
+
+struct Tunables {
+    int col_max = 0;          // 0: default
+    int aperiodic_cutoff = 0; // 0: per-shape default
+};
+Tunables& tunables();
+
+bool is_7smooth(int64_t n);
+// 0 on success; on failure a message in *why.
+int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* out, std::string* why);
+std::string describe_schedule(const Schedule& s);
+
+}  // namespace sfft

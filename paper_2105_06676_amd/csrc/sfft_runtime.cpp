@@ -1,0 +1,281 @@
+// Per-device runtime: twiddle / phase tables, plan cache, per-stream workspace,
+// error strings and optional per-kernel HIP-event timing.
+#include "sfft_runtime.h"
+
+#include <cmath>
+#include <cstring>
+#include <sstream>
+
+#include "sfft_kernels.h"
+
+namespace sfft {
+
+static thread_local std::string g_last_error;
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+void clear_last_error() { g_last_error.clear(); }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+void check_hip(hipError_t e, const char* what) {
+    if (e != hipSuccess) throw Error(-4, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- context ----
+
+DevCtx& device_ctx() {
+    static std::mutex m;
+    static std::map<int, std::unique_ptr<DevCtx>> ctxs;
+    int dev = 0;
+    check_hip(hipGetDevice(&dev), "hipGetDevice");
+    std::lock_guard<std::mutex> g(m);
+    auto& p = ctxs[dev];
+    if (!p) {
+        p.reset(new DevCtx());
+        p->device = dev;
+        int lds = 0;
+        check_hip(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
+                  "hipDeviceGetAttribute(max shared memory)");
+        p->lds_max = (size_t)lds;
+        // Opt the FFT kernels in to the device's full LDS; the kernels with static
+        // LDS leave room for it.  Not every runtime requires the opt-in, so a
+        // refusal is not fatal: launches that exceed the limit fail loudly.
+        if (set_kernel_lds_limits(p->lds_max - 8192) != hipSuccess) (void)hipGetLastError();
+    }
+    return *p;
+}
+
+std::pair<double2*, float2*> DevCtx::table(const TwiddleReq& r) {
+    auto it = tw.find(r);
+    if (it != tw.end()) return it->second;
+    double2* d64 = nullptr;
+    float2* d32 = nullptr;
+    check_hip(hipMalloc(&d64, sizeof(double2) * r.count), "hipMalloc(twiddles)");
+    check_hip(hipMalloc(&d32, sizeof(float2) * r.count), "hipMalloc(twiddles)");
+    check_hip(launch_twiddle_table(d64, d32, r.N, r.count, r.mult, nullptr), "twiddle table");
+    check_hip(hipDeviceSynchronize(), "twiddle table");
+    tw[r] = {d64, d32};
+    return {d64, d32};
+}
+
+const double2* DevCtx::phase_table(int64_t n) {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = eph.find(n);
+    if (it != eph.end()) return it->second;
+    double2* E = nullptr;
+    check_hip(hipMalloc(&E, sizeof(double2) * n), "hipMalloc(phase table)");
+    check_hip(launch_phase_table(E, n, nullptr), "phase table");
+    check_hip(hipDeviceSynchronize(), "phase table");
+    eph[n] = E;
+    return E;
+}
+
+std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f64) {
+    std::ostringstream key;
+    key << d << ":" << B << ":" << f64 << ":" << tunables().col_max;
+    for (int a = 0; a < d; ++a) key << ":" << dims[a];
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = plans.find(key.str());
+        if (it != plans.end()) return it->second;
+    }
+    auto p = std::make_shared<Plan>();
+    std::string why;
+    const int rc = build_schedule(d, dims, B, f64, &p->s, &why);
+    if (rc) throw Error(rc == -1 ? -1 : -2, why);
+    for (auto& pp : p->s.passes) {
+        if (pp.lds_bytes > lds_max)
+            throw Error(-2, "pass needs " + std::to_string(pp.lds_bytes) + " bytes of LDS");
+    }
+    for (int a = 0; a < d; ++a) p->s.sym.eph[a] = phase_table(dims[a]);
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto& pp : p->s.passes) {
+            PassDesc pd = pp.pd;
+            auto st = table(pp.stage_tab);
+            pd.st_tab = f64 ? (const void*)st.first : (const void*)st.second;
+            if (pp.has_tw) {
+                auto lo = table(pp.tw_lo);
+                auto hi = table(pp.tw_hi);
+                pd.tw_lo = f64 ? (const void*)lo.first : (const void*)lo.second;
+                pd.tw_hi = f64 ? (const void*)hi.first : (const void*)hi.second;
+            }
+            p->pd.push_back(pd);
+            p->lds.push_back(pp.lds_bytes);
+        }
+        plans[key.str()] = p;
+    }
+    return p;
+}
+
+void* DevCtx::workspace(hipStream_t st, size_t bytes) {
+    std::lock_guard<std::mutex> g(mu);
+    auto& w = ws[st];
+    if (bytes == 0) return w.first;
+    if (w.second < bytes) {
+        if (w.first) {
+            check_hip(hipStreamSynchronize(st), "hipStreamSynchronize(workspace growth)");
+            check_hip(hipFree(w.first), "hipFree(workspace)");
+            w.first = nullptr;
+            w.second = 0;
+        }
+        hipError_t e = hipMalloc(&w.first, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            w.first = nullptr;
+            throw Error(-3, "workspace of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+        }
+        w.second = bytes;
+    }
+    return w.first;
+}
+
+void* DevCtx::scratch(hipStream_t st, int slot, size_t bytes) {
+    std::lock_guard<std::mutex> g(mu);
+    auto& w = extra[{st, slot}];
+    if (w.second < bytes) {
+        if (w.first) {
+            check_hip(hipStreamSynchronize(st), "hipStreamSynchronize(scratch growth)");
+            check_hip(hipFree(w.first), "hipFree(scratch)");
+            w.first = nullptr;
+            w.second = 0;
+        }
+        hipError_t e = hipMalloc(&w.first, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            w.first = nullptr;
+            throw Error(-3, "scratch of " + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+        }
+        w.second = bytes;
+    }
+    return w.first;
+}
+
+// ---------------------------------------------------------------- symbol -----
+
+void fill_symbol(SymParams& sp, const double* coeffs, int r, int d, int64_t T, double scale) {
+    int nc = 1;
+    for (int a = 0; a < d; ++a) nc *= 2 * r + 1;
+    sp.r = r;
+    sp.ncoef = nc;
+    sp.T = T;
+    sp.scale = scale;
+    // 1 - sum(c) with the sum carried as hi + lo (Neumaier's compensated sum); when
+    // the sum is close to 1, 1 - hi is exact and only the final subtraction rounds.
+    double s = 0.0, comp = 0.0;
+    for (int i = 0; i < nc; ++i) {
+        sp.c[i] = coeffs[i];
+        const double t = s + coeffs[i];
+        if (std::fabs(s) >= std::fabs(coeffs[i])) comp += (s - t) + coeffs[i];
+        else comp += (coeffs[i] - t) + s;
+        s = t;
+    }
+    sp.one_minus_sum = (1.0 - s) - comp;
+    // point symmetric coefficients (c[o] == c[-o]) give a real symbol
+    int sym = 1;
+    for (int i = 0; i < nc; ++i)
+        if (coeffs[i] != coeffs[nc - 1 - i]) { sym = 0; break; }
+    sp.real_sym = sym;
+}
+
+RealView dense_view(void* ptr, int d, const int64_t* dims) {
+    RealView v;
+    std::memset(&v, 0, sizeof(v));
+    v.ptr = ptr;
+    int64_t s = 1;
+    for (int a = d - 1; a >= 0; --a) {
+        v.stride[a] = s;
+        v.ext[a] = dims[a];
+        s *= dims[a];
+    }
+    v.boff = s;
+    return v;
+}
+
+void run_plan(const Plan& p, void* ws, const RealView& in, const RealView& out, const KeepRule& keep,
+              const SymParams& sym, hipStream_t st) {
+    const bool f64 = p.s.f64;
+    for (size_t i = 0; i < p.pd.size(); ++i) {
+        PassDesc pd = p.pd[i];
+        pd.buf = ws;
+        if (pd.in_real) pd.rv = in;
+        if (pd.out_real) {
+            pd.rv = out;
+            pd.keep = keep;
+        }
+        hipEvent_t ev = nullptr;
+        const bool prof = profiling();
+        if (prof) profile_launch_begin(st, &ev);
+        check_hip(launch_pass(pd, sym, f64, p.lds[i], st), "FFT pass launch");
+        if (prof) profile_launch_end(st, ev, p.s.passes[i].name + (f64 ? "_f64" : "_f32"), p.s.passes[i].model_bytes);
+    }
+}
+
+// ---------------------------------------------------------------- profiling --
+
+namespace {
+struct ProfRec {
+    hipEvent_t a, b;
+    std::string name;
+    int64_t bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+}  // namespace
+
+bool profiling() { return g_prof_on; }
+
+void profile_launch_begin(hipStream_t st, hipEvent_t* ev) {
+    check_hip(hipEventCreate(ev), "hipEventCreate");
+    check_hip(hipEventRecord(*ev, st), "hipEventRecord");
+}
+
+void profile_launch_end(hipStream_t st, hipEvent_t ev0, const std::string& name, int64_t bytes) {
+    hipEvent_t ev1;
+    check_hip(hipEventCreate(&ev1), "hipEventCreate");
+    check_hip(hipEventRecord(ev1, st), "hipEventRecord");
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof.push_back({ev0, ev1, name, bytes});
+}
+
+void profile_enable(bool on) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto& r : g_prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+    g_prof_on = on;
+}
+
+std::string profile_json() {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    struct Acc {
+        int64_t n = 0;
+        double ms = 0;
+        int64_t bytes = 0;
+    };
+    std::map<std::string, Acc> acc;
+    for (auto& r : g_prof) {
+        check_hip(hipEventSynchronize(r.b), "hipEventSynchronize");
+        float ms = 0.f;
+        check_hip(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+        auto& a = acc[r.name];
+        a.n += 1;
+        a.ms += ms;
+        a.bytes += r.bytes;
+    }
+    std::ostringstream o;
+    o.precision(9);
+    o << "{\"kernels\": {";
+    bool first = true;
+    for (auto& kv : acc) {
+        o << (first ? "" : ", ") << "\"" << kv.first << "\": {\"launches\": " << kv.second.n
+          << ", \"ms\": " << kv.second.ms << ", \"bytes\": " << kv.second.bytes << "}";
+        first = false;
+    }
+    o << "}}";
+    return o.str();
+}
+
+}  // namespace sfft

@@ -1,0 +1,71 @@
+// Per-device runtime shared by the entry points: tables, plans, workspace,
+// error reporting and kernel timing.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "sfft_plan.h"
+#include "sfft_types.h"
+
+namespace sfft {
+
+// Error carried to the C ABI boundary.
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+void check_hip(hipError_t e, const char* what);
+void set_last_error(const std::string& msg);
+void clear_last_error();
+
+struct Plan {
+    Schedule s;
+    std::vector<PassDesc> pd;      // with table pointers bound
+    std::vector<size_t> lds;
+};
+
+struct DevCtx {
+    int device = 0;
+    std::mutex mu;
+    std::map<TwiddleReq, std::pair<double2*, float2*>> tw;
+    std::map<int64_t, double2*> eph;
+    std::map<std::string, std::shared_ptr<Plan>> plans;
+    std::map<hipStream_t, std::pair<void*, size_t>> ws;
+    size_t lds_max = 0;
+
+    std::shared_ptr<Plan> plan(int d, const int64_t* dims, int64_t B, bool f64);
+    const double2* phase_table(int64_t n);
+    void* workspace(hipStream_t st, size_t bytes);
+    void* scratch(hipStream_t st, int slot, size_t bytes);  // extra per-stream buffers
+    std::map<std::pair<hipStream_t, int>, std::pair<void*, size_t>> extra;
+
+   private:
+    std::pair<double2*, float2*> table(const TwiddleReq& r);
+};
+
+DevCtx& device_ctx();  // context of the current HIP device (created on first use)
+
+// Coefficient-dependent part of the symbol parameters (Sec. 3 Steps 1(i), 2).
+void fill_symbol(SymParams& sp, const double* coeffs, int radius, int d, int64_t T, double scale);
+
+// Enqueue every pass of a plan.  in/out: real views of the first / last pass.
+void run_plan(const Plan& p, void* ws, const RealView& in, const RealView& out, const KeepRule& keep,
+              const SymParams& sym, hipStream_t st);
+
+// Natural row-major view of a dense array of `dims` (batch stride = element count).
+RealView dense_view(void* ptr, int d, const int64_t* dims);
+
+// Kernel timing (HIP events on the launch stream).
+bool profiling();
+void profile_launch_begin(hipStream_t st, hipEvent_t* ev);
+void profile_launch_end(hipStream_t st, hipEvent_t ev0, const std::string& name, int64_t bytes);
+
+}  // namespace sfft

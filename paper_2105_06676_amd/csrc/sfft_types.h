@@ -1,0 +1,111 @@
+// Descriptors shared by the host planner and the HIP kernels.
+//
+// A periodic solve is a short list of passes over one complex spectrum buffer
+// (Sec. 3, StencilFFT-P): a forward pass per axis (the first one real-to-complex
+// along the contiguous axis), one fused middle pass that finishes the forward
+// transform of axis 0, multiplies by lambda^T / N (Steps 1(i), 2 and 3) and
+// starts the inverse transform, then inverse passes in reverse order (Step 4).
+// Every pass is "rows" (transform along the contiguous axis, whole rows in LDS)
+// or "columns" (transform along a strided axis, a tile of W adjacent columns
+// in LDS).  Long strided axes are split into up to three sub-transforms with
+// twiddles between them (Cooley-Tukey, Sec. 2); the forward output is left in
+// digit-reversed order, which the symbol lookup undoes and the inverse passes
+// consume directly, so no transposes are needed.
+#pragma once
+
+#include <stdint.h>
+
+namespace sfft {
+
+constexpr int kThreads = 256;     // threads per FFT workgroup (four wave64s)
+constexpr int kMaxStages = 16;    // radix stages per sub-transform
+constexpr int kMaxCoef = 125;     // (2r+1)^d for r <= 2, d <= 3
+constexpr int kMaxR = 2;          // largest stencil radius with a fused symbol
+constexpr int kTileElems = 8192;  // complex elements one FFT tile may hold
+
+enum PassKind { PASS_ROW = 0, PASS_COL = 1 };
+enum PassMode { MODE_FWD = 0, MODE_INV = 1, MODE_MID = 2 };
+// How a row pass maps real data to its complex transform.
+//  RT_C2C : the row is complex already (1-D problems split over rows)
+//  RT_HALF: even real length n, transformed as n/2 complex points plus an
+//           even/odd untangling step (n/2+1 spectral entries stored)
+//  RT_ODD : odd real length n, transformed as n complex points with zero
+//           imaginary part ((n+1)/2 spectral entries stored)
+enum RowTrans { RT_C2C = 0, RT_HALF = 1, RT_ODD = 2 };
+
+// A strided real array: the first pass reads it, the last pass writes it.
+struct RealView {
+    void* ptr;            // float* or double*, per the pass precision
+    int64_t boff;         // element offset between consecutive batch items
+    int64_t stride[3];    // element stride of axes 0..d-1
+    int64_t ext[3];       // cells at index >= ext along an axis read as zero and are never written
+};
+
+// Which output cells the last pass stores (Sec. 4 region bookkeeping).
+// dist(g) = 1 + min over faces of the index distance of global interior cell g to
+// the frame.  A cell is stored iff lo < dist <= hi and, when face_axis >= 0, the
+// first face (axis 0 low, axis 0 high, axis 1 low, ...) at distance dist is the
+// slab's own face.
+struct KeepRule {
+    int enabled;
+    int face_axis;        // -1: no face test
+    int face_side;        // 0 low, 1 high, -1 either side, 2 = the batch index
+    int pad_;
+    int64_t lo, hi;
+    int64_t gdim[3];      // interior extents
+    int64_t gorg[3];      // global coordinate of local cell 0 of batch item 0
+    int64_t gbstep[3];    // added per batch item
+};
+
+// Everything the fused middle pass needs to form lambda(k)^T / N in FP64.
+struct SymParams {
+    int d, r, ncoef, real_sym;
+    int64_t T;
+    double one_minus_sum;     // 1 - sum(c), exact (host TwoSum)
+    double scale;             // 1 / prod(n)
+    int64_t n[3];             // transform extents per axis
+    int nlev[3];              // sub-transform levels per axis
+    int64_t sub[3][3];        // sub-lengths per axis in pass order
+    int64_t sdim[3];          // spectrum buffer extents per axis (last axis padded)
+    int64_t hcount;           // valid entries along the last axis (d >= 2)
+    const void* eph[3];       // per-axis tables exp(2 pi i m / n_a) - 1, FP64 complex
+    double c[kMaxCoef];       // coefficients, row-major over offsets
+};
+
+struct PassDesc {
+    int kind, mode, rowtrans;
+    int in_real, out_real;
+    int L;                    // complex transform length of this (sub-)pass
+    int nreal;                // row passes: real length (RT_HALF / RT_ODD)
+    int hcount;               // row passes: stored spectral entries per row
+    int W;                    // columns per tile (col) or rows per tile (row)
+    int lds_stride;           // row passes: LDS stride between rows (complex elements)
+    int64_t outer, inner;     // col: [outer][L][inner]; row: outer = number of rows
+    int64_t ostride, kstride; // complex buffer strides (col: o, k; row: row, -)
+    int64_t ntiles;           // workgroups of this pass
+    int64_t tiles_inner;      // col: tiles per outer index
+    // twiddle between sub-transforms: w = exp(-+2 pi i (k * (c / tw_div)) / tw_n)
+    int tw;                   // 0 none, 1 multiply after forward / before inverse
+    int tw_B;                 // two-level table split: e = q * tw_B + l
+    int64_t tw_n, tw_div;
+    const void* tw_lo;        // exp(-2 pi i l / tw_n), l < tw_B
+    const void* tw_hi;        // exp(-2 pi i q tw_B / tw_n)
+    // radix stages; stage twiddles read exp(-2 pi i m / st_n) at m = e * st_mul
+    const void* st_tab;
+    int st_mul;
+    int nst;
+    int radix[kMaxStages];
+    void* buf;                // complex spectrum buffer
+    RealView rv;
+    KeepRule keep;
+    // problem geometry for addressing real views and the symbol
+    int d;
+    int pad2_;
+    int64_t B;                // batch items
+    int64_t rdims[3];         // transform extents per axis
+    int64_t q_mod;            // mid pass: prefix digits of axis 0 = (outer or row) % q_mod
+    int64_t cpitch;           // col passes: padded pitch of the last axis inside `inner`
+                              // (columns with (c % cpitch) >= hcount are padding); 0 = none
+};
+
+}  // namespace sfft

@@ -1,0 +1,87 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared symbol,
+rejects invalid arguments before touching the GPU, and plans without a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "stencil_fft.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(?:int|void|const char\*)\s+\**\s*(\w+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2105_06676_amd as s
+    names = _declared_functions()
+    assert "stencil_fft_periodic" in names and "stencil_fft_aperiodic" in names
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(s.lib, n), n
+
+
+def test_invalid_arguments_are_rejected_without_a_gpu():
+    import paper_2105_06676_amd as s
+    lib = s.lib
+    f = lib.stencil_fft_periodic
+    dims = (ctypes.c_int64 * 2)(8, 8)
+    c = np.ones((3, 3)) / 9
+    cp = c.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    fake = ctypes.c_void_p(0x1000)
+    # null grid
+    assert f(None, 0, 2, dims, cp, 1, 5, None) == -1
+    # bad ndim, dtype, radius, T
+    assert f(fake, 0, 4, dims, cp, 1, 5, None) == -1
+    assert f(fake, 7, 2, dims, cp, 1, 5, None) == -1
+    assert f(fake, 0, 2, dims, cp, -1, 5, None) == -1
+    assert f(fake, 0, 2, dims, cp, 1, -5, None) == -1
+    # non-finite coefficient
+    bad = c.copy()
+    bad[1, 1] = np.nan
+    assert f(fake, 0, 2, dims, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 1, 5, None) == -1
+    assert "not finite" in s._binding._last_error().decode()
+    # zero extent
+    z = (ctypes.c_int64 * 2)(0, 8)
+    assert f(fake, 0, 2, z, cp, 1, 5, None) == -1
+    # prime factor above 7
+    p = (ctypes.c_int64 * 2)(11, 8)
+    assert f(fake, 0, 2, p, cp, 1, 5, None) == -2
+    assert "prime factor" in s._binding._last_error().decode()
+
+
+def test_unknown_option_rejected():
+    import paper_2105_06676_amd as s
+    with pytest.raises(s.SfftError):
+        s.set_option("no_such_option", 1)
+    with pytest.raises(s.SfftError):
+        s.set_option("col_max", 100)
+
+
+@pytest.mark.parametrize("dims,dtype", [((65536,), "f64"), ((8192, 8192), "f32"), ((8192, 8192), "f64"),
+                                        ((512, 512, 512), "f32"), ((1000,), "f64"), ((1, 64), "f32"),
+                                        ((7, 9, 5), "f64"), ((1 << 24,), "f32")])
+def test_plan_schedule_shape(dims, dtype):
+    """The schedule has 2*(number of passes per axis) - 1 passes with one fused middle
+    pass, and its model bytes add up per pass."""
+    import paper_2105_06676_amd as s
+    p = s.plan_describe(dims, dtype)
+    modes = [q["mode"] for q in p["passes"]]
+    assert modes.count("mid") == 1
+    mid = modes.index("mid")
+    assert all(m == "fwd" for m in modes[:mid]) and all(m == "inv" for m in modes[mid + 1:])
+    assert len(modes[:mid]) == len(modes[mid + 1:])
+    assert p["model_bytes"] == sum(q["model_bytes"] for q in p["passes"])
+    # every sub-transform length factors the extent
+    for a, lev in enumerate(p["levels"]):
+        assert int(np.prod(lev)) == dims[a]
+    for q in p["passes"]:
+        assert int(np.prod(q["radices"] or [1])) == q["L"]
+        assert q["lds_bytes"] <= 160 * 1024
