@@ -1,10 +1,314 @@
-// StencilFFT-A / RecursiveBoundary (Sec. 4) -- placeholder until the planner lands.
+// StencilFFT-A and RecursiveBoundary (Sec. 4) on one GPU.
+//
+// The stored array has extents n_a + 2r; its r-wide frame holds fixed boundary
+// values.  dist(cell) = 1 + min over faces of the index distance to the frame.
+// After T steps only cells with dist <= r*T see the frame (region of influence),
+// so the result is assembled from
+//   * the periodic solve (StencilFFT-P) of the whole interior, kept where
+//     dist > r*T, and
+//   * RecursiveBoundary(T), which produces dist <= r*T from the band
+//     dist <= 2 r T of the initial array:
+//       T <= cutoff: loop T steps in LDS on the band (base-case kernel);
+//       else T1 = floor(T/2), T2 = T - T1, and
+//         step 1: periodic solves of the 2d slabs of band (0, 2rT] for T1 steps,
+//                 kept on (r T1, r T + r T2], plus RecursiveBoundary(T1) for
+//                 (0, r T1], giving the band at time T1;
+//         step 2: periodic solves of the slabs of band (0, r T + r T2] for T2
+//                 steps, kept on (r T2, r T], plus RecursiveBoundary(T2) for
+//                 (0, r T2].
+// A slab of face f spans the band's depth along f's normal and the whole interior
+// along the other axes; a cell is taken from the slab of its nearest face, where
+// its r*steps cone stays inside the slab and away from every other face.  Slab
+// and interior transforms may therefore be zero-padded to 7-smooth extents.  The
+// two slabs of one axis share a shape and run as one batched solve.
+#include <algorithm>
+#include <climits>
+#include <cstring>
+#include <vector>
+
+#include "sfft_base.h"
 #include "sfft_runtime.h"
 
 namespace sfft {
 
-void solve_aperiodic(void*, bool, int, const int64_t*, const double*, int, int64_t, hipStream_t) {
-    throw Error(-2, "aperiodic solver not built yet");
+namespace {
+
+int64_t pad7(int64_t n) {
+    while (!is_7smooth(n)) ++n;
+    return n;
+}
+
+int64_t ceil_half(int64_t n) { return (n + 1) / 2; }
+
+struct Ap {
+    bool f64;
+    int d, r;
+    int64_t n[3];        // interior extents (axes 0..d-1)
+    int64_t sstride[3];  // element strides of the stored array
+    size_t esz;
+    const double* coeffs;
+    hipStream_t st;
+    void* grid;
+    int64_t total;       // stored elements
+    std::vector<void*> level;
+    int64_t cutoff;
+    int64_t maxdist;     // largest dist of any interior cell
+};
+
+void* interior_origin(const Ap& a, const void* base) {
+    int64_t off = 0;
+    for (int k = 0; k < a.d; ++k) off += a.r * a.sstride[k];
+    return (char*)base + off * (int64_t)a.esz;
+}
+
+// Periodic solve of B boxes of `ext` cells read from `src` and written to `dst`
+// (both at the interior origin), zero-padded to 7-smooth transform extents.
+void boxed_periodic(Ap& a, const void* src, void* dst, const int64_t* ext, int64_t B, int64_t boff,
+                    const KeepRule& keep, int64_t steps) {
+    int64_t pd[3];
+    for (int k = 0; k < a.d; ++k) pd[k] = pad7(ext[k]);
+    DevCtx& ctx = device_ctx();
+    auto plan = ctx.plan(a.d, pd, B, a.f64);
+    void* ws = ctx.workspace(a.st, (size_t)plan->s.spec_elems * (a.f64 ? 16 : 8));
+    SymParams sp = plan->s.sym;
+    double N = 1.0;
+    for (int k = 0; k < a.d; ++k) N *= (double)pd[k];
+    fill_symbol(sp, a.coeffs, a.r, a.d, steps, 1.0 / N);
+    RealView in;
+    std::memset(&in, 0, sizeof(in));
+    in.boff = boff;
+    for (int k = 0; k < a.d; ++k) {
+        in.stride[k] = a.sstride[k];
+        in.ext[k] = ext[k];
+    }
+    RealView out = in;
+    in.ptr = const_cast<void*>(src);
+    out.ptr = dst;
+    run_plan(*plan, ws, in, out, keep, sp, a.st);
+}
+
+KeepRule make_keep(const Ap& a, int64_t lo, int64_t hi) {
+    KeepRule k;
+    std::memset(&k, 0, sizeof(k));
+    k.enabled = 1;
+    k.face_axis = -1;
+    k.face_side = -1;
+    k.lo = lo;
+    k.hi = hi;
+    for (int i = 0; i < a.d; ++i) k.gdim[i] = a.n[i];
+    return k;
+}
+
+// Periodic solves of the slabs of band (0, w] of `src` over `steps`, storing
+// (lo, hi] into `dst`.
+void slab_solve(Ap& a, const void* src, void* dst, int64_t w, int64_t steps, int64_t lo, int64_t hi) {
+    if (lo >= a.maxdist || hi <= lo) return;
+    const void* s0 = interior_origin(a, src);
+    void* d0 = interior_origin(a, dst);
+    for (int ax = 0; ax < a.d; ++ax) {
+        if (lo >= ceil_half(a.n[ax])) continue;  // no cell nearest to this axis' faces is kept
+        const int64_t ta = std::min(w, a.n[ax]);
+        int64_t ext[3];
+        for (int k = 0; k < a.d; ++k) ext[k] = k == ax ? ta : a.n[k];
+        KeepRule keep = make_keep(a, lo, hi);
+        keep.face_axis = ax;
+        int64_t B = 1;
+        int64_t boff = 0;
+        if (ta < a.n[ax]) {
+            B = 2;
+            keep.face_side = 2;
+            keep.gbstep[ax] = a.n[ax] - ta;
+            boff = (a.n[ax] - ta) * a.sstride[ax];
+        }
+        boxed_periodic(a, s0, d0, ext, B, boff, keep, steps);
+    }
+}
+
+// Loop `tau` steps on the band dist <= 2 r tau of src; store dist <= r tau into dst.
+void base_case(Ap& a, const void* src, void* dst, int64_t tau) {
+    BaseParams bp;
+    std::memset(&bp, 0, sizeof(bp));
+    const int sh = 3 - a.d;  // axis k of the problem is slot k + sh
+    for (int k = 0; k < 3; ++k) {
+        bp.n[k] = 1;
+        bp.r3[k] = 0;
+        bp.halo3[k] = 0;
+        bp.sstride[k] = 0;
+    }
+    for (int k = 0; k < a.d; ++k) {
+        bp.n[k + sh] = a.n[k];
+        bp.r3[k + sh] = a.r;
+        bp.halo3[k + sh] = a.r * tau;
+        bp.sstride[k + sh] = a.sstride[k];
+    }
+    bp.steps = (int)tau;
+    bp.src = src;
+    bp.frame = a.grid;
+    bp.dst = dst;
+    // non-zero stencil terms
+    const int w = 2 * a.r + 1;
+    int nc = 1;
+    for (int k = 0; k < a.d; ++k) nc *= w;
+    int m = 0;
+    for (int i = 0; i < nc; ++i) {
+        if (a.coeffs[i] == 0.0) continue;
+        int rem = i;
+        int o[3] = {0, 0, 0};
+        for (int k = a.d - 1; k >= 0; --k) {
+            o[k + sh] = rem % w - a.r;
+            rem /= w;
+        }
+        bp.off[m][0] = o[0];
+        bp.off[m][1] = o[1];
+        bp.off[m][2] = o[2];
+        bp.c[m] = a.coeffs[i];
+        ++m;
+    }
+    bp.ncoef = m;
+    // strips covering dist <= wout without overlap
+    const int64_t wout = a.r * tau;
+    int64_t first = 0;
+    size_t lds = 0;
+    int ns = 0;
+    for (int ax = 0; ax < a.d; ++ax) {
+        for (int side = 0; side < 2; ++side) {
+            int64_t lo[3], hi[3];
+            bool empty = false;
+            for (int k = 0; k < a.d; ++k) {
+                if (k == ax) {
+                    if (side == 0) { lo[k] = 0; hi[k] = std::min(wout, a.n[k]); }
+                    else { lo[k] = std::max(wout, a.n[k] - wout); hi[k] = a.n[k]; }
+                } else if (k < ax) {
+                    lo[k] = wout;
+                    hi[k] = a.n[k] - wout;
+                } else {
+                    lo[k] = 0;
+                    hi[k] = a.n[k];
+                }
+                if (hi[k] <= lo[k]) empty = true;
+            }
+            if (empty) continue;
+            BaseStrip& s = bp.strip[ns];
+            for (int k = 0; k < 3; ++k) {
+                s.lo[k] = 0;
+                s.ext[k] = 1;
+                s.tile[k] = 1;
+            }
+            for (int k = 0; k < a.d; ++k) {
+                s.lo[k + sh] = lo[k];
+                s.ext[k + sh] = hi[k] - lo[k];
+                s.tile[k + sh] = s.ext[k + sh];
+            }
+            auto foot = [&]() {
+                int64_t f = 1;
+                for (int k = 0; k < 3; ++k) f *= s.tile[k] + 2 * bp.halo3[k];
+                return f;
+            };
+            while (foot() > kBaseMaxCells) {
+                int best = -1;
+                for (int k = 0; k < 3; ++k)
+                    if (s.tile[k] > 1 && (best < 0 || s.tile[k] > s.tile[best])) best = k;
+                if (best < 0) throw Error(-2, "base case band too wide for one LDS tile; lower aperiodic_cutoff");
+                s.tile[best] = (s.tile[best] + 1) / 2;
+            }
+            int64_t cnt = 1;
+            for (int k = 0; k < 3; ++k) {
+                s.ntiles[k] = (s.ext[k] + s.tile[k] - 1) / s.tile[k];
+                cnt *= s.ntiles[k];
+            }
+            s.first = first;
+            first += cnt;
+            lds = std::max(lds, (size_t)foot() * a.esz);
+            ++ns;
+        }
+    }
+    bp.nstrip = ns;
+    if (ns == 0) return;
+    hipEvent_t ev = nullptr;
+    const bool prof = profiling();
+    if (prof) profile_launch_begin(a.st, &ev);
+    check_hip(launch_base(bp, a.f64, first, lds, a.st), "base-case launch");
+    if (prof) profile_launch_end(a.st, ev, a.f64 ? "base_case_f64" : "base_case_f32", 0);
+}
+
+void recursive_boundary(Ap& a, const void* src, void* dst, int64_t T, int lev) {
+    if (T <= a.cutoff) {
+        base_case(a, src, dst, T);
+        return;
+    }
+    const int64_t T1 = T / 2, T2 = T - T1;
+    const int64_t s = a.r;
+    if ((int)a.level.size() <= lev) {
+        void* p = device_ctx().scratch(a.st, 100 + lev, (size_t)a.total * a.esz);
+        a.level.push_back(p);
+    }
+    void* mid = a.level[lev];
+    // step 1: band (0, 2sT] at t0 -> (0, sT + sT2] at t0 + T1
+    slab_solve(a, src, mid, 2 * s * T, T1, s * T1, s * T + s * T2);
+    recursive_boundary(a, src, mid, T1, lev + 1);
+    // step 2: band (0, sT + sT2] at t0 + T1 -> (0, sT] at t0 + T
+    slab_solve(a, mid, dst, s * T + s * T2, T2, s * T2, s * T);
+    recursive_boundary(a, mid, dst, T2, lev + 1);
+}
+
+}  // namespace
+
+void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
+                     hipStream_t st) {
+    Ap a;
+    a.f64 = f64;
+    a.d = d;
+    a.r = r;
+    a.esz = f64 ? 8 : 4;
+    a.coeffs = coeffs;
+    a.st = st;
+    a.grid = grid;
+    int64_t s = 1;
+    for (int k = d - 1; k >= 0; --k) {
+        a.n[k] = dims[k];
+        a.sstride[k] = s;
+        s *= dims[k] + 2 * r;
+    }
+    a.total = s;
+    a.maxdist = LLONG_MAX;
+    for (int k = 0; k < d; ++k) a.maxdist = std::min(a.maxdist, ceil_half(a.n[k]));
+    if (r == 0) {
+        // no neighbours: the frame is never read and every cell scales by c0^T
+        KeepRule keep = make_keep(a, 0, LLONG_MAX);
+        keep.enabled = 0;
+        boxed_periodic(a, interior_origin(a, grid), interior_origin(a, grid), a.n, 1, 0, keep, T);
+        return;
+    }
+    // base-case reach: the halo r * cutoff must fit an LDS tile
+    const int64_t reach = d == 1 ? 256 : d == 2 ? 16 : 4;
+    a.cutoff = tunables().aperiodic_cutoff > 0 ? tunables().aperiodic_cutoff : std::max<int64_t>(1, reach / r);
+    const int64_t sT = (int64_t)r * T;
+    // RecursiveBoundary step 1 reads the initial band before the interior solve
+    // overwrites dist > sT; step 2 writes dist <= sT after the interior solve has
+    // read the whole initial interior.
+    if (T <= a.cutoff) {
+        // The base case reads dist <= 2 sT of the initial array while the result
+        // is stored in place, so it reads from a copy.
+        void* tmp = device_ctx().scratch(st, 99, (size_t)a.total * a.esz);
+        check_hip(hipMemcpyAsync(tmp, grid, (size_t)a.total * a.esz, hipMemcpyDeviceToDevice, st), "copy");
+        if (sT < a.maxdist) {
+            KeepRule keep = make_keep(a, sT, LLONG_MAX);
+            boxed_periodic(a, interior_origin(a, tmp), interior_origin(a, grid), a.n, 1, 0, keep, T);
+        }
+        base_case(a, tmp, grid, T);
+        return;
+    }
+    const int64_t T1 = T / 2, T2 = T - T1;
+    void* mid = device_ctx().scratch(st, 100, (size_t)a.total * a.esz);
+    a.level.push_back(mid);
+    slab_solve(a, grid, mid, 2 * sT, T1, r * T1, sT + r * T2);
+    recursive_boundary(a, grid, mid, T1, 1);
+    if (sT < a.maxdist) {
+        KeepRule keep = make_keep(a, sT, LLONG_MAX);
+        boxed_periodic(a, interior_origin(a, grid), interior_origin(a, grid), a.n, 1, 0, keep, T);
+    }
+    slab_solve(a, mid, grid, sT + r * T2, T2, r * T2, sT);
+    recursive_boundary(a, mid, grid, T2, 1);
 }
 
 }  // namespace sfft

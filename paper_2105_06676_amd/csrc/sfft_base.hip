@@ -1,0 +1,129 @@
+// Base case of RecursiveBoundary (Sec. 4): loop `steps` stencil steps near the
+// fixed frame, in LDS, and store the cells within `wout` of the frame.
+//
+// The band to produce (dist <= wout) is cut into disjoint boxes ("strips", one
+// per face, later faces excluding what earlier faces cover) and each strip into
+// tiles.  A workgroup loads its tile plus a halo of radius*steps cells (clipped to
+// the stored array, whose frame is fixed and read from the frame source), runs the
+// steps in LDS (cells whose neighbourhood is not loaded keep stale values; the
+// stale margin grows by `radius` per step and never reaches the tile), and
+// stores the tile.  Reads stay inside dist <= 2 * wout, as the recursion
+// guarantees valid input there.
+#include <hip/hip_runtime.h>
+
+#include "sfft_base.h"
+
+namespace sfft {
+
+template <typename R>
+__global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    R* A = reinterpret_cast<R*>(smem_raw);
+    __shared__ int offs[kMaxCoef];
+    __shared__ R coef[kMaxCoef];
+
+    // which strip and tile
+    const int64_t bid = blockIdx.x;
+    int s = 0;
+    while (s + 1 < bp.nstrip && bid >= bp.strip[s + 1].first) ++s;
+    const BaseStrip& st = bp.strip[s];
+    int64_t t = bid - st.first;
+    int64_t org[3], ext[3];
+    for (int a = 2; a >= 0; --a) {
+        const int64_t ti = t % st.ntiles[a];
+        t /= st.ntiles[a];
+        org[a] = st.lo[a] + ti * st.tile[a];
+        ext[a] = min(st.tile[a], st.lo[a] + st.ext[a] - org[a]);
+    }
+    // LDS region in storage coordinates: [rlo, rlo + rext)
+    int64_t rlo[3], rext[3];
+    for (int a = 0; a < 3; ++a) {
+        const int64_t slo = org[a] + bp.r3[a] - bp.halo3[a];
+        const int64_t shi = org[a] + bp.r3[a] + ext[a] + bp.halo3[a];
+        rlo[a] = slo < 0 ? 0 : slo;
+        const int64_t sx = bp.n[a] + 2 * bp.r3[a];
+        rext[a] = (shi > sx ? sx : shi) - rlo[a];
+    }
+    const int le1 = (int)rext[2];
+    const int le0 = (int)(rext[1] * rext[2]);
+    const int cells = (int)(rext[0] * rext[1] * rext[2]);
+
+    for (int i = threadIdx.x; i < bp.ncoef; i += kBaseThreads) {
+        offs[i] = bp.off[i][0] * le0 + bp.off[i][1] * le1 + bp.off[i][2];
+        coef[i] = (R)bp.c[i];
+    }
+
+    const R* src = (const R*)bp.src;
+    const R* frame = (const R*)bp.frame;
+    // load
+    for (int i = threadIdx.x; i < cells; i += kBaseThreads) {
+        const int x0 = i / le0, rem = i - x0 * le0, x1 = rem / le1, x2 = rem - x1 * le1;
+        const int64_t g0 = rlo[0] + x0, g1 = rlo[1] + x1, g2 = rlo[2] + x2;
+        const bool fr = g0 < bp.r3[0] || g0 >= bp.n[0] + bp.r3[0] || g1 < bp.r3[1] || g1 >= bp.n[1] + bp.r3[1] ||
+                        g2 < bp.r3[2] || g2 >= bp.n[2] + bp.r3[2];
+        const int64_t gi = g0 * bp.sstride[0] + g1 * bp.sstride[1] + g2 * bp.sstride[2];
+        A[i] = fr ? frame[gi] : src[gi];
+    }
+    // per-thread cells and whether they are updated (interior cell whose whole
+    // neighbourhood lies inside the loaded region)
+    constexpr int MAXC = kBaseMaxCells / kBaseThreads;
+    int idx[MAXC];
+    bool upd[MAXC];
+#pragma unroll
+    for (int k = 0; k < MAXC; ++k) {
+        const int i = threadIdx.x + k * kBaseThreads;
+        idx[k] = i;
+        upd[k] = false;
+        if (i < cells) {
+            const int x0 = i / le0, rem = i - x0 * le0, x1 = rem / le1, x2 = rem - x1 * le1;
+            const int64_t xs[3] = {x0, x1, x2};
+            bool ok = true;
+            for (int a = 0; a < 3; ++a) {
+                const int64_t g = rlo[a] + xs[a];
+                if (g < bp.r3[a] || g >= bp.n[a] + bp.r3[a]) ok = false;             // frame cell: fixed
+                if (xs[a] < bp.r3[a] || xs[a] + bp.r3[a] >= rext[a]) ok = false;     // neighbourhood not loaded
+            }
+            upd[k] = ok;
+        }
+    }
+    __syncthreads();
+
+    for (int step = 0; step < bp.steps; ++step) {
+        R nv[MAXC];
+#pragma unroll
+        for (int k = 0; k < MAXC; ++k) {
+            if (upd[k]) {
+                R acc = R(0);
+                for (int j = 0; j < bp.ncoef; ++j) acc += coef[j] * A[idx[k] + offs[j]];
+                nv[k] = acc;
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < MAXC; ++k)
+            if (upd[k]) A[idx[k]] = nv[k];
+        __syncthreads();
+    }
+
+    // store the tile (every tile cell lies in the band dist <= wout)
+    R* dst = (R*)bp.dst;
+    const int64_t tcells = ext[0] * ext[1] * ext[2];
+    for (int64_t i = threadIdx.x; i < tcells; i += kBaseThreads) {
+        const int64_t y0 = i / (ext[1] * ext[2]);
+        const int64_t rem = i - y0 * ext[1] * ext[2];
+        const int64_t y1 = rem / ext[2], y2 = rem - y1 * ext[2];
+        const int64_t s0 = org[0] + bp.r3[0] + y0, s1 = org[1] + bp.r3[1] + y1, s2 = org[2] + bp.r3[2] + y2;
+        const int li = (int)(((s0 - rlo[0]) * rext[1] + (s1 - rlo[1])) * rext[2] + (s2 - rlo[2]));
+        dst[s0 * bp.sstride[0] + s1 * bp.sstride[1] + s2 * bp.sstride[2]] = A[li];
+    }
+}
+
+hipError_t launch_base(const BaseParams& bp, bool f64, int64_t nblocks, size_t lds, hipStream_t st) {
+    if (f64)
+        hipLaunchKernelGGL(k_base<double>, dim3((unsigned)nblocks), dim3(kBaseThreads), lds, st, bp);
+    else
+        hipLaunchKernelGGL(k_base<float>, dim3((unsigned)nblocks), dim3(kBaseThreads), lds, st, bp);
+    return hipGetLastError();
+}
+
+}  // namespace sfft

@@ -31,15 +31,15 @@ __device__ __forceinline__ int64_t row_coords(const PassDesc& pd, int64_t row, i
     return rem;
 }
 
-__device__ __forceinline__ bool prefix_inside(const PassDesc& pd, const int64_t* i) {
-    for (int a = 0; a < pd.d - 1; ++a)
-        if (i[a] >= pd.rv.ext[a]) return false;
+__device__ __forceinline__ bool prefix_inside(const RealView& v, int d, const int64_t* i) {
+    for (int a = 0; a < d - 1; ++a)
+        if (i[a] >= v.ext[a]) return false;
     return true;
 }
 
-__device__ __forceinline__ int64_t prefix_offset(const PassDesc& pd, int64_t b, const int64_t* i) {
-    int64_t off = b * pd.rv.boff;
-    for (int a = 0; a < pd.d - 1; ++a) off += i[a] * pd.rv.stride[a];
+__device__ __forceinline__ int64_t prefix_offset(const RealView& v, int d, int64_t b, const int64_t* i) {
+    int64_t off = b * v.boff;
+    for (int a = 0; a < d - 1; ++a) off += i[a] * v.stride[a];
     return off;
 }
 
@@ -121,8 +121,8 @@ __global__ __launch_bounds__(kThreads) void k_row(PassDesc pd, SymParams sp) {
             int64_t idx[3];
             const int64_t b = row_coords(pd, row0 + rr, idx);
             cx<R> v = {R(0), R(0)};
-            if (prefix_inside(pd, idx)) {
-                const int64_t base = prefix_offset(pd, b, idx);
+            if (prefix_inside(pd.rv, pd.d, idx)) {
+                const int64_t base = prefix_offset(pd.rv, pd.d, b, idx);
                 if (pd.rowtrans == RT_HALF) {
                     if (2 * m < el) v.x = rin[base + (int64_t)(2 * m) * sl];
                     if (2 * m + 1 < el) v.y = rin[base + (int64_t)(2 * m + 1) * sl];
@@ -181,20 +181,20 @@ __global__ __launch_bounds__(kThreads) void k_row(PassDesc pd, SymParams sp) {
 
     // ---- store
     if (pd.out_real) {
-        R* rout = (R*)pd.rv.ptr;
-        const int64_t sl = pd.rv.stride[pd.d - 1];
-        const int64_t el = pd.rv.ext[pd.d - 1];
+        R* rout = (R*)pd.rvo.ptr;
+        const int64_t sl = pd.rvo.stride[pd.d - 1];
+        const int64_t el = pd.rvo.ext[pd.d - 1];
         const int per = half ? 2 * L : L;
         for (int e = threadIdx.x; e < nrows * per; e += kThreads) {
             const int rr = e / per, m = e - rr * per;
             if (m >= el) continue;
             int64_t idx[3];
             const int64_t b = row_coords(pd, row0 + rr, idx);
-            if (!prefix_inside(pd, idx)) continue;
+            if (!prefix_inside(pd.rvo, pd.d, idx)) continue;
             idx[pd.d - 1] = m;
             if (!keep_cell(pd.keep, pd.d, b, idx)) continue;
             const cx<R> z = lds[rr * LS + (half ? (m >> 1) : m)];
-            rout[prefix_offset(pd, b, idx) + (int64_t)m * sl] = half ? ((m & 1) ? z.y : z.x) : z.x;
+            rout[prefix_offset(pd.rvo, pd.d, b, idx) + (int64_t)m * sl] = half ? ((m & 1) ? z.y : z.x) : z.x;
         }
     } else {
         cx<R>* dst = (cx<R>*)pd.buf;
@@ -293,10 +293,10 @@ __global__ __launch_bounds__(kThreads) void k_col(PassDesc pd, SymParams sp) {
         if (pd.mode == MODE_FWD && pd.tw) v = cmul(v, step_twiddle<R>(pd, (int64_t)k * (c / pd.tw_div)));
         if (pd.out_real) {
             const int64_t m = (int64_t)k * pd.kstride + c;
-            if (m >= pd.rv.ext[0]) continue;
+            if (m >= pd.rvo.ext[0]) continue;
             int64_t idx[3] = {m, 0, 0};
             if (!keep_cell(pd.keep, 1, o, idx)) continue;
-            ((R*)pd.rv.ptr)[o * pd.rv.boff + m * pd.rv.stride[0]] = v.x;
+            ((R*)pd.rvo.ptr)[o * pd.rvo.boff + m * pd.rvo.stride[0]] = v.x;
         } else {
             ((cx<R>*)pd.buf)[o * pd.ostride + (int64_t)k * pd.kstride + c] = v;
         }

@@ -199,7 +199,7 @@ void run_plan(const Plan& p, void* ws, const RealView& in, const RealView& out, 
         pd.buf = ws;
         if (pd.in_real) pd.rv = in;
         if (pd.out_real) {
-            pd.rv = out;
+            pd.rvo = out;
             pd.keep = keep;
         }
         hipEvent_t ev = nullptr;

@@ -96,7 +96,8 @@ struct PassDesc {
     int nst;
     int radix[kMaxStages];
     void* buf;                // complex spectrum buffer
-    RealView rv;
+    RealView rv;              // real input of the first pass
+    RealView rvo;             // real output of the last pass
     KeepRule keep;
     // problem geometry for addressing real views and the symbol
     int d;
