@@ -136,6 +136,9 @@ int stencil_fft_set_option(const char* name, int64_t value) {
             if (value != 0 && (value < 16 || value > 1024 || (value & (value - 1))))
                 throw Error(SFFT_EINVAL, "col_max must be 0 or a power of two in 16..1024");
             tunables().col_max = (int)value;
+        } else if (n == "generic_kernels") {
+            if (value != 0 && value != 1) throw Error(SFFT_EINVAL, "generic_kernels must be 0 or 1");
+            tunables().no_fast = (int)value;
         } else if (n == "aperiodic_cutoff") {
             if (value < 0 || value > (1 << 20)) throw Error(SFFT_EINVAL, "aperiodic_cutoff out of range");
             tunables().aperiodic_cutoff = (int)value;

@@ -226,9 +226,9 @@ template <typename R>
 __device__ __forceinline__ cx<R> step_twiddle(const PassDesc& pd, int64_t e) {
     const cx<R>* lo = (const cx<R>*)pd.tw_lo;
     const cx<R>* hi = (const cx<R>*)pd.tw_hi;
-    const int64_t q = e / pd.tw_B;
-    const int64_t l = e - q * pd.tw_B;
-    cx<R> w = lo[l];
+    const uint32_t u = (uint32_t)e;  // e < tw_n <= 2^31
+    cx<R> w = lo[u & (kTwSplit - 1)];
+    const uint32_t q = u >> kTwSplitLog;
     if (q) w = cmul(w, hi[q]);
     return w;
 }
@@ -303,44 +303,104 @@ __device__ __forceinline__ dcx eph(const SymParams& sp, int a, int o, int64_t k)
     return e;
 }
 
-// Per-column part: G[o0] and K = (1 - sum c) - sum D for the axis-1..d-1 frequencies f.
-__device__ inline void symbol_column(const SymParams& sp, const int64_t* f, dcx* G, dcx* K) {
+// Per-column part of the symbol for the axis-1..d-1 frequencies f: G[o0] for
+// o0 = +1..+r (Gp) and -1..-r (Gm), and K = (1 - sum c) - sum_{o0} D[o0].  All
+// arrays are indexed by compile-time offsets so they stay in registers.
+struct SymCol {
+    dcx Gp[kMaxR + 1], Gm[kMaxR + 1];
+    dcx K;
+};
+
+// E_a((o * f) mod n_a) for o in [-kMaxR, kMaxR] (32-bit index arithmetic).
+__device__ __forceinline__ dcx eph32(const SymParams& sp, int a, int o, uint32_t f) {
+    const uint32_t n = (uint32_t)sp.n[a];
+    uint32_t m = (uint32_t)(o < 0 ? -o : o) * f;
+    m = (n & (n - 1)) == 0 ? (m & (n - 1)) : (m % n);
+    dcx e = ((const dcx*)sp.eph[a])[m];
+    if (o < 0) e.y = -e.y;  // E(-m) = conj(E(m))
+    return e;
+}
+
+__device__ inline SymCol symbol_column(const SymParams& sp, const int64_t* f) {
+    SymCol out;
     const int r = sp.r, w = 2 * r + 1;
+    // phases of axes 1 and 2 for every offset, looked up once
+    dcx e1[2 * kMaxR + 1], e2[2 * kMaxR + 1];
+#pragma unroll
+    for (int o = -kMaxR; o <= kMaxR; ++o) {
+        e1[o + kMaxR] = (sp.d >= 2 && o >= -r && o <= r) ? eph32(sp, 1, o, (uint32_t)f[1]) : dcx{0.0, 0.0};
+        e2[o + kMaxR] = (sp.d >= 3 && o >= -r && o <= r) ? eph32(sp, 2, o, (uint32_t)f[2]) : dcx{0.0, 0.0};
+    }
     dcx dsum = {0.0, 0.0};
-    for (int o0 = -r; o0 <= r; ++o0) {
+#pragma unroll
+    for (int o0 = -kMaxR; o0 <= kMaxR; ++o0) {
         dcx g = {0.0, 0.0}, dd = {0.0, 0.0};
-        if (sp.d == 1) {
-            g.x = sp.c[o0 + r];
-        } else if (sp.d == 2) {
-            for (int o1 = -r; o1 <= r; ++o1) {
-                const double c = sp.c[(o0 + r) * w + (o1 + r)];
-                const dcx p = eph(sp, 1, o1, f[1]);
-                g = dadd(g, dcx{c * (1.0 + p.x), c * p.y});
-                dd = dadd(dd, dcx{c * p.x, c * p.y});
-            }
-        } else {
-            for (int o1 = -r; o1 <= r; ++o1) {
-                const dcx e1 = eph(sp, 1, o1, f[1]);
-                for (int o2 = -r; o2 <= r; ++o2) {
-                    const double c = sp.c[((o0 + r) * w + (o1 + r)) * w + (o2 + r)];
-                    const dcx e2 = eph(sp, 2, o2, f[2]);
-                    const dcx p = dadd(dadd(e1, e2), dmul(e1, e2));
+        if (o0 >= -r && o0 <= r) {
+            if (sp.d == 1) {
+                g.x = sp.c[o0 + r];
+            } else if (sp.d == 2) {
+#pragma unroll
+                for (int o1 = -kMaxR; o1 <= kMaxR; ++o1) {
+                    if (o1 < -r || o1 > r) continue;
+                    const double c = sp.c[(o0 + r) * w + (o1 + r)];
+                    const dcx p = e1[o1 + kMaxR];
                     g = dadd(g, dcx{c * (1.0 + p.x), c * p.y});
                     dd = dadd(dd, dcx{c * p.x, c * p.y});
                 }
+            } else {
+#pragma unroll
+                for (int o1 = -kMaxR; o1 <= kMaxR; ++o1) {
+                    if (o1 < -r || o1 > r) continue;
+                    const dcx a1 = e1[o1 + kMaxR];
+#pragma unroll
+                    for (int o2 = -kMaxR; o2 <= kMaxR; ++o2) {
+                        if (o2 < -r || o2 > r) continue;
+                        const double c = sp.c[((o0 + r) * w + (o1 + r)) * w + (o2 + r)];
+                        const dcx a2 = e2[o2 + kMaxR];
+                        const dcx p = dadd(dadd(a1, a2), dmul(a1, a2));
+                        g = dadd(g, dcx{c * (1.0 + p.x), c * p.y});
+                        dd = dadd(dd, dcx{c * p.x, c * p.y});
+                    }
+                }
             }
+            dsum = dadd(dsum, dd);
         }
-        G[o0 + r] = g;
-        dsum = dadd(dsum, dd);
+        if (o0 > 0) out.Gp[o0] = g;
+        if (o0 < 0) out.Gm[-o0] = g;
     }
-    *K = dcx{sp.one_minus_sum - dsum.x, -dsum.y};
+    out.Gp[0] = out.Gm[0] = dcx{0.0, 0.0};
+    out.K = dcx{sp.one_minus_sum - dsum.x, -dsum.y};
+    return out;
 }
 
-__device__ __forceinline__ dcx symbol_mu(const SymParams& sp, const dcx* G, dcx K, int64_t f0) {
-    dcx mu = K;
-    for (int o0 = -sp.r; o0 <= sp.r; ++o0) {
-        if (o0 == 0) continue;
-        mu = dsub(mu, dmul(eph(sp, 0, o0, f0), G[o0 + sp.r]));
+// 1-D symbol: G = c, K = 1 - sum c.
+__device__ inline SymCol symbol_column_1d(const SymParams& sp) {
+    SymCol out;
+#pragma unroll
+    for (int o = 0; o <= kMaxR; ++o) {
+        out.Gp[o] = dcx{o >= 1 && o <= sp.r ? sp.c[sp.r + o] : 0.0, 0.0};
+        out.Gm[o] = dcx{o >= 1 && o <= sp.r ? sp.c[sp.r - o] : 0.0, 0.0};
+    }
+    out.K = dcx{sp.one_minus_sum, 0.0};
+    return out;
+}
+
+// mu = 1 - lambda at axis-0 frequency f0 given the column part.
+__device__ __forceinline__ dcx symbol_mu(const SymParams& sp, const SymCol& col, int64_t f0) {
+    dcx mu = col.K;
+    const uint32_t n = (uint32_t)sp.n[0];
+    const bool p2 = (n & (n - 1)) == 0;
+    const dcx* t = (const dcx*)sp.eph[0];
+    const uint32_t f = (uint32_t)f0;
+#pragma unroll
+    for (int o = 1; o <= kMaxR; ++o) {
+        if (o <= sp.r) {
+            uint32_t m = (uint32_t)o * f;
+            m = p2 ? (m & (n - 1)) : (m % n);
+            const dcx e = t[m];
+            const dcx ec = {e.x, -e.y};
+            mu = dsub(mu, dadd(dmul(e, col.Gp[o]), dmul(ec, col.Gm[o])));
+        }
     }
     return mu;
 }
@@ -406,11 +466,78 @@ __device__ inline double power_real(double mu, int64_t T) {
 }
 
 // lambda^T * scale for a mode, from its per-column part and axis-0 frequency.
-__device__ __forceinline__ dcx symbol_power_at(const SymParams& sp, const dcx* G, dcx K, int64_t f0) {
-    const dcx mu = symbol_mu(sp, G, K, f0);
+__device__ __forceinline__ dcx symbol_power_at(const SymParams& sp, const SymCol& col, int64_t f0) {
+    const dcx mu = symbol_mu(sp, col, f0);
     if (sp.real_sym) return dcx{power_real(mu.x, sp.T) * sp.scale, 0.0};
     const dcx v = power_complex(mu, sp.T);
     return dcx{v.x * sp.scale, v.y * sp.scale};
+}
+
+
+// Branch-free form for the solver's middle passes: the deviations of the running
+// square (1 - lambda^(2^k)) and of the product are updated for N modes at once
+// (independent chains for instruction-level parallelism) over the bits of T,
+// which are the same for every lane.  This keeps lambda^T within a few ulps of
+// absolute error for every mode (relative accuracy near lambda = 1, where the
+// surviving modes are); a mode that decays to a tiny value only loses relative
+// accuracy of that tiny value.
+template <int N>
+__device__ __forceinline__ void power_real_dev(double* mu, double* out, int64_t T) {
+    double v[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) v[e] = 0.0;
+    for (int64_t R = T; R > 0; R >>= 1) {
+        if (R & 1) {
+#pragma unroll
+            for (int e = 0; e < N; ++e) v[e] = fma(-v[e], mu[e], v[e] + mu[e]);
+        }
+        if (R > 1) {
+#pragma unroll
+            for (int e = 0; e < N; ++e) mu[e] = fma(-mu[e], mu[e], 2.0 * mu[e]);
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < N; ++e) out[e] = 1.0 - v[e];
+}
+
+template <int N>
+__device__ __forceinline__ void power_complex_dev(dcx* mu, dcx* out, int64_t T) {
+    dcx v[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) v[e] = dcx{0.0, 0.0};
+    for (int64_t R = T; R > 0; R >>= 1) {
+        if (R & 1) {
+#pragma unroll
+            for (int e = 0; e < N; ++e) v[e] = dsub(dadd(v[e], mu[e]), dmul(v[e], mu[e]));
+        }
+        if (R > 1) {
+#pragma unroll
+            for (int e = 0; e < N; ++e) mu[e] = dsub(dcx{2.0 * mu[e].x, 2.0 * mu[e].y}, dmul(mu[e], mu[e]));
+        }
+    }
+#pragma unroll
+    for (int e = 0; e < N; ++e) out[e] = dcx{1.0 - v[e].x, -v[e].y};
+}
+
+// lambda^T * scale for N modes of one column at axis-0 frequencies f0[e].
+template <int N>
+__device__ __forceinline__ void symbol_power_n(const SymParams& sp, const SymCol& col, const int64_t* f0, dcx* out) {
+    dcx mu[N];
+#pragma unroll
+    for (int e = 0; e < N; ++e) mu[e] = symbol_mu(sp, col, f0[e]);
+    if (sp.real_sym) {
+        double m[N], o[N];
+#pragma unroll
+        for (int e = 0; e < N; ++e) m[e] = mu[e].x;
+        power_real_dev<N>(m, o, sp.T);
+#pragma unroll
+        for (int e = 0; e < N; ++e) out[e] = dcx{o[e] * sp.scale, 0.0};
+    } else {
+        dcx o[N];
+        power_complex_dev<N>(mu, o, sp.T);
+#pragma unroll
+        for (int e = 0; e < N; ++e) out[e] = dcx{o[e].x * sp.scale, o[e].y * sp.scale};
+    }
 }
 
 }  // namespace sfft

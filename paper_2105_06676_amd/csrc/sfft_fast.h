@@ -1,0 +1,19 @@
+// Power-of-two fast pass kernels (sfft_fast.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sfft_types.h"
+
+namespace sfft {
+
+// fast row pass kinds (PassDesc::fast_kind)
+enum FastRowKind { ROW_R2C = 0, ROW_C2R = 1, ROW_MIDR = 2, ROW_MIDC = 3 };
+
+constexpr int kFastMinL = 16;
+constexpr int kFastMaxRowL = 4096;   // 256 threads x 16 points
+constexpr int kFastMaxColL = 1024;   // at least 4 columns per tile
+
+hipError_t launch_fast_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t lds, hipStream_t st);
+
+}  // namespace sfft

@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "sfft_device.h"
+#include "sfft_fast.h"
 #include "sfft_kernels.h"
 
 namespace sfft {
@@ -159,15 +160,14 @@ __global__ __launch_bounds__(kThreads) void k_row(PassDesc pd, SymParams sp) {
     }
     if (pd.mode == MODE_MID) {
         // 1-D problems: axis 0 is the only axis, G[o] = c[o], K = 1 - sum c.
-        dcx G[2 * kMaxR + 1];
-        for (int o = 0; o < 2 * sp.r + 1; ++o) G[o] = dcx{sp.c[o], 0.0};
-        const dcx K = {sp.one_minus_sum, 0.0};
+        const SymCol col = symbol_column_1d(sp);
         const int cnt = half ? L + 1 : L;
         for (int e = threadIdx.x; e < nrows * cnt; e += kThreads) {
             const int rr = e / cnt, k = e - rr * cnt;
             const int64_t p0 = ((row0 + rr) % pd.q_mod) * L + k;
             const int64_t f0 = pos_to_freq(sp, 0, p0);
-            const dcx v = symbol_power_at(sp, G, K, f0);
+            dcx v;
+            symbol_power_n<1>(sp, col, &f0, &v);
             cx<R>& x = lds[rr * LS + k];
             x = cmul(x, cx<R>{R(v.x), R(v.y)});
         }
@@ -247,8 +247,7 @@ __global__ __launch_bounds__(kThreads) void k_col(PassDesc pd, SymParams sp) {
     if (pd.mode != MODE_INV) tile_fft<R, false, true>(lds, pd, W, 1, W);
 
     if (pd.mode == MODE_MID) {
-        __shared__ dcx Gs[64][2 * kMaxR + 1];
-        __shared__ dcx Ks[64];
+        __shared__ SymCol Cs[64];
         __shared__ int Vs[64];
         // per-column part of the symbol (axes 1..d-1 fixed along a column)
         for (int cc = threadIdx.x; cc < W; cc += kThreads) {
@@ -264,9 +263,7 @@ __global__ __launch_bounds__(kThreads) void k_col(PassDesc pd, SymParams sp) {
                     f[a] = pos_to_freq(sp, a, p);
                 }
             }
-            dcx K;
-            symbol_column(sp, f, Gs[cc], &K);
-            Ks[cc] = K;
+            Cs[cc] = symbol_column(sp, f);
             Vs[cc] = valid;
         }
         __syncthreads();
@@ -275,7 +272,8 @@ __global__ __launch_bounds__(kThreads) void k_col(PassDesc pd, SymParams sp) {
             const int k = e / W, cc = e - k * W;
             if (!Vs[cc]) continue;
             const int64_t f0 = pos_to_freq(sp, 0, qpre + k);
-            const dcx v = symbol_power_at(sp, Gs[cc], Ks[cc], f0);
+            dcx v;
+            symbol_power_n<1>(sp, Cs[cc], &f0, &v);
             cx<R>& x = lds[k * W + cc];
             x = cmul(x, cx<R>{R(v.x), R(v.y)});
         }
@@ -327,6 +325,21 @@ __global__ void k_phase_table(double2* E, int64_t n) {
     E[m] = make_double2(-2.0 * h * h, s);
 }
 
+// Per-column symbol parts for the middle pass: column c = position in the
+// spectrum buffer over axes 1..d-1 (row-major, last axis padded).
+__global__ void k_symbol_columns(SymCol* tab, SymParams sp, int64_t total) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= total) return;
+    int64_t f[3] = {0, 0, 0};
+    int64_t rem = c;
+    for (int a = sp.d - 1; a >= 1; --a) {
+        const int64_t q = rem / sp.sdim[a];
+        f[a] = pos_to_freq(sp, a, rem - q * sp.sdim[a]);
+        rem = q;
+    }
+    tab[c] = symbol_column(sp, f);
+}
+
 // lambda(k)^T in natural order over the full spectrum (row-major k).
 __global__ void k_symbol_power(double2* out, SymParams sp, int64_t total) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -338,10 +351,8 @@ __global__ void k_symbol_power(double2* out, SymParams sp, int64_t total) {
         f[a] = rem - q * sp.n[a];
         rem = q;
     }
-    dcx G[2 * kMaxR + 1];
-    dcx K;
-    symbol_column(sp, f, G, &K);
-    const dcx v = symbol_power_at(sp, G, K, f[0]);
+    const SymCol col = symbol_column(sp, f);
+    const dcx v = symbol_power_at(sp, col, f[0]);
     out[idx] = make_double2(v.x, v.y);
 }
 
@@ -358,6 +369,7 @@ static hipError_t launch_pass_t(const PassDesc& pd, const SymParams& sp, size_t 
 }
 
 hipError_t launch_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t lds, hipStream_t st) {
+    if (pd.fast) return launch_fast_pass(pd, sp, f64, lds, st);
     return f64 ? launch_pass_t<double>(pd, sp, lds, st) : launch_pass_t<float>(pd, sp, lds, st);
 }
 
@@ -379,6 +391,15 @@ hipError_t launch_twiddle_table(double2* t64, float2* t32, int64_t N, int64_t co
 hipError_t launch_phase_table(double2* E, int64_t n, hipStream_t st) {
     const int bs = 256;
     hipLaunchKernelGGL(k_phase_table, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, E, n);
+    return hipGetLastError();
+}
+
+size_t symbol_column_bytes() { return sizeof(SymCol); }
+
+hipError_t launch_symbol_columns(void* tab, const SymParams& sp, int64_t total, hipStream_t st) {
+    const int bs = 64;
+    hipLaunchKernelGGL(k_symbol_columns, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, (SymCol*)tab, sp,
+                       total);
     return hipGetLastError();
 }
 

@@ -12,6 +12,8 @@
 // forward output stays in digit-reversed order (no transposes).
 #include "sfft_plan.h"
 
+#include "sfft_fast.h"
+
 #include <algorithm>
 #include <cstring>
 #include <sstream>
@@ -76,6 +78,19 @@ static bool split_axis(int64_t n, int64_t cap, std::vector<int64_t>* out) {
     return true;
 }
 
+static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+static int ilog2(int64_t x) {
+    int l = 0;
+    while ((int64_t(1) << l) < x) ++l;
+    return l;
+}
+
+static void two_level(int64_t N, TwiddleReq* lo, TwiddleReq* hi) {
+    *lo = {N, 64, 1};
+    *hi = {N, std::max<int64_t>(1, N / 64), 64};
+}
+
 static int64_t pow2_floor(int64_t x) {
     int64_t p = 1;
     while (p * 2 <= x) p *= 2;
@@ -120,6 +135,24 @@ static PassPlan make_row(const Ctx& c, int64_t rows, int L, int rowtrans, int mo
         pd.st_mul = 1;
     }
     p.lds_bytes = (size_t)W * pd.lds_stride * c.csz;
+    const bool fast_ok = (rowtrans == RT_HALF || rowtrans == RT_C2C) && is_pow2(L) && L >= kFastMinL &&
+                         L <= kFastMaxRowL && !tunables().no_fast;
+    if (fast_ok) {
+        pd.fast = 1;
+        pd.logL = ilog2(L);
+        const int64_t ntr = kFastMaxRowL / L;
+        pd.W = (int)ntr;
+        pd.ntiles = (rows + ntr - 1) / ntr;
+        pd.lds_stride = L + L / 16 + 2;
+        p.lds_bytes = (size_t)ntr * pd.lds_stride * c.csz;
+        p.has_fast = true;
+        two_level(L, &p.f_lo, &p.f_hi);
+        if (rowtrans == RT_HALF) {
+            p.has_half = true;
+            two_level(2 * (int64_t)L, &p.h_lo, &p.h_hi);
+        }
+        pd.fast_kind = rowtrans == RT_C2C ? ROW_MIDC : mode == MODE_FWD ? ROW_R2C : mode == MODE_INV ? ROW_C2R : ROW_MIDR;
+    }
     return p;
 }
 
@@ -149,12 +182,24 @@ static PassPlan make_col(const Ctx& c, int64_t outer, int L, int64_t inner, int 
         pd.tw = 1;
         pd.tw_n = tw_n;
         pd.tw_div = tw_div;
-        pd.tw_B = (int)std::min<int64_t>(tw_n, 1024);
+        pd.tw_B = kTwSplit;
         p.has_tw = true;
-        p.tw_lo = {tw_n, pd.tw_B, 1};
-        p.tw_hi = {tw_n, (tw_n + pd.tw_B - 1) / pd.tw_B, pd.tw_B};
+        p.tw_lo = {tw_n, kTwSplit, 1};
+        p.tw_hi = {tw_n, (tw_n + kTwSplit - 1) / kTwSplit, kTwSplit};
     }
     p.lds_bytes = (size_t)L * W * c.csz;
+    if (is_pow2(L) && L >= kFastMinL && L <= kFastMaxColL && !tunables().no_fast) {
+        pd.fast = 1;
+        pd.logL = ilog2(L);
+        const int64_t Wf = kFastMaxRowL / L;
+        pd.W = (int)Wf;
+        pd.tiles_inner = (inner + Wf - 1) / Wf;
+        pd.ntiles = outer * pd.tiles_inner;
+        pd.xcd_remap = 1;
+        p.lds_bytes = (size_t)L * (Wf + 1) * c.csz;
+        p.has_fast = true;
+        two_level(L, &p.f_lo, &p.f_hi);
+    }
     return p;
 }
 
@@ -182,7 +227,7 @@ int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* S,
     }
     Ctx c{f64, f64 ? 8 : 4, f64 ? 16 : 8, f64 ? 4096 : 8192};
     const int64_t col_max = tunables().col_max ? tunables().col_max : 512;
-    const int64_t row_max = f64 ? 4096 : 8192;   // complex points of a row middle pass
+    const int64_t row_max = 4096;                // complex points of a row middle pass
     const int64_t row_single = 8192;             // complex points of one LDS row (any pass)
     SymParams& sp = S->sym;
     std::memset(&sp, 0, sizeof(sp));
@@ -345,7 +390,7 @@ std::string describe_schedule(const Schedule& s) {
         o << (i ? ", " : "") << "{\"name\": \"" << p.name << "\", \"kind\": \""
           << (pd.kind == PASS_ROW ? "row" : "col") << "\", \"mode\": \""
           << (pd.mode == MODE_FWD ? "fwd" : pd.mode == MODE_INV ? "inv" : "mid") << "\", \"L\": " << pd.L
-          << ", \"W\": " << pd.W << ", \"outer\": " << pd.outer << ", \"inner\": " << pd.inner
+          << ", \"fast\": " << pd.fast << ", \"W\": " << pd.W << ", \"outer\": " << pd.outer << ", \"inner\": " << pd.inner
           << ", \"tiles\": " << pd.ntiles << ", \"twiddle\": " << pd.tw << ", \"lds_bytes\": " << p.lds_bytes
           << ", \"model_bytes\": " << p.model_bytes << ", \"radices\": [";
         for (int k = 0; k < pd.nst; ++k) o << (k ? ", " : "") << pd.radix[k];

@@ -25,6 +25,10 @@ struct PassPlan {
     TwiddleReq stage_tab;     // stage twiddles
     bool has_tw = false;
     TwiddleReq tw_lo, tw_hi;  // split twiddles
+    bool has_fast = false;    // power-of-two kernels: two-level tables of exp(-2 pi i m / L)
+    TwiddleReq f_lo, f_hi;
+    bool has_half = false;    // ... and of exp(-2 pi i m / 2L) for real rows
+    TwiddleReq h_lo, h_hi;
     size_t lds_bytes = 0;
     int64_t model_bytes = 0;  // algorithmic HBM bytes (read + write) of one launch
     std::string name;         // kernel family for profiling
@@ -44,6 +48,7 @@ struct Schedule {
 struct Tunables {
     int col_max = 0;          // 0: default
     int aperiodic_cutoff = 0; // 0: per-shape default
+    int no_fast = 0;          // 1: generic kernels only (testing)
 };
 Tunables& tunables();
 

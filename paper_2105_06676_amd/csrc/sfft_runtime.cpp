@@ -71,7 +71,7 @@ const double2* DevCtx::phase_table(int64_t n) {
 
 std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f64) {
     std::ostringstream key;
-    key << d << ":" << B << ":" << f64 << ":" << tunables().col_max;
+    key << d << ":" << B << ":" << f64 << ":" << tunables().col_max << ":" << tunables().no_fast;
     for (int a = 0; a < d; ++a) key << ":" << dims[a];
     {
         std::lock_guard<std::mutex> g(mu);
@@ -93,6 +93,18 @@ std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f
             PassDesc pd = pp.pd;
             auto st = table(pp.stage_tab);
             pd.st_tab = f64 ? (const void*)st.first : (const void*)st.second;
+            if (pp.has_fast) {
+                auto lo = table(pp.f_lo);
+                auto hi = table(pp.f_hi);
+                pd.f_lo = f64 ? (const void*)lo.first : (const void*)lo.second;
+                pd.f_hi = f64 ? (const void*)hi.first : (const void*)hi.second;
+            }
+            if (pp.has_half) {
+                auto lo = table(pp.h_lo);
+                auto hi = table(pp.h_hi);
+                pd.h_lo = f64 ? (const void*)lo.first : (const void*)lo.second;
+                pd.h_hi = f64 ? (const void*)hi.first : (const void*)hi.second;
+            }
             if (pp.has_tw) {
                 auto lo = table(pp.tw_lo);
                 auto hi = table(pp.tw_hi);
@@ -192,8 +204,22 @@ RealView dense_view(void* ptr, int d, const int64_t* dims) {
 }
 
 void run_plan(const Plan& p, void* ws, const RealView& in, const RealView& out, const KeepRule& keep,
-              const SymParams& sym, hipStream_t st) {
+              const SymParams& sym_in, hipStream_t st) {
     const bool f64 = p.s.f64;
+    SymParams sym = sym_in;
+    if (sym.d >= 2) {
+        // per-column part of the symbol (axes 1..d-1), once per solve
+        int64_t ncol = 1;
+        for (int a = 1; a < sym.d; ++a) ncol *= sym.sdim[a];
+        void* tab = device_ctx().scratch(st, 50, (size_t)ncol * symbol_column_bytes());
+        sym.coltab = tab;
+        sym.ncol = ncol;
+        hipEvent_t ev = nullptr;
+        const bool prof = profiling();
+        if (prof) profile_launch_begin(st, &ev);
+        check_hip(launch_symbol_columns(tab, sym, ncol, st), "symbol column launch");
+        if (prof) profile_launch_end(st, ev, f64 ? "symbol_columns_f64" : "symbol_columns_f32", 0);
+    }
     for (size_t i = 0; i < p.pd.size(); ++i) {
         PassDesc pd = p.pd[i];
         pd.buf = ws;

@@ -22,6 +22,8 @@ constexpr int kMaxStages = 16;    // radix stages per sub-transform
 constexpr int kMaxCoef = 125;     // (2r+1)^d for r <= 2, d <= 3
 constexpr int kMaxR = 2;          // largest stencil radius with a fused symbol
 constexpr int kTileElems = 8192;  // complex elements one FFT tile may hold
+constexpr int kTwSplit = 1024;    // split twiddles: exp(-2 pi i e / N) = lo[e mod 1024] * hi[e div 1024]
+constexpr int kTwSplitLog = 10;
 
 enum PassKind { PASS_ROW = 0, PASS_COL = 1 };
 enum PassMode { MODE_FWD = 0, MODE_INV = 1, MODE_MID = 2 };
@@ -69,6 +71,8 @@ struct SymParams {
     int64_t sdim[3];          // spectrum buffer extents per axis (last axis padded)
     int64_t hcount;           // valid entries along the last axis (d >= 2)
     const void* eph[3];       // per-axis tables exp(2 pi i m / n_a) - 1, FP64 complex
+    const void* coltab;       // d >= 2: per-column symbol parts (SymCol) of the middle pass
+    int64_t ncol;             // entries of coltab
     double c[kMaxCoef];       // coefficients, row-major over offsets
 };
 
@@ -107,6 +111,15 @@ struct PassDesc {
     int64_t q_mod;            // mid pass: prefix digits of axis 0 = (outer or row) % q_mod
     int64_t cpitch;           // col passes: padded pitch of the last axis inside `inner`
                               // (columns with (c % cpitch) >= hcount are padding); 0 = none
+    // power-of-two fast kernels
+    int fast;                 // 1: run the register radix-16 kernels
+    int fast_kind;            // row passes: R2C / C2R / 1-D real middle / complex middle
+    int logL;
+    int xcd_remap;            // column passes: place consecutive tiles on one XCD
+    const void* f_lo;         // exp(-2 pi i m / L): m mod 64 ...
+    const void* f_hi;         // ... and 64 * (m div 64)
+    const void* h_lo;         // exp(-2 pi i m / 2L) for the real-data untangling
+    const void* h_hi;
 };
 
 }  // namespace sfft
