@@ -84,6 +84,88 @@ def time_path(sfft, torch, w, dtype: str, steps: int, warmup: int):
     return wall, lat, prof["kernels"], ok
 
 
+def serving_run(sfft, torch, reqs, rate=None, window=None, chunk=128, seed=5):
+    """Drive the continuous-batching server with the request list.  rate=None:
+    closed loop (keep `window` requests outstanding); else open-loop Poisson
+    arrivals at `rate` requests/s (the list's arrival times rescaled).  Grids are
+    filled on the device from seeded torch generators, a chunk ahead of use."""
+    import time as _t
+    srv = sfft.Server(0, 32 << 30, 64)
+    gen = torch.Generator(device="cuda")
+    ready = []
+    nxt = 0
+
+    def refill():
+        nonlocal nxt
+        out = []
+        for r in reqs[nxt:nxt + chunk]:
+            gen.manual_seed(seed * 1000003 + r.rid)
+            td = torch.float32 if r.dtype == "f32" else torch.float64
+            out.append((r, torch.rand(r.dims, generator=gen, device="cuda", dtype=td)))
+        nxt += len(out)
+        torch.cuda.synchronize()
+        ready.extend(out)
+
+    scale = None
+    if rate is not None:
+        scale = (len(reqs) / rate) / max(reqs[-1].arrival_s, 1e-9)
+    pending = {}
+    lat, cells_T, failed = [], 0.0, 0
+    t0 = _t.perf_counter()
+    i = 0
+    while i < len(reqs) or pending:
+        now = _t.perf_counter() - t0
+        while i < len(reqs):
+            if rate is not None and reqs[i].arrival_s * scale > now:
+                break
+            if rate is None and len(pending) >= window:
+                break
+            if not ready:
+                refill()
+            r, g = ready.pop(0)
+            i += 1
+            try:
+                t = srv.submit(g, r.coeffs, r.T)
+            except sfft.SfftError:
+                failed += 1
+                continue
+            pending[t] = (r, g)
+        for t in list(pending):
+            try:
+                done = srv.poll(t)
+            except sfft.SfftError:
+                failed += 1
+                del pending[t]
+                continue
+            if done:
+                a, b = srv.times(t)
+                lat.append(b - a)
+                cells_T += float(pending[t][0].cells) * pending[t][0].T
+                del pending[t]
+        _t.sleep(20e-6)
+    wall = _t.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = np.array(lat) * 1e3
+    return {"requests": len(reqs), "completed": len(lat), "failed": failed, "wall_s": wall,
+            "req_per_s": len(lat) / wall,
+            "cell_updates_per_s": cells_T / wall, "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "batches": st["batches"], "max_batch": st["max_batch"],
+            "peak_workspace_bytes": st["peak_bytes"]}
+
+
+def serving_bench(sfft, torch, count):
+    import workloads as wl
+    reqs = wl.serving_mix(count)
+    # warm the plan cache with a short closed-loop pass over every distinct shape
+    closed = serving_run(sfft, torch, reqs, rate=None, window=256)
+    mu = closed["req_per_s"]
+    openl = serving_run(sfft, torch, reqs, rate=0.7 * mu)
+    return {"workload": f"Poisson stream of {count} periodic requests: d ~ U{{1,2,3}}, cells log-uniform "
+                        "2^10..2^24 (7-smooth extents), r ~ U{1,2}, T log-uniform 1..1e5, FP32/FP64 50/50",
+            "closed_loop": closed, "open_loop_rate_req_s": 0.7 * mu, "open_loop": openl}
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
     """The FP64 loop oracle on the full-size grid for a bounded number of steps."""
     import oracle
@@ -109,6 +191,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 path")
+    ap.add_argument("--serving", type=int, default=10000, help="serving-mix requests (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -172,6 +255,7 @@ def main():
                             "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in k32.items()},
         "f64": res64,
         "cpu_baseline": None if args.no_cpu else cpu_baseline(w),
+        "serving": serving_bench(sfft, torch, args.serving) if args.serving > 0 else None,
     }
     print(json.dumps(out))
 

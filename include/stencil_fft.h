@@ -132,6 +132,20 @@ typedef struct {
 int stencil_fft_batch(const sfft_problem* probs, int n, void* stream);
 
 /*
+ * A batch of periodic problems captured once into a hipGraph and replayed with
+ * one launch (spec pattern: batched launches captured in graphs).  The
+ * graph binds the grids, coefficients and T given at creation; each replay
+ * advances every grid by its T steps again, in place.  create() plans the
+ * problems, allocates the graph's own workspace and captures the batched
+ * program; it must not be called while another capture is active on the
+ * calling thread.  Aperiodic problems are rejected (SFFT_EUNSUPPORTED).
+ */
+typedef struct sfft_graph sfft_graph;
+int stencil_fft_graph_create(const sfft_problem* probs, int n, sfft_graph** out);
+int stencil_fft_graph_launch(sfft_graph* g, void* stream);
+void stencil_fft_graph_destroy(sfft_graph* g);
+
+/*
  * Serving loop (continuous batching).  A server owns a worker thread, a set of
  * HIP streams and an HBM budget for workspace.  submit() never blocks: it
  * copies the request (coefficients included) and returns a ticket, or
@@ -156,6 +170,9 @@ int sfft_server_submit(sfft_server* s, const sfft_problem* p, uint64_t* ticket);
 int sfft_server_poll(sfft_server* s, uint64_t ticket, int* done);
 int sfft_server_wait(sfft_server* s, uint64_t ticket);
 int sfft_server_stats(sfft_server* s, char* buf, int64_t cap);
+/* Seconds since server creation at which the ticket was submitted and found
+ * complete by the worker (done_s = -1 while pending). */
+int sfft_server_ticket_times(sfft_server* s, uint64_t ticket, double* submit_s, double* done_s);
 void sfft_server_destroy(sfft_server* s);
 
 /*

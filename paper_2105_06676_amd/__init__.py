@@ -7,6 +7,7 @@ of the library.  Importing this package fails loudly when the library has not
 been built (``python -m paper_2105_06676_amd.build``); there is no CPU fallback.
 """
 from ._binding import (  # noqa: F401
+    Graph,
     SfftError,
     Server,
     aperiodic,

@@ -60,6 +60,10 @@ _srv_poll = _sig("sfft_server_poll", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes
 _srv_wait = _sig("sfft_server_wait", ctypes.c_int, [_vp, ctypes.c_uint64])
 _srv_stats = _sig("sfft_server_stats", ctypes.c_int, [_vp, ctypes.c_char_p, ctypes.c_int64])
 _srv_destroy = _sig("sfft_server_destroy", None, [_vp])
+_srv_times = _sig("sfft_server_ticket_times", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)])
+_graph_create = _sig("stencil_fft_graph_create", ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, ctypes.POINTER(_vp)])
+_graph_launch = _sig("stencil_fft_graph_launch", ctypes.c_int, [_vp, _vp])
+_graph_destroy = _sig("stencil_fft_graph_destroy", None, [_vp])
 
 
 class SfftError(RuntimeError):
@@ -184,6 +188,36 @@ def batch(problems, stream=None):
         _check(_batch(arr, len(problems), _stream(problems[0][0], stream)))
 
 
+class Graph:
+    """A batch of periodic problems captured into a hipGraph; each launch() advances
+    every bound grid by its T steps again."""
+
+    def __init__(self, problems):
+        import torch
+        self._keep = []
+        arr = (_Problem * len(problems))()
+        for i, pr in enumerate(problems):
+            arr[i] = _problem(pr[0], pr[1], pr[2], False, self._keep)
+        self._grids = [pr[0] for pr in problems]
+        self._h = _vp()
+        with torch.cuda.device(problems[0][0].device):
+            _check(_graph_create(arr, len(problems), ctypes.byref(self._h)))
+
+    def launch(self, stream=None):
+        _check(_graph_launch(self._h, _stream(self._grids[0], stream)))
+
+    def close(self):
+        if self._h:
+            _graph_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Server:
     """Continuous-batching stencil server (one per device)."""
 
@@ -210,6 +244,12 @@ class Server:
     def wait(self, ticket: int):
         _check(_srv_wait(self._h, ticket))
         self._keep.pop(ticket, None)
+
+    def times(self, ticket: int):
+        """(submit, done) in seconds since the server started; done is -1 while pending."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        _check(_srv_times(self._h, ticket, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     def stats(self) -> dict:
         buf = ctypes.create_string_buffer(1 << 16)

@@ -1,6 +1,7 @@
 // C ABI entry points (declared in include/stencil_fft.h).
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <string>
 
 #include "../../include/stencil_fft.h"
@@ -58,6 +59,8 @@ void validate(const void* ptr, int dtype, int ndim, const int64_t* dims, const d
 }  // namespace
 
 namespace sfft {
+
+int guarded_call(const std::function<void()>& f) { return guarded(f); }
 
 // Periodic solve of B dense grids of `dims` stored back to back.
 void solve_periodic_dense(void* grid, bool f64, int d, const int64_t* dims, int64_t B, const double* coeffs, int r,

@@ -15,5 +15,8 @@ constexpr int kFastMaxRowL = 4096;   // 256 threads x 16 points
 constexpr int kFastMaxColL = 1024;   // at least 4 columns per tile
 
 hipError_t launch_fast_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t lds, hipStream_t st);
+// One launch running pass `proto`'s kernel variant over a work list (device memory).
+hipError_t launch_fast_batch(const PassDesc& proto, const BatchItem* items, int n, const SymParams* syms,
+                             int64_t tiles, bool f64, size_t lds, hipStream_t st);
 
 }  // namespace sfft

@@ -202,7 +202,7 @@ __device__ __forceinline__ void apply_symbol(cx<R>* v, cx<R>* lds, const SymPara
 // Row passes
 // ---------------------------------------------------------------------------
 template <typename R, int KIND, int LOGL>
-__global__ __launch_bounds__(kThreads) void k_frow(PassDesc pd, SymParams sp) {
+__device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& sp, uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
     constexpr int L = 1 << LOGL;
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(kThreads) void k_frow(PassDesc pd, SymParams sp) {
     constexpr int LS = L + L / 16 + 2;
     const int rr = threadIdx.x / P;
     const int q = threadIdx.x % P;
-    const int64_t row = (int64_t)blockIdx.x * NTR + rr;
+    const int64_t row = (int64_t)bid * NTR + rr;
     const bool active = row < pd.outer;
     const RowIdx idx{rr * LS};
     const cx<R>* tlo = (const cx<R>*)pd.f_lo;
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kThreads) void k_frow(PassDesc pd, SymParams sp) {
 // Column passes
 // ---------------------------------------------------------------------------
 template <typename R, int MODE, int LOGL>
-__global__ __launch_bounds__(kThreads) void k_fcol(PassDesc pd, SymParams sp) {
+__device__ __forceinline__ void fcol_tile(const PassDesc& pd, const SymParams& sp, uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
     constexpr int L = 1 << LOGL;
@@ -377,7 +377,7 @@ __global__ __launch_bounds__(kThreads) void k_fcol(PassDesc pd, SymParams sp) {
     constexpr int W = kThreads / P;
     const int cl = threadIdx.x % W;
     const int q = threadIdx.x / W;
-    uint32_t tile = blockIdx.x;
+    uint32_t tile = bid;
     if (pd.xcd_remap) {
         // workgroups are dealt round-robin over the 8 XCDs; give each XCD a
         // contiguous run of tiles so neighbouring columns share its L2
@@ -450,51 +450,98 @@ __global__ __launch_bounds__(kThreads) void k_fcol(PassDesc pd, SymParams sp) {
 }
 
 // ---------------------------------------------------------------------------
-template <typename R, int LOGL>
-static void launch_row_l(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st) {
-    const dim3 g((unsigned)pd.ntiles), b(kThreads);
-    switch (pd.fast_kind) {
-        case ROW_R2C: hipLaunchKernelGGL((k_frow<R, ROW_R2C, LOGL>), g, b, lds, st, pd, sp); break;
-        case ROW_C2R: hipLaunchKernelGGL((k_frow<R, ROW_C2R, LOGL>), g, b, lds, st, pd, sp); break;
-        case ROW_MIDR: hipLaunchKernelGGL((k_frow<R, ROW_MIDR, LOGL>), g, b, lds, st, pd, sp); break;
-        default: hipLaunchKernelGGL((k_frow<R, ROW_MIDC, LOGL>), g, b, lds, st, pd, sp); break;
+// Direct launches (descriptor in kernel arguments) and batched launches (a
+// sorted work list of problems' passes that share this kernel variant).
+__device__ __forceinline__ int batch_find(const BatchItem* it, int n, uint32_t bid) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (it[mid].first <= (int64_t)bid) lo = mid;
+        else hi = mid - 1;
     }
+    return lo;
+}
+
+template <typename R, int KIND, int LOGL>
+__global__ __launch_bounds__(kThreads) void k_frow(PassDesc pd, SymParams sp) {
+    frow_tile<R, KIND, LOGL>(pd, sp, blockIdx.x);
+}
+template <typename R, int KIND, int LOGL>
+__global__ __launch_bounds__(kThreads) void k_frow_b(const BatchItem* it, int n, const SymParams* sy) {
+    const int i = batch_find(it, n, blockIdx.x);
+    frow_tile<R, KIND, LOGL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
+}
+template <typename R, int MODE, int LOGL>
+__global__ __launch_bounds__(kThreads) void k_fcol(PassDesc pd, SymParams sp) {
+    fcol_tile<R, MODE, LOGL>(pd, sp, blockIdx.x);
+}
+template <typename R, int MODE, int LOGL>
+__global__ __launch_bounds__(kThreads) void k_fcol_b(const BatchItem* it, int n, const SymParams* sy) {
+    const int i = batch_find(it, n, blockIdx.x);
+    fcol_tile<R, MODE, LOGL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
+}
+
+struct BatchArgs {
+    const BatchItem* items;
+    int n;
+    const SymParams* syms;
+    int64_t tiles;
+};
+
+template <typename R, int LOGL>
+static void launch_row_l(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st, const BatchArgs* ba) {
+    const dim3 g((unsigned)(ba ? ba->tiles : pd.ntiles)), b(kThreads);
+#define SFFT_ROW(K)                                                                               \
+    if (ba) hipLaunchKernelGGL((k_frow_b<R, K, LOGL>), g, b, lds, st, ba->items, ba->n, ba->syms); \
+    else hipLaunchKernelGGL((k_frow<R, K, LOGL>), g, b, lds, st, pd, sp);
+    switch (pd.fast_kind) {
+        case ROW_R2C: SFFT_ROW(ROW_R2C) break;
+        case ROW_C2R: SFFT_ROW(ROW_C2R) break;
+        case ROW_MIDR: SFFT_ROW(ROW_MIDR) break;
+        default: SFFT_ROW(ROW_MIDC) break;
+    }
+#undef SFFT_ROW
 }
 
 template <typename R, int LOGL>
-static void launch_col_l(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st) {
-    const dim3 g((unsigned)pd.ntiles), b(kThreads);
+static void launch_col_l(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st, const BatchArgs* ba) {
+    const dim3 g((unsigned)(ba ? ba->tiles : pd.ntiles)), b(kThreads);
+#define SFFT_COL(M)                                                                               \
+    if (ba) hipLaunchKernelGGL((k_fcol_b<R, M, LOGL>), g, b, lds, st, ba->items, ba->n, ba->syms); \
+    else hipLaunchKernelGGL((k_fcol<R, M, LOGL>), g, b, lds, st, pd, sp);
     switch (pd.mode) {
-        case MODE_FWD: hipLaunchKernelGGL((k_fcol<R, MODE_FWD, LOGL>), g, b, lds, st, pd, sp); break;
-        case MODE_INV: hipLaunchKernelGGL((k_fcol<R, MODE_INV, LOGL>), g, b, lds, st, pd, sp); break;
-        default: hipLaunchKernelGGL((k_fcol<R, MODE_MID, LOGL>), g, b, lds, st, pd, sp); break;
+        case MODE_FWD: SFFT_COL(MODE_FWD) break;
+        case MODE_INV: SFFT_COL(MODE_INV) break;
+        default: SFFT_COL(MODE_MID) break;
     }
+#undef SFFT_COL
 }
 
 template <typename R>
-static hipError_t launch_fast_t(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st) {
+static hipError_t launch_fast_t(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st,
+                                const BatchArgs* ba) {
     if (pd.kind == PASS_ROW) {
         switch (pd.logL) {
-            case 4: launch_row_l<R, 4>(pd, sp, lds, st); break;
-            case 5: launch_row_l<R, 5>(pd, sp, lds, st); break;
-            case 6: launch_row_l<R, 6>(pd, sp, lds, st); break;
-            case 7: launch_row_l<R, 7>(pd, sp, lds, st); break;
-            case 8: launch_row_l<R, 8>(pd, sp, lds, st); break;
-            case 9: launch_row_l<R, 9>(pd, sp, lds, st); break;
-            case 10: launch_row_l<R, 10>(pd, sp, lds, st); break;
-            case 11: launch_row_l<R, 11>(pd, sp, lds, st); break;
-            case 12: launch_row_l<R, 12>(pd, sp, lds, st); break;
+            case 4: launch_row_l<R, 4>(pd, sp, lds, st, ba); break;
+            case 5: launch_row_l<R, 5>(pd, sp, lds, st, ba); break;
+            case 6: launch_row_l<R, 6>(pd, sp, lds, st, ba); break;
+            case 7: launch_row_l<R, 7>(pd, sp, lds, st, ba); break;
+            case 8: launch_row_l<R, 8>(pd, sp, lds, st, ba); break;
+            case 9: launch_row_l<R, 9>(pd, sp, lds, st, ba); break;
+            case 10: launch_row_l<R, 10>(pd, sp, lds, st, ba); break;
+            case 11: launch_row_l<R, 11>(pd, sp, lds, st, ba); break;
+            case 12: launch_row_l<R, 12>(pd, sp, lds, st, ba); break;
             default: return hipErrorInvalidValue;
         }
     } else {
         switch (pd.logL) {
-            case 4: launch_col_l<R, 4>(pd, sp, lds, st); break;
-            case 5: launch_col_l<R, 5>(pd, sp, lds, st); break;
-            case 6: launch_col_l<R, 6>(pd, sp, lds, st); break;
-            case 7: launch_col_l<R, 7>(pd, sp, lds, st); break;
-            case 8: launch_col_l<R, 8>(pd, sp, lds, st); break;
-            case 9: launch_col_l<R, 9>(pd, sp, lds, st); break;
-            case 10: launch_col_l<R, 10>(pd, sp, lds, st); break;
+            case 4: launch_col_l<R, 4>(pd, sp, lds, st, ba); break;
+            case 5: launch_col_l<R, 5>(pd, sp, lds, st, ba); break;
+            case 6: launch_col_l<R, 6>(pd, sp, lds, st, ba); break;
+            case 7: launch_col_l<R, 7>(pd, sp, lds, st, ba); break;
+            case 8: launch_col_l<R, 8>(pd, sp, lds, st, ba); break;
+            case 9: launch_col_l<R, 9>(pd, sp, lds, st, ba); break;
+            case 10: launch_col_l<R, 10>(pd, sp, lds, st, ba); break;
             default: return hipErrorInvalidValue;
         }
     }
@@ -502,7 +549,14 @@ static hipError_t launch_fast_t(const PassDesc& pd, const SymParams& sp, size_t 
 }
 
 hipError_t launch_fast_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t lds, hipStream_t st) {
-    return f64 ? launch_fast_t<double>(pd, sp, lds, st) : launch_fast_t<float>(pd, sp, lds, st);
+    return f64 ? launch_fast_t<double>(pd, sp, lds, st, nullptr) : launch_fast_t<float>(pd, sp, lds, st, nullptr);
+}
+
+hipError_t launch_fast_batch(const PassDesc& proto, const BatchItem* items, int n, const SymParams* syms,
+                             int64_t tiles, bool f64, size_t lds, hipStream_t st) {
+    const BatchArgs ba{items, n, syms, tiles};
+    SymParams dummy;
+    return f64 ? launch_fast_t<double>(proto, dummy, lds, st, &ba) : launch_fast_t<float>(proto, dummy, lds, st, &ba);
 }
 
 }  // namespace sfft

@@ -9,6 +9,9 @@ namespace sfft {
 
 hipError_t launch_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t lds, hipStream_t st);
 hipError_t set_kernel_lds_limits(size_t bytes);
+// One launch running the kernel variant of `proto` over a device work list.
+hipError_t launch_pass_batch(const PassDesc& proto, const BatchItem* items, int n, const SymParams* syms,
+                             int64_t tiles, bool f64, size_t lds, hipStream_t st);
 hipError_t launch_twiddle_table(double2* t64, float2* t32, int64_t N, int64_t count, int64_t mult,
                                 hipStream_t st);
 hipError_t launch_phase_table(double2* E, int64_t n, hipStream_t st);

@@ -102,12 +102,12 @@ __device__ void c2r_tangle(cx<R>* lds, int nrows, int LS, int L, const cx<R>* ta
 }
 
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_row(PassDesc pd, SymParams sp) {
+__device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp, uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
     const int L = pd.L;
     const int LS = pd.lds_stride;
-    const int64_t row0 = (int64_t)blockIdx.x * pd.W;
+    const int64_t row0 = (int64_t)bid * pd.W;
     const int nrows = (int)imin64(pd.W, pd.outer - row0);
     const cx<R>* buf = (const cx<R>*)pd.buf;
     const R* rin = (const R*)pd.rv.ptr;
@@ -210,11 +210,11 @@ __global__ __launch_bounds__(kThreads) void k_row(PassDesc pd, SymParams sp) {
 // Column pass
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(kThreads) void k_col(PassDesc pd, SymParams sp) {
+__device__ __forceinline__ void col_tile(const PassDesc& pd, const SymParams& sp, uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
     const int L = pd.L, W = pd.W;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = bid;
     const int64_t o = tile / pd.tiles_inner;
     const int64_t c0 = (tile - o * pd.tiles_inner) * W;
     const int wc = (int)imin64(W, pd.inner - c0);
@@ -301,6 +301,36 @@ __global__ __launch_bounds__(kThreads) void k_col(PassDesc pd, SymParams sp) {
     }
 }
 
+
+__device__ __forceinline__ int batch_find_g(const BatchItem* it, int n, uint32_t bid) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (it[mid].first <= (int64_t)bid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_row(PassDesc pd, SymParams sp) {
+    row_tile<R>(pd, sp, blockIdx.x);
+}
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_row_b(const BatchItem* it, int n, const SymParams* sy) {
+    const int i = batch_find_g(it, n, blockIdx.x);
+    row_tile<R>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
+}
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_col(PassDesc pd, SymParams sp) {
+    col_tile<R>(pd, sp, blockIdx.x);
+}
+template <typename R>
+__global__ __launch_bounds__(kThreads) void k_col_b(const BatchItem* it, int n, const SymParams* sy) {
+    const int i = batch_find_g(it, n, blockIdx.x);
+    col_tile<R>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
+}
+
 // ---------------------------------------------------------------------------
 // Tables
 // ---------------------------------------------------------------------------
@@ -373,12 +403,30 @@ hipError_t launch_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t
     return f64 ? launch_pass_t<double>(pd, sp, lds, st) : launch_pass_t<float>(pd, sp, lds, st);
 }
 
+hipError_t launch_pass_batch(const PassDesc& proto, const BatchItem* items, int n, const SymParams* syms,
+                             int64_t tiles, bool f64, size_t lds, hipStream_t st) {
+    if (proto.fast) return launch_fast_batch(proto, items, n, syms, tiles, f64, lds, st);
+    const dim3 g((unsigned)tiles), b(kThreads);
+    if (proto.kind == PASS_ROW) {
+        if (f64) hipLaunchKernelGGL(k_row_b<double>, g, b, lds, st, items, n, syms);
+        else hipLaunchKernelGGL(k_row_b<float>, g, b, lds, st, items, n, syms);
+    } else {
+        if (f64) hipLaunchKernelGGL(k_col_b<double>, g, b, lds, st, items, n, syms);
+        else hipLaunchKernelGGL(k_col_b<float>, g, b, lds, st, items, n, syms);
+    }
+    return hipGetLastError();
+}
+
 hipError_t set_kernel_lds_limits(size_t bytes) {
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void*)k_row<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_row<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_col<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
     if ((e = hipFuncSetAttribute((const void*)k_col<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_row_b<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_row_b<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_col_b<float>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
+    if ((e = hipFuncSetAttribute((const void*)k_col_b<double>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes))) return e;
     return hipSuccess;
 }
 

@@ -36,6 +36,9 @@ DevCtx& device_ctx() {
         check_hip(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev),
                   "hipDeviceGetAttribute(max shared memory)");
         p->lds_max = (size_t)lds;
+        // tables are generated on a private stream and waited for on the host, so
+        // building a plan never synchronises the whole device
+        check_hip(hipStreamCreateWithFlags(&p->tstream, hipStreamNonBlocking), "hipStreamCreate(tables)");
         // Opt the FFT kernels in to the device's full LDS; the kernels with static
         // LDS leave room for it.  Not every runtime requires the opt-in, so a
         // refusal is not fatal: launches that exceed the limit fail loudly.
@@ -51,8 +54,8 @@ std::pair<double2*, float2*> DevCtx::table(const TwiddleReq& r) {
     float2* d32 = nullptr;
     check_hip(hipMalloc(&d64, sizeof(double2) * r.count), "hipMalloc(twiddles)");
     check_hip(hipMalloc(&d32, sizeof(float2) * r.count), "hipMalloc(twiddles)");
-    check_hip(launch_twiddle_table(d64, d32, r.N, r.count, r.mult, nullptr), "twiddle table");
-    check_hip(hipDeviceSynchronize(), "twiddle table");
+    check_hip(launch_twiddle_table(d64, d32, r.N, r.count, r.mult, tstream), "twiddle table");
+    check_hip(hipStreamSynchronize(tstream), "twiddle table");
     tw[r] = {d64, d32};
     return {d64, d32};
 }
@@ -63,8 +66,8 @@ const double2* DevCtx::phase_table(int64_t n) {
     if (it != eph.end()) return it->second;
     double2* E = nullptr;
     check_hip(hipMalloc(&E, sizeof(double2) * n), "hipMalloc(phase table)");
-    check_hip(launch_phase_table(E, n, nullptr), "phase table");
-    check_hip(hipDeviceSynchronize(), "phase table");
+    check_hip(launch_phase_table(E, n, tstream), "phase table");
+    check_hip(hipStreamSynchronize(tstream), "phase table");
     eph[n] = E;
     return E;
 }
@@ -249,7 +252,9 @@ bool g_prof_on = false;
 std::vector<ProfRec> g_prof;
 }  // namespace
 
-bool profiling() { return g_prof_on; }
+bool g_prof_paused = false;
+bool profiling() { return g_prof_on && !g_prof_paused; }
+void profile_pause(bool p) { g_prof_paused = p; }
 
 void profile_launch_begin(hipStream_t st, hipEvent_t* ev) {
     check_hip(hipEventCreate(ev), "hipEventCreate");

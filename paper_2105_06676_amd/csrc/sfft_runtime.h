@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <map>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
@@ -40,6 +41,7 @@ struct DevCtx {
     std::map<std::string, std::shared_ptr<Plan>> plans;
     std::map<hipStream_t, std::pair<void*, size_t>> ws;
     size_t lds_max = 0;
+    hipStream_t tstream = nullptr;   // table generation
 
     std::shared_ptr<Plan> plan(int d, const int64_t* dims, int64_t B, bool f64);
     const double2* phase_table(int64_t n);
@@ -65,6 +67,7 @@ RealView dense_view(void* ptr, int d, const int64_t* dims);
 
 // Kernel timing (HIP events on the launch stream).
 bool profiling();
+void profile_pause(bool paused);  // no events while a graph is being captured
 void profile_launch_begin(hipStream_t st, hipEvent_t* ev);
 void profile_launch_end(hipStream_t st, hipEvent_t ev0, const std::string& name, int64_t bytes);
 

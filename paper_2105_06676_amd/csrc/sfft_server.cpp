@@ -1,13 +1,402 @@
-// Batched and serving entry points -- placeholder until the batch executor lands.
-#include "../../include/stencil_fft.h"
-#include "sfft_runtime.h"
+// Serving loop: continuous batching of stencil solves on one GPU.
+//
+// submit() copies a request into a FIFO and returns a ticket.  A worker thread
+// admits requests in arrival order while a slot is free and the request's
+// workspace fits what is left of the HBM budget (one device arena allocated
+// at creation, first-fit), packs the admitted requests into one batched
+// program on a free stream, and retires a batch when its completion event has
+// fired: tickets become done, slots and arena space return.  Requests that
+// arrive while batches run therefore join the next batch, and batches on
+// different streams overlap on the device.
+#include <algorithm>
+#include <functional>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <thread>
+
+#include "sfft_batch.h"
+
+namespace sfft {
+void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
+                     hipStream_t st);
+int guarded_call(const std::function<void()>& f);
+}  // namespace sfft
+
+using namespace sfft;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+    uint64_t ticket;
+    sfft_problem p;
+    std::vector<double> coeffs;
+    size_t bytes;
+};
+
+// first-fit allocator over [0, cap)
+struct Arena {
+    size_t cap = 0;
+    std::map<size_t, size_t> free_;  // offset -> size
+    void init(size_t c) {
+        cap = c;
+        free_.clear();
+        free_[0] = c;
+    }
+    bool alloc(size_t n, size_t* off) {
+        n = (n + 255) / 256 * 256;
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const size_t rest = it->second - n;
+                const size_t o2 = it->first + n;
+                free_.erase(it);
+                if (rest) free_[o2] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t n) {
+        n = (n + 255) / 256 * 256;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+struct Flight {
+    int stream;
+    hipEvent_t done;
+    std::vector<uint64_t> tickets;
+    std::vector<std::pair<size_t, size_t>> allocs;
+};
+
+struct TicketInfo {
+    int status = 1;  // 1 pending, 0 done, < 0 error
+    double t_submit = 0, t_done = 0;
+};
+
+}  // namespace
+
+struct sfft_server {
+    int device = 0;
+    uint64_t budget = 0;
+    int max_slots = 64;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Req> queue;
+    std::map<uint64_t, TicketInfo> tickets;
+    uint64_t next_ticket = 1;
+    std::vector<hipStream_t> streams;
+    std::vector<char*> desc;
+    std::vector<size_t> desc_cap;
+    std::vector<int> stream_busy;
+    std::vector<Flight> flights;
+    char* arena_base = nullptr;
+    Arena arena;
+    size_t in_use = 0, peak_use = 0;
+    int inflight_reqs = 0;
+    uint64_t n_admitted = 0, n_completed = 0, n_batches = 0, max_batch = 0;
+    bool stop = false;
+    std::thread worker;
+    Clock::time_point t0 = Clock::now();
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+    void run();
+    void launch(int si, std::vector<Req>& reqs, std::vector<size_t>& offs);
+};
+
+void sfft_server::launch(int si, std::vector<Req>& reqs, std::vector<size_t>& offs) {
+    hipStream_t st = streams[si];
+    std::vector<ProblemRun> runs;
+    std::vector<int> which;
+    for (size_t i = 0; i < reqs.size(); ++i)
+        if (!reqs[i].p.aperiodic && reqs[i].p.T > 0) {
+            runs.push_back(prepare_periodic(reqs[i].p));
+            which.push_back((int)i);
+        }
+    if (!runs.empty()) {
+        // every admitted request owns an arena block holding its workspace and
+        // column table
+        const size_t need = batch_desc_bytes(runs);
+        if (desc_cap[si] < need) {
+            if (desc[si]) {
+                check_hip(hipStreamSynchronize(st), "hipStreamSynchronize");
+                check_hip(hipFree(desc[si]), "hipFree");
+            }
+            desc[si] = nullptr;
+            check_hip(hipMalloc(&desc[si], need), "hipMalloc(descriptors)");
+            desc_cap[si] = need;
+        }
+        BatchMem mem;
+        mem.desc = desc[si];
+        mem.desc_cap = desc_cap[si];
+        std::vector<char*> bases;
+        for (int k : which) bases.push_back(arena_base + offs[k]);
+        BatchProgram prog = build_batch(runs, mem, &bases);
+        enqueue_batch(prog, runs, mem, st, true);
+    }
+    for (auto& r : reqs)
+        if (r.p.aperiodic && r.p.T > 0)
+            solve_aperiodic(r.p.grid, r.p.dtype == SFFT_F64, r.p.ndim, r.p.dims, r.coeffs.data(), r.p.radius, r.p.T,
+                            st);
+}
+
+void sfft_server::run() {
+    (void)hipSetDevice(device);
+    std::unique_lock<std::mutex> lk(mu);
+    for (;;) {
+        // retire finished batches
+        for (size_t i = 0; i < flights.size();) {
+            Flight& f = flights[i];
+            const hipError_t q = hipEventQuery(f.done);
+            if (q == hipErrorNotReady) {
+                ++i;
+                continue;
+            }
+            const int status = q == hipSuccess ? 0 : SFFT_EHIP;
+            const double t = now();
+            for (uint64_t tk : f.tickets) {
+                auto& ti = tickets[tk];
+                ti.status = status;
+                ti.t_done = t;
+            }
+            for (auto& a : f.allocs) {
+                arena.release(a.first, a.second);
+                in_use -= (a.second + 255) / 256 * 256;
+            }
+            inflight_reqs -= (int)f.tickets.size();
+            n_completed += f.tickets.size();
+            stream_busy[f.stream] = 0;
+            (void)hipEventDestroy(f.done);
+            flights.erase(flights.begin() + i);
+            cv_done.notify_all();
+        }
+        // admit and launch
+        int si = -1;
+        for (size_t k = 0; k < streams.size(); ++k)
+            if (!stream_busy[k]) { si = (int)k; break; }
+        if (si >= 0 && !queue.empty()) {
+            std::vector<Req> adm;
+            std::vector<size_t> offs;
+            std::vector<std::pair<size_t, size_t>> allocs;
+            while (!queue.empty() && inflight_reqs + (int)adm.size() < max_slots) {
+                Req& r = queue.front();
+                size_t off = 0;
+                if (!arena.alloc(std::max<size_t>(r.bytes, 256), &off)) break;
+                in_use += (std::max<size_t>(r.bytes, 256) + 255) / 256 * 256;
+                peak_use = std::max(peak_use, in_use);
+                allocs.push_back({off, std::max<size_t>(r.bytes, 256)});
+                offs.push_back(off);
+                adm.push_back(std::move(r));
+                queue.pop_front();
+            }
+            if (!adm.empty()) {
+                Flight f;
+                f.stream = si;
+                f.allocs = allocs;
+                for (auto& r : adm) {
+                    f.tickets.push_back(r.ticket);
+                    // requests point at their own coefficient copies
+                    r.p.coeffs = r.coeffs.data();
+                }
+                stream_busy[si] = 1;
+                inflight_reqs += (int)adm.size();
+                n_admitted += adm.size();
+                n_batches += 1;
+                max_batch = std::max<uint64_t>(max_batch, adm.size());
+                lk.unlock();
+                int status = 0;
+                try {
+                    launch(si, adm, offs);
+                } catch (const Error& e) {
+                    status = e.code;
+                } catch (...) {
+                    status = SFFT_EHIP;
+                }
+                hipEvent_t ev;
+                (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                (void)hipEventRecord(ev, streams[si]);
+                lk.lock();
+                f.done = ev;
+                if (status) {
+                    // failed to enqueue: finish these tickets with the error at once
+                    (void)hipStreamSynchronize(streams[si]);
+                    for (uint64_t tk : f.tickets) {
+                        tickets[tk].status = status;
+                        tickets[tk].t_done = now();
+                    }
+                    for (auto& a : f.allocs) {
+                        arena.release(a.first, a.second);
+                        in_use -= (a.second + 255) / 256 * 256;
+                    }
+                    inflight_reqs -= (int)f.tickets.size();
+                    stream_busy[si] = 0;
+                    (void)hipEventDestroy(ev);
+                    cv_done.notify_all();
+                } else {
+                    flights.push_back(std::move(f));
+                }
+                continue;
+            }
+        }
+        if (stop && queue.empty() && flights.empty()) break;
+        cv_work.wait_for(lk, std::chrono::microseconds(flights.empty() ? 2000 : 50));
+    }
+}
 
 extern "C" {
-int stencil_fft_batch(const sfft_problem*, int, void*) { return SFFT_EUNSUPPORTED; }
-int sfft_server_create(sfft_server**, int, uint64_t, int) { return SFFT_EUNSUPPORTED; }
-int sfft_server_submit(sfft_server*, const sfft_problem*, uint64_t*) { return SFFT_EUNSUPPORTED; }
-int sfft_server_poll(sfft_server*, uint64_t, int*) { return SFFT_EUNSUPPORTED; }
-int sfft_server_wait(sfft_server*, uint64_t) { return SFFT_EUNSUPPORTED; }
-int sfft_server_stats(sfft_server*, char*, int64_t) { return SFFT_EUNSUPPORTED; }
-void sfft_server_destroy(sfft_server*) {}
+
+int sfft_server_create(sfft_server** out, int device, uint64_t hbm_budget_bytes, int max_slots) {
+    return guarded_call([&] {
+        if (!out) throw Error(SFFT_EINVAL, "out is null");
+        *out = nullptr;
+        int ndev = 0;
+        check_hip(hipGetDeviceCount(&ndev), "hipGetDeviceCount");
+        if (device < 0 || device >= ndev) throw Error(SFFT_EINVAL, "no such device");
+        std::unique_ptr<sfft_server> s(new sfft_server());
+        s->device = device;
+        s->budget = hbm_budget_bytes ? hbm_budget_bytes : (32ull << 30);
+        s->max_slots = max_slots > 0 ? max_slots : 64;
+        int prev = 0;
+        check_hip(hipGetDevice(&prev), "hipGetDevice");
+        check_hip(hipSetDevice(device), "hipSetDevice");
+        hipError_t e = hipMalloc(&s->arena_base, s->budget);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipSetDevice(prev);
+            throw Error(SFFT_ENOMEM, "HBM budget of " + std::to_string(s->budget) + " bytes: " + hipGetErrorString(e));
+        }
+        s->arena.init(s->budget);
+        const int nst = 4;
+        for (int i = 0; i < nst; ++i) {
+            hipStream_t st;
+            check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+            s->streams.push_back(st);
+            s->desc.push_back(nullptr);
+            s->desc_cap.push_back(0);
+            s->stream_busy.push_back(0);
+        }
+        (void)hipSetDevice(prev);
+        sfft_server* raw = s.get();
+        s->worker = std::thread([raw] { raw->run(); });
+        *out = s.release();
+    });
 }
+
+int sfft_server_submit(sfft_server* s, const sfft_problem* p, uint64_t* ticket) {
+    return guarded_call([&] {
+        if (!s || !p || !ticket) throw Error(SFFT_EINVAL, "null argument");
+        validate_problem(*p);
+        Req r;
+        r.p = *p;
+        int nc = 1;
+        for (int a = 0; a < p->ndim; ++a) nc *= 2 * p->radius + 1;
+        r.coeffs.assign(p->coeffs, p->coeffs + nc);
+        r.p.coeffs = r.coeffs.data();
+        if (p->aperiodic) {
+            int64_t cells = 1;
+            for (int a = 0; a < p->ndim; ++a) cells *= p->dims[a] + 2 * p->radius;
+            r.bytes = 256;  // the aperiodic path uses per-stream scratch outside the arena
+            (void)cells;
+        } else {
+            r.bytes = problem_workspace_bytes(*p);
+        }
+        if (r.bytes > s->budget) throw Error(SFFT_ENOMEM, "request workspace exceeds the server's HBM budget");
+        std::lock_guard<std::mutex> g(s->mu);
+        r.ticket = s->next_ticket++;
+        TicketInfo ti;
+        ti.t_submit = s->now();
+        s->tickets[r.ticket] = ti;
+        *ticket = r.ticket;
+        s->queue.push_back(std::move(r));
+        s->cv_work.notify_one();
+    });
+}
+
+int sfft_server_poll(sfft_server* s, uint64_t ticket, int* done) {
+    if (!s || !done) return SFFT_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return SFFT_ENOTFOUND;
+    if (it->second.status < 0) return it->second.status;
+    *done = it->second.status == 0 ? 1 : 0;
+    return SFFT_OK;
+}
+
+int sfft_server_wait(sfft_server* s, uint64_t ticket) {
+    if (!s) return SFFT_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return SFFT_ENOTFOUND;
+    s->cv_done.wait(lk, [&] { return s->tickets[ticket].status != 1; });
+    return s->tickets[ticket].status;
+}
+
+int sfft_server_ticket_times(sfft_server* s, uint64_t ticket, double* submit_s, double* done_s) {
+    if (!s || !submit_s || !done_s) return SFFT_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    auto it = s->tickets.find(ticket);
+    if (it == s->tickets.end()) return SFFT_ENOTFOUND;
+    *submit_s = it->second.t_submit;
+    *done_s = it->second.status == 1 ? -1.0 : it->second.t_done;
+    return SFFT_OK;
+}
+
+int sfft_server_stats(sfft_server* s, char* buf, int64_t cap) {
+    if (!s || !buf || cap < 1) return SFFT_EINVAL;
+    std::ostringstream o;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        o << "{\"admitted\": " << s->n_admitted << ", \"completed\": " << s->n_completed << ", \"batches\": "
+          << s->n_batches << ", \"max_batch\": " << s->max_batch << ", \"queued\": " << s->queue.size()
+          << ", \"in_flight\": " << s->inflight_reqs << ", \"budget_bytes\": " << s->budget
+          << ", \"peak_bytes\": " << s->peak_use << ", \"streams\": " << s->streams.size()
+          << ", \"max_slots\": " << s->max_slots << "}";
+    }
+    const std::string str = o.str();
+    if ((int64_t)str.size() >= cap) return SFFT_EINVAL;
+    std::memcpy(buf, str.c_str(), str.size() + 1);
+    return (int)str.size();
+}
+
+void sfft_server_destroy(sfft_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(s->device);
+    for (auto st : s->streams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    for (auto d : s->desc)
+        if (d) (void)hipFree(d);
+    if (s->arena_base) (void)hipFree(s->arena_base);
+    (void)hipSetDevice(prev);
+    delete s;
+}
+
+}  // extern "C"

@@ -122,4 +122,13 @@ struct PassDesc {
     const void* h_hi;
 };
 
+// One problem's pass inside a batched launch: workgroups [first, first + pd.ntiles)
+// of the launch run this pass with symbol parameters syms[sym].
+struct BatchItem {
+    PassDesc pd;
+    int64_t first;
+    int sym;
+    int pad_;
+};
+
 }  // namespace sfft

@@ -1,0 +1,161 @@
+"""Batched launches, graph replay and the continuous-batching server.
+
+* a batch of uneven problems (1-D/2-D/3-D, FP32/FP64, different T, periodic and
+  aperiodic) gives every problem exactly the result of solving it alone, and
+  matches the oracle;
+* a captured graph replayed several times, with eager work between replays,
+  reproduces the eager batch every time;
+* the server returns each request's result bit-identical to the request solved
+  alone, also when a tiny HBM budget forces queueing, and rejects invalid or
+  oversize requests at submit.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_util import TOL, rel_l2, rounded_input, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix(seed=7, n=14):
+    rng = np.random.default_rng(seed)
+    shapes = [(4096,), (96,), (1000,), (64, 48), (30, 42), (128, 128), (24, 20, 18), (16, 32, 8),
+              (8192,), (7, 9), (256, 100), (50, 60), (12, 12, 12), (3000,)]
+    probs = []
+    for i in range(n):
+        dims = shapes[i % len(shapes)]
+        r = 1 + (i % 2)
+        if len(dims) == 3 and r == 2 and max(dims) > 20:
+            r = 1
+        c = wl.box_random_coeffs(seed * 100 + i, len(dims), r)
+        T = int(rng.integers(1, 3000))
+        dtype = "f32" if i % 3 == 0 else "f64"
+        a = wl.uniform(seed * 100 + i, "grid", int(np.prod(dims))).reshape(dims)
+        probs.append((a, c, T, dtype))
+    return probs
+
+
+def test_batch_equals_alone_and_oracle():
+    import torch
+    import paper_2105_06676_amd as sfft
+    probs = _mix()
+    alone = []
+    for a, c, T, dt in probs:
+        g = to_dev(a, dt)
+        sfft.periodic(g, c, T)
+        alone.append(g)
+    grids = [to_dev(a, dt) for a, c, T, dt in probs]
+    sfft.batch([(g, c, T) for g, (a, c, T, dt) in zip(grids, probs)])
+    torch.cuda.synchronize()
+    for g, al, (a, c, T, dt) in zip(grids, alone, probs):
+        assert torch.equal(g, al)
+        if a.size <= 70000:
+            ref = oracle.periodic(rounded_input(a, dt), c, T)
+            assert rel_l2(g.cpu().numpy().astype(np.float64), ref) <= TOL[dt]
+
+
+def test_batch_with_aperiodic_members():
+    import torch
+    import paper_2105_06676_amd as sfft
+    c = wl.box_random_coeffs(3, 2, 1)
+    ap = wl.uniform(3, "grid", 42 * 38).reshape(42, 38)
+    pe = wl.uniform(4, "grid", 40 * 36).reshape(40, 36)
+    ga, gp = to_dev(ap, "f64"), to_dev(pe, "f64")
+    sfft.batch([(ga, c, 21, True), (gp, c, 33)])
+    torch.cuda.synchronize()
+    assert rel_l2(ga.cpu().numpy(), oracle.aperiodic(ap, c, 21)) <= 1e-12
+    assert rel_l2(gp.cpu().numpy(), oracle.periodic(pe, c, 33)) <= 1e-12
+
+
+def test_batch_rejects_invalid_member_without_running():
+    import torch
+    import paper_2105_06676_amd as sfft
+    c = wl.box_random_coeffs(3, 2, 1)
+    good = to_dev(np.ones((16, 16)), "f64")
+    bad = to_dev(np.ones((11, 16)), "f64")  # 11 is not 7-smooth
+    with pytest.raises(sfft.SfftError) as e:
+        sfft.batch([(good, c, 5), (bad, c, 5)])
+    assert "problem 1" in str(e.value)
+    torch.cuda.synchronize()
+    assert torch.equal(good, torch.ones_like(good))
+
+
+def test_graph_replays_match_eager():
+    import torch
+    import paper_2105_06676_amd as sfft
+    probs = _mix(seed=9, n=8)
+    a0 = [to_dev(a, dt) for a, c, T, dt in probs]
+    eager = [x.clone() for x in a0]
+    sfft.batch([(g, c, T) for g, (a, c, T, dt) in zip(eager, probs)])
+    grids = [x.clone() for x in a0]
+    graph = sfft.Graph([(g, c, T) for g, (a, c, T, dt) in zip(grids, probs)])
+    for rep in range(3):
+        for g, x in zip(grids, a0):
+            g.copy_(x)
+        torch.cuda.synchronize()
+        graph.launch()
+        torch.cuda.synchronize()
+        # unrelated eager work between replays
+        sfft.periodic(to_dev(np.ones((32, 32)), "f32"), wl.jacobi5_coeffs(), 3)
+        for g, e in zip(grids, eager):
+            assert torch.equal(g, e), rep
+    graph.close()
+
+
+def _serve(probs, budget=0, slots=0):
+    import torch
+    import paper_2105_06676_amd as sfft
+    srv = sfft.Server(0, budget, slots)
+    grids = [to_dev(a, dt) for a, c, T, dt in probs]
+    torch.cuda.synchronize()
+    tickets = [srv.submit(g, c, T) for g, (a, c, T, dt) in zip(grids, probs)]
+    for t in tickets:
+        srv.wait(t)
+    stats = srv.stats()
+    times = [srv.times(t) for t in tickets]
+    srv.close()
+    return grids, stats, times
+
+
+def test_server_results_equal_alone():
+    import torch
+    import paper_2105_06676_amd as sfft
+    probs = _mix(seed=11, n=24)
+    grids, stats, times = _serve(probs)
+    assert stats["completed"] == len(probs)
+    for g, (a, c, T, dt) in zip(grids, probs):
+        al = to_dev(a, dt)
+        sfft.periodic(al, c, T)
+        torch.cuda.synchronize()
+        assert torch.equal(g, al)
+    assert all(d >= s >= 0 for s, d in times)
+
+
+def test_server_tiny_budget_forces_queueing():
+    import torch
+    import paper_2105_06676_amd as sfft
+    probs = _mix(seed=12, n=10)
+    # a budget that holds about one of the larger requests at a time
+    grids, stats, _ = _serve(probs, budget=4 << 20, slots=2)
+    assert stats["completed"] == len(probs)
+    assert stats["batches"] >= len(probs) // 2
+    assert stats["peak_bytes"] <= 4 << 20
+    for g, (a, c, T, dt) in zip(grids, probs):
+        al = to_dev(a, dt)
+        sfft.periodic(al, c, T)
+        torch.cuda.synchronize()
+        assert torch.equal(g, al)
+
+
+def test_server_rejects_bad_requests():
+    import paper_2105_06676_amd as sfft
+    srv = sfft.Server(0, 1 << 20, 4)
+    c = wl.jacobi5_coeffs()
+    with pytest.raises(sfft.SfftError):
+        srv.submit(to_dev(np.ones((13, 16)), "f32"), c, 5)  # not 7-smooth
+    with pytest.raises(sfft.SfftError) as e:
+        srv.submit(to_dev(np.ones((1024, 1024)), "f64"), c, 5)  # workspace above the budget
+    assert e.value.code == -3
+    srv.close()

@@ -225,16 +225,36 @@ def _is_7smooth(n: int) -> bool:
     return n == 1
 
 
+_SMOOTH = None
+
+
+def _smooth_numbers(limit: int = 1 << 26):
+    global _SMOOTH
+    if _SMOOTH is None:
+        out = []
+        p2 = 1
+        while p2 <= limit:
+            p3 = p2
+            while p3 <= limit:
+                p5 = p3
+                while p5 <= limit:
+                    p7 = p5
+                    while p7 <= limit:
+                        out.append(p7)
+                        p7 *= 7
+                    p5 *= 5
+                p3 *= 3
+            p2 *= 2
+        _SMOOTH = np.array(sorted(out), dtype=np.float64)
+    return _SMOOTH
+
+
 def nearest_7smooth(x: float) -> int:
-    best, bd = 1, float("inf")
-    lo = max(1, int(math.floor(x * 0.7)))
-    hi = int(math.ceil(x * 1.3)) + 1
-    for n in range(lo, hi + 1):
-        if _is_7smooth(n):
-            d = abs(math.log(n) - math.log(x))
-            if d < bd:
-                best, bd = n, d
-    return best
+    """The 7-smooth integer closest to x in log distance."""
+    sm = _smooth_numbers()
+    j = int(np.searchsorted(sm, x))
+    cands = [sm[k] for k in (j - 1, j) if 0 <= k < len(sm)]
+    return int(min(cands, key=lambda v: abs(math.log(v) - math.log(x))))
 
 
 @dataclass
