@@ -166,6 +166,28 @@ def serving_bench(sfft, torch, count):
             "closed_loop": closed, "open_loop_rate_req_s": 0.7 * mu, "open_loop": openl}
 
 
+def copy_reference(torch, nbytes: int, reps: int = 10):
+    """Device-to-device copy bandwidth (read + write bytes / time) of a plain
+    elementwise copy of `nbytes`, the practical HBM ceiling the passes are
+    compared with."""
+    n = nbytes // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * nbytes, "avg_us": ms * 1e3, "GBps": 2 * nbytes / (ms * 1e-3) / 1e9}
+
+
 def cpu_baseline(w, budget_s: float = 12.0):
     """The FP64 loop oracle on the full-size grid for a bounded number of steps."""
     import oracle
@@ -192,6 +214,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 path")
     ap.add_argument("--serving", type=int, default=10000, help="serving-mix requests (0 = skip)")
+    ap.add_argument("--no-copy", action="store_true", help="skip the device-copy bandwidth reference")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -203,7 +226,7 @@ def main():
     import paper_2105_06676_amd as sfft
     import workloads as wl
 
-    w = wl.config("C2")
+    w = wl.config("jacobi2d_8192")
     N = int(np.prod(w.dims))
     wall32, lat32, k32, ok32 = time_path(sfft, torch, w, "f32", args.steps, args.warmup)
     ms32 = wall32 * 1e3 / args.steps
@@ -254,6 +277,7 @@ def main():
         "kernels_f32": {k: {"avg_us": v["ms"] * 1e3 / v["launches"], "launches": v["launches"],
                             "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in k32.items()},
         "f64": res64,
+        "copy_reference": None if args.no_copy else copy_reference(torch, N * 4 * 2),
         "cpu_baseline": None if args.no_cpu else cpu_baseline(w),
         "serving": serving_bench(sfft, torch, args.serving) if args.serving > 0 else None,
     }

@@ -133,7 +133,7 @@ int stencil_fft_batch(const sfft_problem* probs, int n, void* stream);
 
 /*
  * A batch of periodic problems captured once into a hipGraph and replayed with
- * one launch (spec pattern: batched launches captured in graphs).  The
+ * one launch.  The
  * graph binds the grids, coefficients and T given at creation; each replay
  * advances every grid by its T steps again, in place.  create() plans the
  * problems, allocates the graph's own workspace and captures the batched

@@ -91,10 +91,10 @@ def test_aperiodic_interior_matches_periodic_far_cells():
 
 @pytest.mark.slow
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_C4_reduced_sizes(dtype):
-    """The C4 stencil (9-point box, r = 1) on 512^2 with T = 512 (the band covers the
+def test_box2d_aperiodic_reduced_sizes(dtype):
+    """The 4096^2 aperiodic workload's stencil (9-point box, r = 1) on 512^2 with T = 512 (the band covers the
     whole grid) and 1024^2 with T = 128, against the full aperiodic oracle."""
-    w = wl.config("C4")
+    w = wl.config("box2d_aperiodic_4096")
     for n, T in ((512, 512), (1024, 128)):
         store = (n + 2, n + 2)
         a = wl.uniform(w.seed, "grid", store[0] * store[1]).reshape(store)
@@ -105,12 +105,12 @@ def test_C4_reduced_sizes(dtype):
 
 @pytest.mark.slow
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_C4_full_size_sampled(dtype):
+def test_box2d_aperiodic_4096_full_size_sampled(dtype):
     """Full 4096^2, T = 512: cells near two corners and a far interior block are
     checked against the oracle run on sub-boxes of the stored array that contain
     each cell's whole r*T dependency cone (cells whose cone stays inside a box do
     not see the box's cut edges; Sec. 4)."""
-    w = wl.config("C4")
+    w = wl.config("box2d_aperiodic_4096")
     a = w.grid()
     got = gpu_aperiodic(a, w.coeffs, w.T, dtype)
     src = rounded_input(a, dtype)

@@ -95,9 +95,9 @@ def test_pure_shift_large_T():
     np.testing.assert_allclose(got, np.roll(a0, -(T % n)), atol=T * 4e-16)
 
 
-def test_single_mode_full_C2_size():
+def test_single_mode_full_jacobi2d_8192():
     """cos mode k of the 8192^2 Jacobi grid scales by exactly lambda(k)^T (symmetric stencil)."""
-    w = wl.config("C2")
+    w = wl.config("jacobi2d_8192")
     n0, n1 = w.dims
     k0, k1 = 3, 5
     m0 = np.arange(n0)[:, None]
@@ -145,8 +145,8 @@ def test_symbol_power_matches_definition():
 
 
 @pytest.mark.slow
-def test_C1_full_against_oracle_and_binomial():
-    w = wl.config("C1")
+def test_heat1d_65536_full_against_oracle_and_binomial():
+    w = wl.config("heat1d_65536")
     a0 = w.grid()
     got = gpu_periodic(a0, w.coeffs, w.T, "f64")
     ref = oracle.periodic(a0, w.coeffs, w.T)
@@ -162,20 +162,20 @@ def test_C1_full_against_oracle_and_binomial():
 
 @pytest.mark.slow
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_C2_crop_instance(dtype):
-    """The 256x256 periodic instance with the C2 stencil and T, initial data = the
+def test_jacobi2d_crop_instance(dtype):
+    """The 256x256 periodic instance with the 8192^2 Jacobi workload's stencil and T, initial data = the
     top-left crop of the seeded 8192^2 grid."""
-    w = wl.config("C2")
+    w = wl.config("jacobi2d_8192")
     a0 = wl.crop_grid(w, 256)
     ref = oracle.periodic(rounded_input(a0, dtype), w.coeffs, w.T)
     assert rel_l2(gpu_periodic(a0, w.coeffs, w.T, dtype), ref) <= TOL[dtype]
 
 
 @pytest.mark.slow
-def test_C2_full_invariants():
+def test_jacobi2d_8192_full_invariants():
     """Full 8192^2, T = 4096: the sum is conserved (coefficients sum to 1 up to the
     rounding of 0.2) and the FP32 path agrees with the FP64 path."""
-    w = wl.config("C2")
+    w = wl.config("jacobi2d_8192")
     a0 = w.grid()
     g64 = gpu_periodic(a0, w.coeffs, w.T, "f64")
     g32 = gpu_periodic(a0, w.coeffs, w.T, "f32")
@@ -185,8 +185,8 @@ def test_C2_full_invariants():
 
 
 @pytest.mark.slow
-def test_C3_instance_and_full_size():
-    w = wl.config("C3")
+def test_star3d_instance_and_full_size():
+    w = wl.config("star3d_512")
     a0 = wl.crop_grid(w, 64)
     ref = oracle.periodic(rounded_input(a0, "f32"), w.coeffs, w.T)
     assert rel_l2(gpu_periodic(a0, w.coeffs, w.T, "f32"), ref) <= TOL["f32"]

@@ -33,7 +33,7 @@ def _printed_matrix():
     return rows
 
 
-# ---------------------------------------------------------------- P1 / P2 -----
+# ---------------------------------------------------------------------------
 
 def test_printed_matrix_columns():
     """S e_j from the loop equals column j of the printed matrix (orientation pin)."""
@@ -82,7 +82,7 @@ def test_symbol_is_eigenvalues_of_printed_matrix():
     assert abs(lam[2]) < 1e-15
 
 
-# ---------------------------------------------------------------- P7 ----------
+# ---------------------------------------------------------------------------
 
 def _dense_periodic(c_int, dims):
     """Dense integer matrix of one periodic step (weights scaled by the common denominator)."""
@@ -166,7 +166,7 @@ def test_exact_affine_power_aperiodic(dims, T):
     assert np.array_equal(got, expect)
 
 
-# ---------------------------------------------------------------- P3 ----------
+# ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("n,k,T", [(64, 3, 100), (50, 7, 37), (128, 1, 1000)])
 def test_single_cosine_mode_heat(n, k, T):
@@ -193,7 +193,7 @@ def test_single_mode_asymmetric_2d():
     np.testing.assert_allclose(got, np.real(lam ** T * np.exp(1j * phase)), atol=1e-13)
 
 
-# ---------------------------------------------------------------- P4 / P5 / P6 / P9 / P10
+# ---------------------------------------------------------------------------
 
 def test_conservation():
     c = workloads.box_random_coeffs(9, 2, 2)
@@ -204,10 +204,10 @@ def test_conservation():
 
 
 @pytest.mark.slow
-def test_binomial_closed_form_full_C1():
+def test_binomial_closed_form_full_heat1d():
     """(1/4, 1/2, 1/4)^{*T} is Binomial(2T, 1/2): a_T[n] = sum_m C(2T, m) 4^-T a_0[(n + m - T) mod N],
     weights computed as exact integers over 4^T and rounded once (textbook identity)."""
-    w = workloads.config("C1")
+    w = workloads.config("heat1d_65536")
     a0 = w.grid()
     T = w.T
     N = a0.shape[0]
@@ -270,7 +270,7 @@ def test_tiny_extent_aliasing():
     np.testing.assert_allclose(oracle.periodic(a0, c, 1), expect, rtol=1e-15)
 
 
-# ---------------------------------------------------------------- P12 / P13 ---
+# ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("dims,r,T", [((40,), 1, 9), ((30, 26), 1, 6), ((24, 20), 2, 3), ((14, 12, 16), 1, 3)])
 def test_aperiodic_interior_matches_periodic(dims, r, T):

@@ -25,12 +25,12 @@ def test_gaussian_moments():
 def test_coefficients_sum_exactly_one():
     for c in (w.star7_random_coeffs(3), w.box_random_coeffs(4, 2, 1), w.box_random_coeffs(7, 3, 2)):
         assert c.sum() == 1.0 and (c >= 0).all()
-    c3 = w.config("C3").coeffs
+    c3 = w.config("star3d_512").coeffs
     assert c3[1, 1, 1] >= 0.4 and np.count_nonzero(c3) == 7
 
 
 def test_crop_matches_full_grid():
-    for name, side in (("C2", 8), ("C3", 2)):
+    for name, side in (("jacobi2d_8192", 8), ("star3d_512", 2)):
         cfg = w.config(name)
         small = w.Workload(cfg.name, cfg.ndim, (side * 3,) * cfg.ndim, cfg.radius, cfg.T,
                            cfg.coeffs, cfg.seed, cfg.init)

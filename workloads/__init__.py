@@ -169,17 +169,17 @@ def box_random_coeffs(seed: int, ndim: int, r: int, purpose: str = "coef") -> np
 
 def config(name: str) -> Workload:
     """The five named workloads at full size."""
-    if name == "C1":
-        return Workload("C1", 1, (65536,), 1, 1024, heat1d_coeffs(), 1, "uniform",
+    if name == "heat1d_65536":
+        return Workload("heat1d_65536", 1, (65536,), 1, 1024, heat1d_coeffs(), 1, "uniform",
                         dtypes=("f64",), notes="1-D periodic 3-point heat")
-    if name == "C2":
-        return Workload("C2", 2, (8192, 8192), 1, 4096, jacobi5_coeffs(), 2, "uniform",
+    if name == "jacobi2d_8192":
+        return Workload("jacobi2d_8192", 2, (8192, 8192), 1, 4096, jacobi5_coeffs(), 2, "uniform",
                         dtypes=("f32", "f64"), notes="2-D periodic 5-point Jacobi")
-    if name == "C3":
-        return Workload("C3", 3, (512, 512, 512), 1, 1000, star7_random_coeffs(3), 3,
+    if name == "star3d_512":
+        return Workload("star3d_512", 3, (512, 512, 512), 1, 1000, star7_random_coeffs(3), 3,
                         "gaussian", dtypes=("f32",), notes="3-D periodic random 7-point star")
-    if name == "C4":
-        return Workload("C4", 2, (4096, 4096), 1, 512, box_random_coeffs(4, 2, 1), 4,
+    if name == "box2d_aperiodic_4096":
+        return Workload("box2d_aperiodic_4096", 2, (4096, 4096), 1, 512, box_random_coeffs(4, 2, 1), 4,
                         "uniform", aperiodic=True, dtypes=("f64", "f32"),
                         notes="2-D aperiodic 9-point box, fixed frame")
     raise KeyError(name)
