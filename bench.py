@@ -166,6 +166,43 @@ def serving_bench(sfft, torch, count):
             "closed_loop": closed, "open_loop_rate_req_s": 0.7 * mu, "open_loop": openl}
 
 
+def time_solve(sfft, torch, w, dtype, reps=5, warmup=1):
+    """Median device time of one solve of workload w (inputs resident in HBM)."""
+    td = torch.float32 if dtype == "f32" else torch.float64
+    grid0 = torch.from_numpy(w.grid()).to(device="cuda:0", dtype=td)
+    grid = grid0.clone()
+    fn = sfft.aperiodic if w.aperiodic else sfft.periodic
+    for _ in range(warmup):
+        fn(grid, w.coeffs, w.T)
+    ts = []
+    for _ in range(reps):
+        grid.copy_(grid0)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        fn(grid, w.coeffs, w.T)
+        b.record()
+        torch.cuda.synchronize()
+        ts.append(a.elapsed_time(b))
+    ms = float(np.median(ts))
+    cells = int(np.prod(w.dims))
+    del grid, grid0
+    torch.cuda.empty_cache()
+    return {"ms": ms, "cell_updates_per_s": cells * w.T / (ms * 1e-3)}
+
+
+def other_workloads(sfft, torch):
+    """The other workloads of the method, timed the same way (context for the headline)."""
+    import workloads as wl
+    out = {}
+    for name, dts in (("heat1d_65536", ("f64",)), ("star3d_512", ("f32",)),
+                      ("box2d_aperiodic_4096", ("f64", "f32"))):
+        w = wl.config(name)
+        for dt in dts:
+            out[f"{name}_{dt}"] = dict(time_solve(sfft, torch, w, dt), dims=list(w.dims), T=w.T,
+                                       aperiodic=w.aperiodic)
+    return out
+
+
 def copy_reference(torch, nbytes: int, reps: int = 10):
     """Device-to-device copy bandwidth (read + write bytes / time) of a plain
     elementwise copy of `nbytes`, the practical HBM ceiling the passes are
@@ -215,6 +252,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 path")
     ap.add_argument("--serving", type=int, default=10000, help="serving-mix requests (0 = skip)")
     ap.add_argument("--no-copy", action="store_true", help="skip the device-copy bandwidth reference")
+    ap.add_argument("--no-others", action="store_true", help="skip the other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -278,6 +316,7 @@ def main():
                             "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in k32.items()},
         "f64": res64,
         "copy_reference": None if args.no_copy else copy_reference(torch, N * 4 * 2),
+        "other_workloads": None if args.no_others else other_workloads(sfft, torch),
         "cpu_baseline": None if args.no_cpu else cpu_baseline(w),
         "serving": serving_bench(sfft, torch, args.serving) if args.serving > 0 else None,
     }

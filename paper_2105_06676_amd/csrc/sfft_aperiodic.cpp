@@ -24,9 +24,11 @@
 #include <algorithm>
 #include <climits>
 #include <cstring>
+#include <map>
 #include <vector>
 
 #include "sfft_base.h"
+#include "sfft_kernels.h"
 #include "sfft_runtime.h"
 
 namespace sfft {
@@ -36,6 +38,16 @@ namespace {
 int64_t pad7(int64_t n) {
     while (!is_7smooth(n)) ++n;
     return n;
+}
+
+// Transform extent for n cells: the next power of two (which runs on the
+// register radix-16 kernels) unless that pads more than 1.5x the next 7-smooth
+// extent.
+int64_t pad_fft(int64_t n) {
+    int64_t p = 1;
+    while (p < n) p *= 2;
+    const int64_t s = pad7(n);
+    return (p <= 16384 && 2 * p <= 3 * s) ? p : s;
 }
 
 int64_t ceil_half(int64_t n) { return (n + 1) / 2; }
@@ -51,6 +63,8 @@ struct Ap {
     void* grid;
     int64_t total;       // stored elements
     std::vector<void*> level;
+    // per-column symbol parts for this solve, per plan and stream
+    std::map<std::pair<const Plan*, hipStream_t>, void*> coltab;
     int64_t cutoff;
     int64_t maxdist;     // largest dist of any interior cell
 };
@@ -62,18 +76,35 @@ void* interior_origin(const Ap& a, const void* base) {
 }
 
 // Periodic solve of B boxes of `ext` cells read from `src` and written to `dst`
-// (both at the interior origin), zero-padded to 7-smooth transform extents.
+// (both at the interior origin), zero-padded to FFT-friendly extents, on stream
+// `st`.  With `read_done` set, that event is recorded once the first pass has
+// read all of `src`.
 void boxed_periodic(Ap& a, const void* src, void* dst, const int64_t* ext, int64_t B, int64_t boff,
-                    const KeepRule& keep, int64_t steps) {
+                    const KeepRule& keep, int64_t steps, hipStream_t st, hipEvent_t read_done = nullptr) {
     int64_t pd[3];
-    for (int k = 0; k < a.d; ++k) pd[k] = pad7(ext[k]);
+    for (int k = 0; k < a.d; ++k) pd[k] = pad_fft(ext[k]);
     DevCtx& ctx = device_ctx();
     auto plan = ctx.plan(a.d, pd, B, a.f64);
-    void* ws = ctx.workspace(a.st, (size_t)plan->s.spec_elems * (a.f64 ? 16 : 8));
+    void* ws = ctx.workspace(st, (size_t)plan->s.spec_elems * (a.f64 ? 16 : 8));
     SymParams sp = plan->s.sym;
     double N = 1.0;
     for (int k = 0; k < a.d; ++k) N *= (double)pd[k];
     fill_symbol(sp, a.coeffs, a.r, a.d, steps, 1.0 / N);
+    if (a.d >= 2) {
+        // the column part of the symbol depends on the plan and the coefficients
+        // only (not on the step count): build it once per plan within this solve
+        auto it = a.coltab.find({plan.get(), st});
+        if (it == a.coltab.end()) {
+            int64_t ncol = 1;
+            for (int k = 1; k < a.d; ++k) ncol *= sp.sdim[k];
+            void* tab = ctx.scratch(st, 300 + (int)a.coltab.size(), (size_t)ncol * symbol_column_bytes());
+            build_symbol_columns(sp, tab, a.f64, st);
+            it = a.coltab.emplace(std::make_pair(plan.get(), st), tab).first;
+        }
+        sp.coltab = it->second;
+        sp.ncol = 1;
+        for (int k = 1; k < a.d; ++k) sp.ncol *= sp.sdim[k];
+    }
     RealView in;
     std::memset(&in, 0, sizeof(in));
     in.boff = boff;
@@ -84,7 +115,13 @@ void boxed_periodic(Ap& a, const void* src, void* dst, const int64_t* ext, int64
     RealView out = in;
     in.ptr = const_cast<void*>(src);
     out.ptr = dst;
-    run_plan(*plan, ws, in, out, keep, sp, a.st);
+    if (!read_done) {
+        run_plan(*plan, ws, in, out, keep, sp, st);
+        return;
+    }
+    run_plan(*plan, ws, in, out, keep, sp, st, 0, 1);
+    check_hip(hipEventRecord(read_done, st), "hipEventRecord");
+    run_plan(*plan, ws, in, out, keep, sp, st, 1);
 }
 
 KeepRule make_keep(const Ap& a, int64_t lo, int64_t hi) {
@@ -99,10 +136,34 @@ KeepRule make_keep(const Ap& a, int64_t lo, int64_t hi) {
     return k;
 }
 
+// Helper streams that run forked work, to be joined back.
+struct Forked {
+    int n = 0;
+    hipStream_t s[3];
+    int ev[3];
+};
+
+// Make `to` wait for all work enqueued so far on `from`.
+void depend(Ap& a, hipStream_t from, hipStream_t to, int ev) {
+    hipEvent_t e = device_ctx().side_event(a.st, ev);
+    check_hip(hipEventRecord(e, from), "hipEventRecord");
+    check_hip(hipStreamWaitEvent(to, e, 0), "hipStreamWaitEvent");
+}
+
+void join(Ap& a, const Forked& f, hipStream_t st) {
+    for (int i = 0; i < f.n; ++i) depend(a, f.s[i], st, f.ev[i]);
+}
+
 // Periodic solves of the slabs of band (0, w] of `src` over `steps`, storing
-// (lo, hi] into `dst`.
-void slab_solve(Ap& a, const void* src, void* dst, int64_t w, int64_t steps, int64_t lo, int64_t hi) {
-    if (lo >= a.maxdist || hi <= lo) return;
+// (lo, hi] into `dst`.  The slabs of each axis keep disjoint cells, so each axis
+// runs on a helper stream of recursion level `lev`, forked off `st`.
+Forked slab_solve(Ap& a, const void* src, void* dst, int64_t w, int64_t steps, int64_t lo, int64_t hi, int lev,
+                  hipStream_t st) {
+    Forked f;
+    if (lo >= a.maxdist || hi <= lo) return f;
+    DevCtx& ctx = device_ctx();
+    hipEvent_t fork = ctx.side_event(a.st, 4 * lev + 3);
+    check_hip(hipEventRecord(fork, st), "hipEventRecord");
     const void* s0 = interior_origin(a, src);
     void* d0 = interior_origin(a, dst);
     for (int ax = 0; ax < a.d; ++ax) {
@@ -120,12 +181,18 @@ void slab_solve(Ap& a, const void* src, void* dst, int64_t w, int64_t steps, int
             keep.gbstep[ax] = a.n[ax] - ta;
             boff = (a.n[ax] - ta) * a.sstride[ax];
         }
-        boxed_periodic(a, s0, d0, ext, B, boff, keep, steps);
+        hipStream_t sa = ctx.side_stream(a.st, 4 * lev + ax);
+        check_hip(hipStreamWaitEvent(sa, fork, 0), "hipStreamWaitEvent");
+        boxed_periodic(a, s0, d0, ext, B, boff, keep, steps, sa);
+        f.s[f.n] = sa;
+        f.ev[f.n] = 4 * lev + ax;
+        ++f.n;
     }
+    return f;
 }
 
 // Loop `tau` steps on the band dist <= 2 r tau of src; store dist <= r tau into dst.
-void base_case(Ap& a, const void* src, void* dst, int64_t tau) {
+void base_case(Ap& a, const void* src, void* dst, int64_t tau, hipStream_t st) {
     BaseParams bp;
     std::memset(&bp, 0, sizeof(bp));
     const int sh = 3 - a.d;  // axis k of the problem is slot k + sh
@@ -224,16 +291,53 @@ void base_case(Ap& a, const void* src, void* dst, int64_t tau) {
     }
     bp.nstrip = ns;
     if (ns == 0) return;
+    // a leaf is latency-bound: cut tiles along the faces until there are enough
+    // workgroups to occupy the device (halo recomputation grows as tiles shrink)
+    auto total_tiles = [&]() {
+        int64_t t = 0;
+        for (int i = 0; i < ns; ++i) {
+            int64_t c = 1;
+            for (int k = 0; k < 3; ++k) c *= (bp.strip[i].ext[k] + bp.strip[i].tile[k] - 1) / bp.strip[i].tile[k];
+            t += c;
+        }
+        return t;
+    };
+    while (total_tiles() < 512) {
+        int bi = -1, bk = -1;
+        for (int i = 0; i < ns; ++i)
+            for (int k = 0; k < 3; ++k)
+                if (bp.strip[i].tile[k] > 32 && (bi < 0 || bp.strip[i].tile[k] > bp.strip[bi].tile[bk])) { bi = i; bk = k; }
+        if (bi < 0) break;
+        bp.strip[bi].tile[bk] = (bp.strip[bi].tile[bk] + 1) / 2;
+    }
+    first = 0;
+    lds = 0;
+    for (int i = 0; i < ns; ++i) {
+        BaseStrip& s = bp.strip[i];
+        int64_t cnt = 1, f = 1;
+        for (int k = 0; k < 3; ++k) {
+            s.ntiles[k] = (s.ext[k] + s.tile[k] - 1) / s.tile[k];
+            cnt *= s.ntiles[k];
+            f *= s.tile[k] + 2 * bp.halo3[k];
+        }
+        s.first = first;
+        first += cnt;
+        lds = std::max(lds, (size_t)f * a.esz);
+    }
     hipEvent_t ev = nullptr;
     const bool prof = profiling();
-    if (prof) profile_launch_begin(a.st, &ev);
-    check_hip(launch_base(bp, a.f64, first, lds, a.st), "base-case launch");
-    if (prof) profile_launch_end(a.st, ev, a.f64 ? "base_case_f64" : "base_case_f32", 0);
+    if (prof) profile_launch_begin(st, &ev);
+    check_hip(launch_base(bp, a.f64, first, lds, st), "base-case launch");
+    if (prof) profile_launch_end(st, ev, a.f64 ? "base_case_f64" : "base_case_f32", 0);
 }
 
-void recursive_boundary(Ap& a, const void* src, void* dst, int64_t T, int lev) {
+// RecursiveBoundary(T) from src (time t0) into dst (time t0 + T), enqueued on
+// `st`.  Step 1's slabs and RecursiveBoundary(T1) read the same band of src and
+// write disjoint bands of `mid`, so the slabs run on helper streams of this
+// level while the recursion continues on `st`; step 2 likewise.
+void recursive_boundary(Ap& a, const void* src, void* dst, int64_t T, int lev, hipStream_t st) {
     if (T <= a.cutoff) {
-        base_case(a, src, dst, T);
+        base_case(a, src, dst, T, st);
         return;
     }
     const int64_t T1 = T / 2, T2 = T - T1;
@@ -244,11 +348,13 @@ void recursive_boundary(Ap& a, const void* src, void* dst, int64_t T, int lev) {
     }
     void* mid = a.level[lev];
     // step 1: band (0, 2sT] at t0 -> (0, sT + sT2] at t0 + T1
-    slab_solve(a, src, mid, 2 * s * T, T1, s * T1, s * T + s * T2);
-    recursive_boundary(a, src, mid, T1, lev + 1);
+    Forked f = slab_solve(a, src, mid, 2 * s * T, T1, s * T1, s * T + s * T2, lev, st);
+    recursive_boundary(a, src, mid, T1, lev + 1, st);
+    join(a, f, st);
     // step 2: band (0, sT + sT2] at t0 + T1 -> (0, sT] at t0 + T
-    slab_solve(a, mid, dst, s * T + s * T2, T2, s * T2, s * T);
-    recursive_boundary(a, mid, dst, T2, lev + 1);
+    f = slab_solve(a, mid, dst, s * T + s * T2, T2, s * T2, s * T, lev, st);
+    recursive_boundary(a, mid, dst, T2, lev + 1, st);
+    join(a, f, st);
 }
 
 }  // namespace
@@ -276,39 +382,52 @@ void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const dou
         // no neighbours: the frame is never read and every cell scales by c0^T
         KeepRule keep = make_keep(a, 0, LLONG_MAX);
         keep.enabled = 0;
-        boxed_periodic(a, interior_origin(a, grid), interior_origin(a, grid), a.n, 1, 0, keep, T);
+        boxed_periodic(a, interior_origin(a, grid), interior_origin(a, grid), a.n, 1, 0, keep, T, st);
         return;
     }
     // base-case reach: the halo r * cutoff must fit an LDS tile
     const int64_t reach = d == 1 ? 256 : d == 2 ? 16 : 4;
     a.cutoff = tunables().aperiodic_cutoff > 0 ? tunables().aperiodic_cutoff : std::max<int64_t>(1, reach / r);
     const int64_t sT = (int64_t)r * T;
-    // RecursiveBoundary step 1 reads the initial band before the interior solve
-    // overwrites dist > sT; step 2 writes dist <= sT after the interior solve has
-    // read the whole initial interior.
+    DevCtx& ctx = device_ctx();
+    // the interior solve runs on a helper stream of its own
+    hipStream_t si = ctx.side_stream(st, -1);
     if (T <= a.cutoff) {
         // The base case reads dist <= 2 sT of the initial array while the result
-        // is stored in place, so it reads from a copy.
-        void* tmp = device_ctx().scratch(st, 99, (size_t)a.total * a.esz);
+        // is stored in place, so both parts read from a copy and run side by side.
+        void* tmp = ctx.scratch(st, 99, (size_t)a.total * a.esz);
         check_hip(hipMemcpyAsync(tmp, grid, (size_t)a.total * a.esz, hipMemcpyDeviceToDevice, st), "copy");
         if (sT < a.maxdist) {
+            depend(a, st, si, -1);
             KeepRule keep = make_keep(a, sT, LLONG_MAX);
-            boxed_periodic(a, interior_origin(a, tmp), interior_origin(a, grid), a.n, 1, 0, keep, T);
+            boxed_periodic(a, interior_origin(a, tmp), interior_origin(a, grid), a.n, 1, 0, keep, T, si);
         }
-        base_case(a, tmp, grid, T);
+        base_case(a, tmp, grid, T, st);
+        if (sT < a.maxdist) depend(a, si, st, -2);
         return;
     }
+    // RecursiveBoundary step 1 reads the initial band before the interior solve
+    // overwrites dist > sT; step 2 writes dist <= sT only after the interior
+    // solve's first pass has read the whole initial interior.
     const int64_t T1 = T / 2, T2 = T - T1;
-    void* mid = device_ctx().scratch(st, 100, (size_t)a.total * a.esz);
+    void* mid = ctx.scratch(st, 100, (size_t)a.total * a.esz);
     a.level.push_back(mid);
-    slab_solve(a, grid, mid, 2 * sT, T1, r * T1, sT + r * T2);
-    recursive_boundary(a, grid, mid, T1, 1);
-    if (sT < a.maxdist) {
+    Forked f = slab_solve(a, grid, mid, 2 * sT, T1, r * T1, sT + r * T2, 0, st);
+    recursive_boundary(a, grid, mid, T1, 1, st);
+    join(a, f, st);
+    const bool interior = sT < a.maxdist;
+    if (interior) {
+        depend(a, st, si, -1);
         KeepRule keep = make_keep(a, sT, LLONG_MAX);
-        boxed_periodic(a, interior_origin(a, grid), interior_origin(a, grid), a.n, 1, 0, keep, T);
+        hipEvent_t read_done = ctx.side_event(st, -3);
+        boxed_periodic(a, interior_origin(a, grid), interior_origin(a, grid), a.n, 1, 0, keep, T, si,
+                       read_done);
+        check_hip(hipStreamWaitEvent(st, read_done, 0), "hipStreamWaitEvent");
     }
-    slab_solve(a, mid, grid, sT + r * T2, T2, r * T2, sT);
-    recursive_boundary(a, mid, grid, T2, 1);
+    f = slab_solve(a, mid, grid, sT + r * T2, T2, r * T2, sT, 0, st);
+    recursive_boundary(a, mid, grid, T2, 1, st);
+    join(a, f, st);
+    if (interior) depend(a, si, st, -2);
 }
 
 }  // namespace sfft

@@ -236,26 +236,46 @@ __device__ __forceinline__ cx<R> step_twiddle(const PassDesc& pd, int64_t e) {
 // ---------------------------------------------------------------------------
 // Region bookkeeping for the last pass: may local cell (b, i) be stored?
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool keep_cell(const KeepRule& kr, int d, int64_t b, const int64_t* i) {
-    if (!kr.enabled) return true;
-    int64_t dist = INT64_MAX;
-    int64_t fd[6];
-    for (int a = 0; a < d; ++a) {
-        const int64_t g = kr.gorg[a] + b * kr.gbstep[a] + i[a];
-        fd[2 * a] = g + 1;
-        fd[2 * a + 1] = kr.gdim[a] - g;
-        dist = min(dist, min(fd[2 * a], fd[2 * a + 1]));
+// The part of the test that is fixed along a row: distance and first face over
+// the axes before the last one.
+struct RowKeep {
+    int64_t dpre;   // min face distance over axes 0..d-2 (huge if none)
+    int fpre;       // first face (in face order) at that distance
+};
+
+__device__ __forceinline__ RowKeep keep_row(const KeepRule& kr, int d, int64_t b, const int64_t* i) {
+    RowKeep rk{INT64_MAX, -1};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        if (a < d - 1) {
+            const int64_t g = kr.gorg[a] + b * kr.gbstep[a] + i[a];
+            const int64_t lo = g + 1, hi = kr.gdim[a] - g;
+            if (lo < rk.dpre) { rk.dpre = lo; rk.fpre = 2 * a; }
+            if (hi < rk.dpre) { rk.dpre = hi; rk.fpre = 2 * a + 1; }
+        }
     }
+    return rk;
+}
+
+// May cell m of the last axis of a row be stored?
+__device__ __forceinline__ bool keep_last(const KeepRule& kr, const RowKeep& rk, int d, int64_t b, int64_t m) {
+    const int L = d - 1;
+    const int64_t g = kr.gorg[L] + b * kr.gbstep[L] + m;
+    const int64_t lo = g + 1, hi = kr.gdim[L] - g;
+    int64_t dist = rk.dpre;
+    int first = rk.fpre;
+    if (lo < dist) { dist = lo; first = 2 * L; }
+    if (hi < dist) { dist = hi; first = 2 * L + 1; }
     if (!(dist > kr.lo && dist <= kr.hi)) return false;
     if (kr.face_axis < 0) return true;
-    int first = 0;
-    for (int f = 0; f < 2 * d; ++f) {
-        if (fd[f] == dist) { first = f; break; }
-    }
     if (first / 2 != kr.face_axis) return false;
     const int side = kr.face_side == 2 ? (int)b : kr.face_side;
-    if (side < 0) return true;
-    return (first & 1) == side;
+    return side < 0 || (first & 1) == side;
+}
+
+__device__ __forceinline__ bool keep_cell(const KeepRule& kr, int d, int64_t b, const int64_t* i) {
+    if (!kr.enabled) return true;
+    return keep_last(kr, keep_row(kr, d, b, i), d, b, i[d - 1]);
 }
 
 // ---------------------------------------------------------------------------

@@ -351,6 +351,7 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
         for (int i = 0; i < 16; ++i) d2[P * i] = v[i];
         return;
     }
+    const RowKeep rk = keep_row(pd.keep, pd.d, b, ii);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int m = q + P * i;
@@ -358,8 +359,7 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
         for (int h = 0; h < 2; ++h) {
             const int64_t mm = 2 * m + h;
             if (mm >= el) continue;
-            ii[pd.d - 1] = mm;
-            if (pd.keep.enabled && !keep_cell(pd.keep, pd.d, b, ii)) continue;
+            if (pd.keep.enabled && !keep_last(pd.keep, rk, pd.d, b, mm)) continue;
             out[base + mm * sl] = h ? v[i].y : v[i].x;
         }
     }
@@ -438,8 +438,7 @@ __device__ __forceinline__ void fcol_tile(const PassDesc& pd, const SymParams& s
         for (int i = 0; i < 16; ++i) {
             const int64_t m = (int64_t)(q + P * i) * pd.kstride + c;
             if (m >= pd.rvo.ext[0]) continue;
-            int64_t ix[3] = {m, 0, 0};
-            if (pd.keep.enabled && !keep_cell(pd.keep, 1, o, ix)) continue;
+            if (pd.keep.enabled && !keep_last(pd.keep, RowKeep{INT64_MAX, -1}, 1, o, m)) continue;
             dst[o * pd.rvo.boff + m * pd.rvo.stride[0]] = v[i].x;
         }
     } else {

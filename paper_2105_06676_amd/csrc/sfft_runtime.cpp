@@ -128,7 +128,7 @@ void* DevCtx::workspace(hipStream_t st, size_t bytes) {
     if (bytes == 0) return w.first;
     if (w.second < bytes) {
         if (w.first) {
-            check_hip(hipStreamSynchronize(st), "hipStreamSynchronize(workspace growth)");
+            check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize(workspace growth)");
             check_hip(hipFree(w.first), "hipFree(workspace)");
             w.first = nullptr;
             w.second = 0;
@@ -144,12 +144,26 @@ void* DevCtx::workspace(hipStream_t st, size_t bytes) {
     return w.first;
 }
 
+hipStream_t DevCtx::side_stream(hipStream_t st, int i) {
+    std::lock_guard<std::mutex> g(mu);
+    auto& s = sides[{st, i}];
+    if (!s) check_hip(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreateWithFlags(side)");
+    return s;
+}
+
+hipEvent_t DevCtx::side_event(hipStream_t st, int i) {
+    std::lock_guard<std::mutex> g(mu);
+    auto& e = side_events[{st, i}];
+    if (!e) check_hip(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreateWithFlags(side)");
+    return e;
+}
+
 void* DevCtx::scratch(hipStream_t st, int slot, size_t bytes) {
     std::lock_guard<std::mutex> g(mu);
     auto& w = extra[{st, slot}];
     if (w.second < bytes) {
         if (w.first) {
-            check_hip(hipStreamSynchronize(st), "hipStreamSynchronize(scratch growth)");
+            check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize(scratch growth)");
             check_hip(hipFree(w.first), "hipFree(scratch)");
             w.first = nullptr;
             w.second = 0;
@@ -206,24 +220,30 @@ RealView dense_view(void* ptr, int d, const int64_t* dims) {
     return v;
 }
 
+void build_symbol_columns(SymParams& sym, void* tab, bool f64, hipStream_t st) {
+    int64_t ncol = 1;
+    for (int a = 1; a < sym.d; ++a) ncol *= sym.sdim[a];
+    sym.coltab = tab;
+    sym.ncol = ncol;
+    hipEvent_t ev = nullptr;
+    const bool prof = profiling();
+    if (prof) profile_launch_begin(st, &ev);
+    check_hip(launch_symbol_columns(tab, sym, ncol, st), "symbol column launch");
+    if (prof) profile_launch_end(st, ev, f64 ? "symbol_columns_f64" : "symbol_columns_f32", 0);
+}
+
 void run_plan(const Plan& p, void* ws, const RealView& in, const RealView& out, const KeepRule& keep,
-              const SymParams& sym_in, hipStream_t st) {
+              const SymParams& sym_in, hipStream_t st, size_t pass_begin, size_t pass_end) {
     const bool f64 = p.s.f64;
     SymParams sym = sym_in;
-    if (sym.d >= 2) {
+    if (sym.d >= 2 && !sym.coltab) {
         // per-column part of the symbol (axes 1..d-1), once per solve
         int64_t ncol = 1;
         for (int a = 1; a < sym.d; ++a) ncol *= sym.sdim[a];
-        void* tab = device_ctx().scratch(st, 50, (size_t)ncol * symbol_column_bytes());
-        sym.coltab = tab;
-        sym.ncol = ncol;
-        hipEvent_t ev = nullptr;
-        const bool prof = profiling();
-        if (prof) profile_launch_begin(st, &ev);
-        check_hip(launch_symbol_columns(tab, sym, ncol, st), "symbol column launch");
-        if (prof) profile_launch_end(st, ev, f64 ? "symbol_columns_f64" : "symbol_columns_f32", 0);
+        build_symbol_columns(sym, device_ctx().scratch(st, 50, (size_t)ncol * symbol_column_bytes()), f64, st);
     }
-    for (size_t i = 0; i < p.pd.size(); ++i) {
+    pass_end = std::min(pass_end, p.pd.size());
+    for (size_t i = pass_begin; i < pass_end; ++i) {
         PassDesc pd = p.pd[i];
         pd.buf = ws;
         if (pd.in_real) pd.rv = in;

@@ -48,6 +48,13 @@ struct DevCtx {
     void* workspace(hipStream_t st, size_t bytes);
     void* scratch(hipStream_t st, int slot, size_t bytes);  // extra per-stream buffers
     std::map<std::pair<hipStream_t, int>, std::pair<void*, size_t>> extra;
+    // Helper streams and events owned by a caller stream, for solves that fork
+    // independent work off it and join it back (created on first use, default
+    // priority, non-blocking).
+    hipStream_t side_stream(hipStream_t st, int i);
+    hipEvent_t side_event(hipStream_t st, int i);
+    std::map<std::pair<hipStream_t, int>, hipStream_t> sides;
+    std::map<std::pair<hipStream_t, int>, hipEvent_t> side_events;
 
    private:
     std::pair<double2*, float2*> table(const TwiddleReq& r);
@@ -58,9 +65,14 @@ DevCtx& device_ctx();  // context of the current HIP device (created on first us
 // Coefficient-dependent part of the symbol parameters (Sec. 3 Steps 1(i), 2).
 void fill_symbol(SymParams& sp, const double* coeffs, int radius, int d, int64_t T, double scale);
 
-// Enqueue every pass of a plan.  in/out: real views of the first / last pass.
+// Fill `tab` with the per-column symbol parts of `sym` (d >= 2) and point
+// sym.coltab / sym.ncol at it.
+void build_symbol_columns(SymParams& sym, void* tab, bool f64, hipStream_t st);
+
+// Enqueue passes [pass_begin, pass_end) of a plan (all by default; builds the
+// column table first unless sym.coltab is set).  in/out: real views of the first / last pass.
 void run_plan(const Plan& p, void* ws, const RealView& in, const RealView& out, const KeepRule& keep,
-              const SymParams& sym, hipStream_t st);
+              const SymParams& sym, hipStream_t st, size_t pass_begin = 0, size_t pass_end = SIZE_MAX);
 
 // Natural row-major view of a dense array of `dims` (batch stride = element count).
 RealView dense_view(void* ptr, int d, const int64_t* dims);
