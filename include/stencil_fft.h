@@ -90,6 +90,10 @@ int stencil_fft_periodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* 
  * frame cells where the stencil reaches them (the aperiodic looping algorithm of
  * Sec. 2 with radius boundary cells on each side).  Interior extents need not
  * be 7-smooth (FFT sub-problems are zero-padded where the method allows it).
+ * Independent parts of the recursion run on helper streams forked from and
+ * joined back into `stream`; repeated identical calls are replayed from a
+ * captured graph (option "aperiodic_graphs").  Calls that share a stream must
+ * not be issued from several host threads at once.
  */
 int stencil_fft_aperiodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims,
                           const double* coeffs, int radius, int64_t T, void* stream);
@@ -124,7 +128,8 @@ typedef struct {
 /*
  * Solve n independent problems of uneven shapes, dtypes and T, enqueued on one
  * stream.  Periodic problems are packed into persistent batched launches: one
- * launch per pass index runs the tiles of every problem's pass of that index.
+ * launch per pass index and kernel variant runs the tiles of every problem's
+ * pass of that index that uses that variant.
  * Aperiodic problems are solved one after another on the same stream.
  * Validation covers every problem before anything is enqueued: on error nothing
  * runs and the message names the offending problem index.
@@ -182,6 +187,12 @@ void sfft_server_destroy(sfft_server* s);
  *                       when 0).
  *   "col_max"           longest sub-transform a strided pass performs (power of
  *                       two, 16..1024; default 0 = per-dtype choice).
+ *   "generic_kernels"   1: run every pass on the generic (runtime-radix) kernels
+ *                       instead of the power-of-two register kernels (testing).
+ *   "aperiodic_graphs"  1 (default): stencil_fft_aperiodic captures the second
+ *                       identical call (same grid address, shape, coefficients,
+ *                       T, stream and tunables) into a graph and replays it on
+ *                       later identical calls; 0: always enqueue directly.
  * Returns SFFT_EINVAL for an unknown name or an out-of-range value.
  */
 int stencil_fft_set_option(const char* name, int64_t value);

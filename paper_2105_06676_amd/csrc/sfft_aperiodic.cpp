@@ -25,6 +25,8 @@
 #include <climits>
 #include <cstring>
 #include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "sfft_base.h"
@@ -359,8 +361,11 @@ void recursive_boundary(Ap& a, const void* src, void* dst, int64_t T, int lev, h
 
 }  // namespace
 
-void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
-                     hipStream_t st) {
+namespace {
+
+// Set up the solve state; resources (helper streams, events, scratch) are owned
+// by the caller's stream `st`.
+Ap make_ap(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, hipStream_t st) {
     Ap a;
     a.f64 = f64;
     a.d = d;
@@ -378,56 +383,202 @@ void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const dou
     a.total = s;
     a.maxdist = LLONG_MAX;
     for (int k = 0; k < d; ++k) a.maxdist = std::min(a.maxdist, ceil_half(a.n[k]));
-    if (r == 0) {
+    // base-case reach: the halo r * cutoff must fit an LDS tile
+    const int64_t reach = d == 1 ? 256 : d == 2 ? 16 : 4;
+    a.cutoff = r == 0 ? 0
+                      : tunables().aperiodic_cutoff > 0 ? tunables().aperiodic_cutoff
+                                                         : std::max<int64_t>(1, reach / r);
+    return a;
+}
+
+// T > cutoff and r > 0: StencilFFT-A with RecursiveBoundary, main-line work
+// enqueued on `ls` (the caller's stream, or a capturing stream).
+void recursive_path(Ap& a, int64_t T, hipStream_t ls) {
+    DevCtx& ctx = device_ctx();
+    const int64_t r = a.r, sT = r * T;
+    hipStream_t si = ctx.side_stream(a.st, -1);  // the interior solve's helper stream
+    // RecursiveBoundary step 1 reads the initial band before the interior solve
+    // overwrites dist > sT; step 2 writes dist <= sT only after the interior
+    // solve's first pass has read the whole initial interior.
+    const int64_t T1 = T / 2, T2 = T - T1;
+    void* mid = ctx.scratch(a.st, 100, (size_t)a.total * a.esz);
+    a.level.push_back(mid);
+    Forked f = slab_solve(a, a.grid, mid, 2 * sT, T1, r * T1, sT + r * T2, 0, ls);
+    recursive_boundary(a, a.grid, mid, T1, 1, ls);
+    join(a, f, ls);
+    const bool interior = sT < a.maxdist;
+    if (interior) {
+        depend(a, ls, si, -1);
+        KeepRule keep = make_keep(a, sT, LLONG_MAX);
+        hipEvent_t read_done = ctx.side_event(a.st, -3);
+        boxed_periodic(a, interior_origin(a, a.grid), interior_origin(a, a.grid), a.n, 1, 0, keep, T, si,
+                       read_done);
+        check_hip(hipStreamWaitEvent(ls, read_done, 0), "hipStreamWaitEvent");
+    }
+    f = slab_solve(a, mid, a.grid, sT + r * T2, T2, r * T2, sT, 0, ls);
+    recursive_boundary(a, mid, a.grid, T2, 1, ls);
+    join(a, f, ls);
+    if (interior) depend(a, si, ls, -2);
+}
+
+// Solves of T <= cutoff or r == 0 (few launches; always enqueued directly).
+void short_path(Ap& a, int64_t T) {
+    DevCtx& ctx = device_ctx();
+    hipStream_t st = a.st;
+    void* grid = a.grid;
+    if (a.r == 0) {
         // no neighbours: the frame is never read and every cell scales by c0^T
         KeepRule keep = make_keep(a, 0, LLONG_MAX);
         keep.enabled = 0;
         boxed_periodic(a, interior_origin(a, grid), interior_origin(a, grid), a.n, 1, 0, keep, T, st);
         return;
     }
-    // base-case reach: the halo r * cutoff must fit an LDS tile
-    const int64_t reach = d == 1 ? 256 : d == 2 ? 16 : 4;
-    a.cutoff = tunables().aperiodic_cutoff > 0 ? tunables().aperiodic_cutoff : std::max<int64_t>(1, reach / r);
-    const int64_t sT = (int64_t)r * T;
-    DevCtx& ctx = device_ctx();
-    // the interior solve runs on a helper stream of its own
+    const int64_t sT = (int64_t)a.r * T;
     hipStream_t si = ctx.side_stream(st, -1);
-    if (T <= a.cutoff) {
-        // The base case reads dist <= 2 sT of the initial array while the result
-        // is stored in place, so both parts read from a copy and run side by side.
-        void* tmp = ctx.scratch(st, 99, (size_t)a.total * a.esz);
-        check_hip(hipMemcpyAsync(tmp, grid, (size_t)a.total * a.esz, hipMemcpyDeviceToDevice, st), "copy");
-        if (sT < a.maxdist) {
-            depend(a, st, si, -1);
-            KeepRule keep = make_keep(a, sT, LLONG_MAX);
-            boxed_periodic(a, interior_origin(a, tmp), interior_origin(a, grid), a.n, 1, 0, keep, T, si);
-        }
-        base_case(a, tmp, grid, T, st);
-        if (sT < a.maxdist) depend(a, si, st, -2);
-        return;
-    }
-    // RecursiveBoundary step 1 reads the initial band before the interior solve
-    // overwrites dist > sT; step 2 writes dist <= sT only after the interior
-    // solve's first pass has read the whole initial interior.
-    const int64_t T1 = T / 2, T2 = T - T1;
-    void* mid = ctx.scratch(st, 100, (size_t)a.total * a.esz);
-    a.level.push_back(mid);
-    Forked f = slab_solve(a, grid, mid, 2 * sT, T1, r * T1, sT + r * T2, 0, st);
-    recursive_boundary(a, grid, mid, T1, 1, st);
-    join(a, f, st);
-    const bool interior = sT < a.maxdist;
-    if (interior) {
+    // The base case reads dist <= 2 sT of the initial array while the result is
+    // stored in place, so both parts read from a copy and run side by side.
+    void* tmp = ctx.scratch(st, 99, (size_t)a.total * a.esz);
+    check_hip(hipMemcpyAsync(tmp, grid, (size_t)a.total * a.esz, hipMemcpyDeviceToDevice, st), "copy");
+    if (sT < a.maxdist) {
         depend(a, st, si, -1);
         KeepRule keep = make_keep(a, sT, LLONG_MAX);
-        hipEvent_t read_done = ctx.side_event(st, -3);
-        boxed_periodic(a, interior_origin(a, grid), interior_origin(a, grid), a.n, 1, 0, keep, T, si,
-                       read_done);
-        check_hip(hipStreamWaitEvent(st, read_done, 0), "hipStreamWaitEvent");
+        boxed_periodic(a, interior_origin(a, tmp), interior_origin(a, grid), a.n, 1, 0, keep, T, si);
     }
-    f = slab_solve(a, mid, grid, sT + r * T2, T2, r * T2, sT, 0, st);
-    recursive_boundary(a, mid, grid, T2, 1, st);
-    join(a, f, st);
-    if (interior) depend(a, si, st, -2);
+    base_case(a, tmp, grid, T, st);
+    if (sT < a.maxdist) depend(a, si, st, -2);
+}
+
+// Captured graphs of repeated recursive solves.  A solve is a pure function of
+// the key below (the grid is read and written through its address at replay
+// time), so a replay recomputes exactly what a direct enqueue would; the graph
+// also bakes in workspace and scratch addresses, hence the epoch check.
+struct GraphKey {
+    int dev;
+    hipStream_t st;
+    void* grid;
+    int f64, d, r;
+    int64_t dims[3];
+    int64_t T, cutoff;
+    int col_max, no_fast;
+    std::vector<double> c;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(dev, st, grid, f64, d, r, dims[0], dims[1], dims[2], T, cutoff, col_max, no_fast, c) <
+               std::tie(o.dev, o.st, o.grid, o.f64, o.d, o.r, o.dims[0], o.dims[1], o.dims[2], o.T, o.cutoff,
+                        o.col_max, o.no_fast, o.c);
+    }
+};
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    uint64_t epoch = 0;  // buffer epoch after the last direct enqueue
+    uint64_t used = 0;
+};
+constexpr size_t kMaxGraphs = 16;
+std::mutex g_mu;
+std::map<GraphKey, GraphEntry> g_cache;
+uint64_t g_clock = 0;
+
+void drop_graph(GraphEntry& e) {
+    if (!e.exec) return;
+    check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize(graph release)");
+    check_hip(hipGraphExecDestroy(e.exec), "hipGraphExecDestroy");
+    e.exec = nullptr;
+}
+
+}  // namespace
+
+void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
+                     hipStream_t st) {
+    Ap a = make_ap(grid, f64, d, dims, coeffs, r, st);
+    if (r == 0 || T <= a.cutoff)
+        short_path(a, T);
+    else
+        recursive_path(a, T, st);
+}
+
+// Entry-point variant: the second identical call (same grid address, shape,
+// coefficients, T, stream and tunables) captures the recursive enqueue into a
+// graph and later identical calls replay it, which removes the per-launch and
+// per-event host cost of the several hundred launches of a deep recursion.
+void solve_aperiodic_cached(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
+                            int64_t T, hipStream_t st) {
+    Ap a = make_ap(grid, f64, d, dims, coeffs, r, st);
+    if (r == 0 || T <= a.cutoff) {
+        short_path(a, T);
+        return;
+    }
+    if (!tunables().aperiodic_graphs || profiling()) {
+        recursive_path(a, T, st);
+        return;
+    }
+    DevCtx& ctx = device_ctx();
+    GraphKey key;
+    key.dev = ctx.device;
+    key.st = st;
+    key.grid = grid;
+    key.f64 = f64;
+    key.d = d;
+    key.r = r;
+    for (int k = 0; k < 3; ++k) key.dims[k] = k < d ? dims[k] : 0;
+    key.T = T;
+    key.cutoff = a.cutoff;
+    key.col_max = tunables().col_max;
+    key.no_fast = tunables().no_fast;
+    int nc = 1;
+    for (int k = 0; k < d; ++k) nc *= 2 * r + 1;
+    key.c.assign(coeffs, coeffs + nc);
+
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_cache.find(key);
+    if (it == g_cache.end()) {
+        if (g_cache.size() >= kMaxGraphs) {
+            auto lru = g_cache.begin();
+            for (auto j = g_cache.begin(); j != g_cache.end(); ++j)
+                if (j->second.used < lru->second.used) lru = j;
+            drop_graph(lru->second);
+            g_cache.erase(lru);
+        }
+        it = g_cache.emplace(key, GraphEntry{}).first;
+        it->second.used = ++g_clock;
+        recursive_path(a, T, st);
+        it->second.epoch = ctx.epoch;
+        return;
+    }
+    GraphEntry& e = it->second;
+    e.used = ++g_clock;
+    if (e.epoch != ctx.epoch) {
+        // a buffer this solve used has been released since: enqueue directly
+        drop_graph(e);
+        recursive_path(a, T, st);
+        e.epoch = ctx.epoch;
+        return;
+    }
+    if (!e.exec) {
+        // every buffer and plan the solve needs exists already, so capturing
+        // allocates and synchronises nothing
+        hipStream_t cs = ctx.side_stream(st, -100);
+        check_hip(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        hipGraph_t graph = nullptr;
+        try {
+            recursive_path(a, T, cs);
+        } catch (...) {
+            (void)hipStreamEndCapture(cs, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            throw;
+        }
+        check_hip(hipStreamEndCapture(cs, &graph), "hipStreamEndCapture");
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        check_hip(ie, "hipGraphInstantiate");
+        if (ctx.epoch != e.epoch) {
+            // defensive: the capture must not have released anything
+            (void)hipGraphExecDestroy(exec);
+            throw Error(-4, "aperiodic graph capture released a buffer");
+        }
+        e.exec = exec;
+    }
+    check_hip(hipGraphLaunch(e.exec, st), "hipGraphLaunch");
 }
 
 }  // namespace sfft

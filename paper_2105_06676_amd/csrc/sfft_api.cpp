@@ -12,7 +12,7 @@ namespace sfft {
 const char* last_error_cstr();
 void profile_enable(bool on);
 std::string profile_json();
-void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
+void solve_aperiodic_cached(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
                      hipStream_t st);
 }  // namespace sfft
 
@@ -103,7 +103,7 @@ int stencil_fft_aperiodic(void* grid, sfft_dtype dtype, int ndim, const int64_t*
     return guarded([&] {
         validate(grid, dtype, ndim, dims, coeffs, radius, T);
         if (T == 0) return;
-        solve_aperiodic(grid, dtype == SFFT_F64, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
+        solve_aperiodic_cached(grid, dtype == SFFT_F64, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
     });
 }
 
@@ -142,6 +142,9 @@ int stencil_fft_set_option(const char* name, int64_t value) {
         } else if (n == "generic_kernels") {
             if (value != 0 && value != 1) throw Error(SFFT_EINVAL, "generic_kernels must be 0 or 1");
             tunables().no_fast = (int)value;
+        } else if (n == "aperiodic_graphs") {
+            if (value != 0 && value != 1) throw Error(SFFT_EINVAL, "aperiodic_graphs must be 0 or 1");
+            tunables().aperiodic_graphs = (int)value;
         } else if (n == "aperiodic_cutoff") {
             if (value < 0 || value > (1 << 20)) throw Error(SFFT_EINVAL, "aperiodic_cutoff out of range");
             tunables().aperiodic_cutoff = (int)value;

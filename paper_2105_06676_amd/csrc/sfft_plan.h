@@ -49,6 +49,7 @@ struct Tunables {
     int col_max = 0;          // 0: default
     int aperiodic_cutoff = 0; // 0: per-shape default
     int no_fast = 0;          // 1: generic kernels only (testing)
+    int aperiodic_graphs = 1; // 1: replay repeated aperiodic solves from captured graphs
 };
 Tunables& tunables();
 

@@ -130,6 +130,7 @@ void* DevCtx::workspace(hipStream_t st, size_t bytes) {
         if (w.first) {
             check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize(workspace growth)");
             check_hip(hipFree(w.first), "hipFree(workspace)");
+            ++epoch;
             w.first = nullptr;
             w.second = 0;
         }
@@ -165,6 +166,7 @@ void* DevCtx::scratch(hipStream_t st, int slot, size_t bytes) {
         if (w.first) {
             check_hip(hipDeviceSynchronize(), "hipDeviceSynchronize(scratch growth)");
             check_hip(hipFree(w.first), "hipFree(scratch)");
+            ++epoch;
             w.first = nullptr;
             w.second = 0;
         }

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
 #include <map>
 #include <functional>
 #include <memory>
@@ -55,6 +56,9 @@ struct DevCtx {
     hipEvent_t side_event(hipStream_t st, int i);
     std::map<std::pair<hipStream_t, int>, hipStream_t> sides;
     std::map<std::pair<hipStream_t, int>, hipEvent_t> side_events;
+    // Count of workspace / scratch buffers released so far; enqueued work (or a
+    // captured graph) that baked in buffer addresses is stale once it changes.
+    std::atomic<uint64_t> epoch{0};
 
    private:
     std::pair<double2*, float2*> table(const TwiddleReq& r);
