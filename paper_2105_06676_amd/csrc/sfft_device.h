@@ -18,14 +18,17 @@ template <typename R>
 __device__ __forceinline__ cx<R> operator+(cx<R> a, cx<R> b) { return {a.x + b.x, a.y + b.y}; }
 template <typename R>
 __device__ __forceinline__ cx<R> operator-(cx<R> a, cx<R> b) { return {a.x - b.x, a.y - b.y}; }
+// Products write their fused multiply-adds out: a * b - c * d could otherwise be
+// contracted either way round, and kernels compiled separately (direct and
+// batched launches) would then round differently.
 template <typename R>
 __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
-    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+    return {fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
 }
 // a * conj(b)
 template <typename R>
 __device__ __forceinline__ cx<R> cmulc(cx<R> a, cx<R> b) {
-    return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y};
+    return {fma(a.x, b.x, a.y * b.y), fma(a.y, b.x, -(a.x * b.y))};
 }
 template <typename R>
 __device__ __forceinline__ cx<R> conj(cx<R> a) { return {a.x, -a.y}; }
@@ -238,6 +241,12 @@ __device__ __forceinline__ cx<R> step_twiddle(const PassDesc& pd, int64_t e) {
 // ---------------------------------------------------------------------------
 // The part of the test that is fixed along a row: distance and first face over
 // the axes before the last one.
+// a[i] for i in 0..2 through selects (a runtime index into a small array would
+// place the array in scratch memory).
+__device__ __forceinline__ int64_t pick3(const int64_t* a, int i) {
+    return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]);
+}
+
 struct RowKeep {
     int64_t dpre;   // min face distance over axes 0..d-2 (huge if none)
     int fpre;       // first face (in face order) at that distance
@@ -260,8 +269,8 @@ __device__ __forceinline__ RowKeep keep_row(const KeepRule& kr, int d, int64_t b
 // May cell m of the last axis of a row be stored?
 __device__ __forceinline__ bool keep_last(const KeepRule& kr, const RowKeep& rk, int d, int64_t b, int64_t m) {
     const int L = d - 1;
-    const int64_t g = kr.gorg[L] + b * kr.gbstep[L] + m;
-    const int64_t lo = g + 1, hi = kr.gdim[L] - g;
+    const int64_t g = pick3(kr.gorg, L) + b * pick3(kr.gbstep, L) + m;
+    const int64_t lo = g + 1, hi = pick3(kr.gdim, L) - g;
     int64_t dist = rk.dpre;
     int first = rk.fpre;
     if (lo < dist) { dist = lo; first = 2 * L; }
@@ -275,7 +284,7 @@ __device__ __forceinline__ bool keep_last(const KeepRule& kr, const RowKeep& rk,
 
 __device__ __forceinline__ bool keep_cell(const KeepRule& kr, int d, int64_t b, const int64_t* i) {
     if (!kr.enabled) return true;
-    return keep_last(kr, keep_row(kr, d, b, i), d, b, i[d - 1]);
+    return keep_last(kr, keep_row(kr, d, b, i), d, b, pick3(i, d - 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -294,7 +303,9 @@ __device__ __forceinline__ bool keep_cell(const KeepRule& kr, int d, int64_t b, 
 struct dcx {
     double x, y;
 };
-__device__ __forceinline__ dcx dmul(dcx a, dcx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ dcx dmul(dcx a, dcx b) {
+    return {fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x)};
+}
 __device__ __forceinline__ dcx dadd(dcx a, dcx b) { return {a.x + b.x, a.y + b.y}; }
 __device__ __forceinline__ dcx dsub(dcx a, dcx b) { return {a.x - b.x, a.y - b.y}; }
 
@@ -332,10 +343,18 @@ struct SymCol {
 };
 
 // E_a((o * f) mod n_a) for o in [-kMaxR, kMaxR] (32-bit index arithmetic).
+// (o * f) mod n for 0 <= f < n <= 2^31 and 0 <= o <= kMaxR, by conditional
+// subtraction (o * f < kMaxR * n) instead of an integer division.
+__device__ __forceinline__ uint32_t mul_mod_small(uint32_t o, uint32_t f, uint32_t n) {
+    uint32_t m = o * f;
+#pragma unroll
+    for (int k = 1; k < kMaxR; ++k) m = m >= n ? m - n : m;
+    return m;
+}
+
 __device__ __forceinline__ dcx eph32(const SymParams& sp, int a, int o, uint32_t f) {
     const uint32_t n = (uint32_t)sp.n[a];
-    uint32_t m = (uint32_t)(o < 0 ? -o : o) * f;
-    m = (n & (n - 1)) == 0 ? (m & (n - 1)) : (m % n);
+    const uint32_t m = mul_mod_small((uint32_t)(o < 0 ? -o : o), f, n);
     dcx e = ((const dcx*)sp.eph[a])[m];
     if (o < 0) e.y = -e.y;  // E(-m) = conj(E(m))
     return e;
@@ -409,17 +428,33 @@ __device__ inline SymCol symbol_column_1d(const SymParams& sp) {
 __device__ __forceinline__ dcx symbol_mu(const SymParams& sp, const SymCol& col, int64_t f0) {
     dcx mu = col.K;
     const uint32_t n = (uint32_t)sp.n[0];
-    const bool p2 = (n & (n - 1)) == 0;
     const dcx* t = (const dcx*)sp.eph[0];
     const uint32_t f = (uint32_t)f0;
 #pragma unroll
     for (int o = 1; o <= kMaxR; ++o) {
         if (o <= sp.r) {
-            uint32_t m = (uint32_t)o * f;
-            m = p2 ? (m & (n - 1)) : (m % n);
+            const uint32_t m = mul_mod_small((uint32_t)o, f, n);
             const dcx e = t[m];
             const dcx ec = {e.x, -e.y};
             mu = dsub(mu, dadd(dmul(e, col.Gp[o]), dmul(ec, col.Gm[o])));
+        }
+    }
+    return mu;
+}
+
+// mu for a point-symmetric stencil (c(-o) = c(o)), where lambda is real: the
+// column parts of opposite axis-0 offsets are conjugate (Gm = conj Gp), so the
+// two terms of an offset pair sum to 2 Re(E Gp).
+__device__ __forceinline__ double symbol_mu_real(const SymParams& sp, const SymCol& col, uint32_t f) {
+    double mu = col.K.x;
+    const uint32_t n = (uint32_t)sp.n[0];
+    const dcx* t = (const dcx*)sp.eph[0];
+#pragma unroll
+    for (int o = 1; o <= kMaxR; ++o) {
+        if (o <= sp.r) {
+            const uint32_t m = mul_mod_small((uint32_t)o, f, n);
+            const dcx e = t[m];
+            mu -= 2.0 * fma(e.x, col.Gp[o].x, -e.y * col.Gp[o].y);
         }
     }
     return mu;

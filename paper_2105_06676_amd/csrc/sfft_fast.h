@@ -19,4 +19,9 @@ hipError_t launch_fast_pass(const PassDesc& pd, const SymParams& sp, bool f64, s
 hipError_t launch_fast_batch(const PassDesc& proto, const BatchItem* items, int n, const SymParams* syms,
                              int64_t tiles, bool f64, size_t lds, hipStream_t st);
 
+// Threads of a column tile of length 2^logl: FP64 tiles of short columns use
+// half-size workgroups, so that more of them share a compute unit's LDS.
+constexpr bool col_half(bool f64, int logl) { return f64 && logl <= 7; }
+template <typename R>
+constexpr int col_threads(int logl) { return col_half(sizeof(R) == 8, logl) ? 128 : 256; }
 }  // namespace sfft

@@ -154,10 +154,13 @@ __device__ __forceinline__ void fast_fft(cx<R>* v, cx<R>* lds, IDX idx, int q, c
 // Row r of a row pass -> (batch b, i_0 .. i_{d-2}); returns b.
 __device__ __forceinline__ int64_t row_split(const PassDesc& pd, int64_t row, int64_t* i) {
     int64_t rem = row;
-    for (int a = pd.d - 2; a >= 0; --a) {
-        const int64_t qq = rem / pd.rdims[a];
-        i[a] = rem - qq * pd.rdims[a];
-        rem = qq;
+#pragma unroll
+    for (int a = 1; a >= 0; --a) {
+        if (a <= pd.d - 2) {
+            const int64_t qq = rem / pd.rdims[a];
+            i[a] = rem - qq * pd.rdims[a];
+            rem = qq;
+        }
     }
     return rem;
 }
@@ -165,9 +168,12 @@ __device__ __forceinline__ int64_t row_split(const PassDesc& pd, int64_t row, in
 // Base offset of a row in a real view, or -1 when the row lies outside its extents.
 __device__ __forceinline__ int64_t row_base(const RealView& v, int d, int64_t b, const int64_t* i) {
     int64_t off = b * v.boff;
-    for (int a = 0; a < d - 1; ++a) {
-        if (i[a] >= v.ext[a]) return -1;
-        off += i[a] * v.stride[a];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        if (a < d - 1) {
+            if (i[a] >= v.ext[a]) return -1;
+            off += i[a] * v.stride[a];
+        }
     }
     return off;
 }
@@ -175,27 +181,42 @@ __device__ __forceinline__ int64_t row_base(const RealView& v, int d, int64_t b,
 
 }  // namespace
 
-// Multiply the thread's 16 points by lambda(f0_i)^T * scale, f0_i = fbase + fstep * i.
-// The FP64 symbol power runs in a loop that is not unrolled (one copy of its
-// registers); its results pass through thread-private slots of the tile's LDS,
-// which is idle between the forward and the inverse transform.
-template <typename R>
-__device__ __forceinline__ void apply_symbol(cx<R>* v, cx<R>* lds, const SymParams& sp, const SymCol& col,
-                                             int64_t fbase, int64_t fstep) {
-    __syncthreads();  // every thread is done reading the tile
+// Multiply the thread's 16 points by lambda(f0_i)^T * scale, f0_i = fbase + fstep * i
+// (axis-0 frequencies, below 2^31).  Groups of four independent FP64 chains run
+// in a loop that is not unrolled (one copy of their registers); the results pass
+// through thread-private slots of the tile's LDS, which is idle between the
+// forward and the inverse transform.
+template <typename R, int NTH = kThreads>
+__device__ __forceinline__ void apply_symbol(cx<R>* v, cx<R>* lds, const SymParams& sp, const SymCol& col, uint32_t fbase,
+                                             uint32_t fstep) {
+    __syncthreads();
     constexpr int G = 4;
+    if (sp.real_sym) {
+        R* sl = reinterpret_cast<R*>(lds);
 #pragma unroll 1
-    for (int g = 0; g < 16; g += G) {
-        int64_t f[G];
-        dcx s[G];
+        for (int g = 0; g < 16; g += G) {
+            double m[G], o[G];
 #pragma unroll
-        for (int e = 0; e < G; ++e) f[e] = fbase + fstep * (g + e);
-        symbol_power_n<G>(sp, col, f, s);
+            for (int e = 0; e < G; ++e) m[e] = symbol_mu_real(sp, col, fbase + fstep * (uint32_t)(g + e));
+            power_real_dev<G>(m, o, sp.T);
 #pragma unroll
-        for (int e = 0; e < G; ++e) lds[threadIdx.x + kThreads * (g + e)] = cx<R>{R(s[e].x), R(s[e].y)};
+            for (int e = 0; e < G; ++e) sl[threadIdx.x + NTH * (g + e)] = R(o[e] * sp.scale);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = scale(v[i], sl[threadIdx.x + NTH * i]);
+    } else {
+#pragma unroll 1
+        for (int g = 0; g < 16; g += G) {
+            dcx m[G], o[G];
+#pragma unroll
+            for (int e = 0; e < G; ++e) m[e] = symbol_mu(sp, col, fbase + fstep * (uint32_t)(g + e));
+            power_complex_dev<G>(m, o, sp.T);
+#pragma unroll
+            for (int e = 0; e < G; ++e) lds[threadIdx.x + NTH * (g + e)] = cx<R>{R(o[e].x * sp.scale), R(o[e].y * sp.scale)};
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) v[i] = cmul(v[i], lds[threadIdx.x + NTH * i]);
     }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) v[i] = cmul(v[i], lds[threadIdx.x + kThreads * i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -227,7 +248,7 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
     if (KIND == ROW_R2C || KIND == ROW_MIDR) {
         const R* src = (const R*)pd.rv.ptr;
         const int64_t base = active ? row_base(pd.rv, pd.d, b, ii) : -1;
-        const int64_t sl = pd.rv.stride[pd.d - 1], el = pd.rv.ext[pd.d - 1];
+        const int64_t sl = pick3(pd.rv.stride, pd.d - 1), el = pick3(pd.rv.ext, pd.d - 1);
         const bool vec = base >= 0 && sl == 1 && el >= 2 * L && ((((uintptr_t)(src + base)) % (2 * sizeof(R))) == 0);
         if (vec) {
             const cx<R>* s2 = (const cx<R>*)(src + base) + q;
@@ -290,7 +311,7 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
         }
         // 1-D middle: multiply X[k], k = 0..L, by lambda^T / n
         const SymCol col = symbol_column_1d(sp);
-        apply_symbol<R>(v, lds, sp, col, q, P);
+        apply_symbol<R>(v, lds, sp, col, (uint32_t)q, (uint32_t)P);
         if (q == 0) {
             const int64_t fl = L;
             dcx s;
@@ -324,7 +345,7 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
         const int64_t fp = pos_to_freq(sp, 0, qd * L);
         const int64_t M = sp.n[0] / L;
         const SymCol col = symbol_column_1d(sp);
-        apply_symbol<R>(v, lds, sp, col, fp + M * q, M * P);
+        apply_symbol<R>(v, lds, sp, col, (uint32_t)(fp + M * q), (uint32_t)(M * P));
     }
 
     fast_fft<R, true, LOGL>(v, lds, idx, q, tlo, thi);
@@ -342,7 +363,7 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
     R* out = (R*)pd.rvo.ptr;
     const int64_t base = active ? row_base(pd.rvo, pd.d, b, ii) : -1;
     if (base < 0) return;
-    const int64_t sl = pd.rvo.stride[pd.d - 1], el = pd.rvo.ext[pd.d - 1];
+    const int64_t sl = pick3(pd.rvo.stride, pd.d - 1), el = pick3(pd.rvo.ext, pd.d - 1);
     const bool vec = !pd.keep.enabled && sl == 1 && el >= 2 * L &&
                      ((((uintptr_t)(out + base)) % (2 * sizeof(R))) == 0);
     if (vec) {
@@ -374,7 +395,8 @@ __device__ __forceinline__ void fcol_tile(const PassDesc& pd, const SymParams& s
     cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
     constexpr int L = 1 << LOGL;
     constexpr int P = L / 16;
-    constexpr int W = kThreads / P;
+    constexpr int NTH = col_threads<R>(LOGL);
+    constexpr int W = NTH / P;
     const int cl = threadIdx.x % W;
     const int q = threadIdx.x / W;
     uint32_t tile = bid;
@@ -421,7 +443,7 @@ __device__ __forceinline__ void fcol_tile(const PassDesc& pd, const SymParams& s
         const SymCol col = valid ? ((const SymCol*)sp.coltab)[c] : SymCol{};
         const int64_t fp = pos_to_freq(sp, 0, (o % pd.q_mod) * L);
         const int64_t M = sp.n[0] / L;
-        apply_symbol<R>(v, lds, sp, col, fp + M * q, M * P);
+        apply_symbol<R, NTH>(v, lds, sp, col, (uint32_t)(fp + M * q), (uint32_t)(M * P));
         fast_fft<R, true, LOGL>(v, lds, idx, q, tlo, thi);
     }
     if (MODE == MODE_INV) fast_fft<R, true, LOGL>(v, lds, idx, q, tlo, thi);
@@ -504,7 +526,7 @@ static void launch_row_l(const PassDesc& pd, const SymParams& sp, size_t lds, hi
 
 template <typename R, int LOGL>
 static void launch_col_l(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st, const BatchArgs* ba) {
-    const dim3 g((unsigned)(ba ? ba->tiles : pd.ntiles)), b(kThreads);
+    const dim3 g((unsigned)(ba ? ba->tiles : pd.ntiles)), b(col_threads<R>(LOGL));
 #define SFFT_COL(M)                                                                               \
     if (ba) hipLaunchKernelGGL((k_fcol_b<R, M, LOGL>), g, b, lds, st, ba->items, ba->n, ba->syms); \
     else hipLaunchKernelGGL((k_fcol<R, M, LOGL>), g, b, lds, st, pd, sp);

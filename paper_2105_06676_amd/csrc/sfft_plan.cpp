@@ -191,7 +191,7 @@ static PassPlan make_col(const Ctx& c, int64_t outer, int L, int64_t inner, int 
     if (is_pow2(L) && L >= kFastMinL && L <= kFastMaxColL && !tunables().no_fast) {
         pd.fast = 1;
         pd.logL = ilog2(L);
-        const int64_t Wf = kFastMaxRowL / L;
+        const int64_t Wf = (col_half(c.f64, ilog2(L)) ? kFastMaxRowL / 2 : kFastMaxRowL) / L;
         pd.W = (int)Wf;
         pd.tiles_inner = (inner + Wf - 1) / Wf;
         pd.ntiles = outer * pd.tiles_inner;
