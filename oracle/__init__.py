@@ -13,6 +13,10 @@ Contents
 ``aperiodic(a, coeffs, T)``
     The aperiodic nested loop with a fixed r-wide frame (Sec. 2 aperiodic looping
     algorithm; Sec. 4 for what StencilFFT-A must reproduce).
+``periodic_fields(a, coeffs, T)``
+    T sweeps of the periodic loop for m coupled scalar fields (the vector-valued
+    extension of Sec. 3 and its appendix): field i at t+1 is the sum over j of
+    stencil (i, j) applied to field j at t.
 ``symbol(coeffs, dims)``
     Step 1(i) of the periodic algorithm written literally: build the first column
     ``s`` of the circulant matrix and take its N-point DFT (appendix, eigenvalue-FFT
@@ -62,6 +66,10 @@ def _load():
             f.restype = ctypes.c_int
             f.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
                           ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int]
+        lib.oracle_periodic_fields.restype = ctypes.c_int
+        lib.oracle_periodic_fields.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                               ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p, ctypes.c_int,
+                                               ctypes.c_int64, ctypes.c_int]
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -87,6 +95,22 @@ def periodic(a: np.ndarray, coeffs: np.ndarray, T: int, nthreads: int = 0) -> np
     rc = _load().oracle_periodic(x.ctypes.data, x.ndim, dims, c.ctypes.data, r, int(T), int(nthreads))
     if rc != 0:
         raise RuntimeError(f"oracle_periodic failed ({rc})")
+    return x
+
+
+def periodic_fields(a: np.ndarray, coeffs: np.ndarray, T: int, nthreads: int = 0) -> np.ndarray:
+    """m coupled fields: ``a`` has shape (m, *dims), ``coeffs`` (m, m, *(2r+1,)*d);
+    block ``coeffs[i, j]`` is the stencil from field j at t to field i at t+1."""
+    x = np.ascontiguousarray(a, dtype=np.float64).copy()
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    m, d = x.shape[0], x.ndim - 1
+    if c.ndim != d + 2 or c.shape[0] != m or c.shape[1] != m:
+        raise ValueError(f"coefficients must be ({m}, {m}) + (2r+1,)*{d}, got {c.shape}")
+    r = _check_coeffs(c[0, 0], d)
+    dims = (ctypes.c_int64 * d)(*x.shape[1:])
+    rc = _load().oracle_periodic_fields(x.ctypes.data, m, d, dims, c.ctypes.data, r, int(T), int(nthreads))
+    if rc != 0:
+        raise RuntimeError(f"oracle_periodic_fields failed ({rc})")
     return x
 
 

@@ -19,6 +19,11 @@
  *    interior cells use the same sum without the modulo (the aperiodic looping
  *    algorithm of the same figure, with r boundary cells on each side).
  *
+ *  - periodic fields: m scalar fields a^(0..m-1) on the same periodic grid, each
+ *    step computing b^(i)[x] = sum over j (field order), then over offsets o (row-major),
+ *    of c^(i,j)[o] * a^(j)[(x + o) mod n] (the vector-valued extension: every field
+ *    at t+1 is a sum of stencils applied to every field at t).
+ *
  * Coefficients are a (2r+1)^d row-major array; c[o] multiplies the neighbour at
  * offset +o (the periodic loop's S[i, (i + j) % N] convention).  Sweeps are double
  * buffered; OpenMP splits the outermost spatial index, which does not change any
@@ -134,6 +139,58 @@ int oracle_aperiodic(double* a, int ndim, const int64_t* dims, const double* coe
         double* tmp = src; src = dst; dst = tmp;
     }
     if (src != a) memcpy(a, src, sizeof(double) * (size_t)S);
+    free(b);
+    return 0;
+}
+
+/* a: m * prod(dims) doubles, field-major ([m][dims...]), overwritten with the state
+ * after T sweeps; coeffs: m * m * (2r+1)^d doubles ([i][j][offsets...]), block
+ * (i, j) applied to field j contributes to field i. */
+int oracle_periodic_fields(double* a, int m, int ndim, const int64_t* dims, const double* coeffs,
+                           int r, int64_t T, int nthreads) {
+    if (m < 1 || ndim < 1 || ndim > 3 || r < 0 || T < 0 || !a || !dims || !coeffs) return -1;
+    int64_t n[3]; int rr[3];
+    expand3(ndim, dims, r, n, rr);
+    for (int k = 0; k < 3; ++k) if (n[k] < 1) return -1;
+    const int64_t N = n[0] * n[1] * n[2];
+    const int w0 = 2 * rr[0] + 1, w1 = 2 * rr[1] + 1, w2 = 2 * rr[2] + 1;
+    const int64_t nc = (int64_t)w0 * w1 * w2;
+    double* b = (double*)malloc(sizeof(double) * (size_t)(N * m));
+    if (!b) return -3;
+    double* src = a;
+    double* dst = b;
+    if (nthreads <= 0) nthreads = oracle_threads();
+    for (int64_t t = 0; t < T; ++t) {
+        for (int i = 0; i < m; ++i) {
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+            for (int64_t i0 = 0; i0 < n[0]; ++i0) {
+                for (int64_t i1 = 0; i1 < n[1]; ++i1) {
+                    for (int64_t i2 = 0; i2 < n[2]; ++i2) {
+                        double acc = 0.0;
+                        for (int j = 0; j < m; ++j) {
+                            const double* cij = coeffs + ((int64_t)i * m + j) * nc;
+                            const double* aj = src + (int64_t)j * N;
+                            for (int o0 = -rr[0]; o0 <= rr[0]; ++o0) {
+                                const int64_t j0 = wrap(i0 + o0, n[0]);
+                                for (int o1 = -rr[1]; o1 <= rr[1]; ++o1) {
+                                    const int64_t j1 = wrap(i1 + o1, n[1]);
+                                    for (int o2 = -rr[2]; o2 <= rr[2]; ++o2) {
+                                        const int64_t j2 = wrap(i2 + o2, n[2]);
+                                        const double c = cij[((o0 + rr[0]) * w1 + (o1 + rr[1])) * w2 + (o2 + rr[2])];
+                                        const double prod = c * aj[(j0 * n[1] + j1) * n[2] + j2];
+                                        acc = acc + prod;
+                                    }
+                                }
+                            }
+                        }
+                        dst[(int64_t)i * N + (i0 * n[1] + i1) * n[2] + i2] = acc;
+                    }
+                }
+            }
+        }
+        double* tmp = src; src = dst; dst = tmp;
+    }
+    if (src != a) memcpy(a, src, sizeof(double) * (size_t)(N * m));
     free(b);
     return 0;
 }
