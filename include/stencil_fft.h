@@ -98,6 +98,28 @@ int stencil_fft_periodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* 
 int stencil_fft_aperiodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims,
                           const double* coeffs, int radius, int64_t T, void* stream);
 
+/*
+ * Vector-valued fields (the appendix on vector-valued fields): nfields scalar
+ * fields on one periodic grid evolve together, field i at t+1 being the sum over j
+ * of the circulant stencil (i, j) applied to field j at t.  Affine updates and
+ * updates that read several earlier time steps are instances (an extra constant
+ * field; earlier steps carried as fields).
+ *   grid    DEVICE pointer to nfields * prod(dims) elements, field-major
+ *           ([nfields][dims...]); overwritten with the fields after T steps.
+ *   nfields 1..4 (SFFT_EUNSUPPORTED above 4).
+ *   coeffs  HOST pointer to nfields * nfields * (2*radius+1)^ndim doubles,
+ *           [i][j][offsets...]: block (i, j), laid out like the scalar
+ *           coefficients, weights field j's neighbours in field i's update; copied
+ *           before the call returns.
+ * The forward transforms of all fields run as one batch, the m x m symbol matrix
+ * of every mode is raised to the power T by repeated squaring in FP64 (deviation
+ * form), and the inverse transforms follow.  Same extent rules as
+ * stencil_fft_periodic, except that a 1-D extent must fit one row (n/2 <= 8192 for
+ * even n, n <= 8192 for odd n).  Errors as for stencil_fft_periodic.
+ */
+int stencil_fft_periodic_fields(void* grid, sfft_dtype dtype, int nfields, int ndim, const int64_t* dims,
+                                const double* coeffs, int radius, int64_t T, void* stream);
+
 /* Message describing the last failing call on this thread ("" if none).  The
  * pointer stays valid until the thread's next call into the library. */
 const char* stencil_fft_last_error(void);

@@ -15,6 +15,7 @@ from ._binding import (  # noqa: F401
     lib,
     library_path,
     periodic,
+    periodic_fields,
     plan_describe,
     profile_read,
     profile_start,

@@ -45,6 +45,8 @@ def _sig(name, res, args):
 
 
 _periodic = _sig("stencil_fft_periodic", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
+_periodic_fields = _sig("stencil_fft_periodic_fields", ctypes.c_int,
+                       [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
 _aperiodic = _sig("stencil_fft_aperiodic", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
 _last_error = _sig("stencil_fft_last_error", ctypes.c_char_p, [])
 _symbol_power = _sig("stencil_fft_symbol_power", ctypes.c_int, [_vp, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
@@ -122,6 +124,24 @@ def periodic(grid, coeffs, T: int, stream=None):
     with torch.cuda.device(grid.device):
         _check(_periodic(grid.data_ptr(), _dtype_code(grid), grid.dim(), dims,
                          c.ctypes.data_as(_dp), r, int(T), _stream(grid, stream)))
+    return grid
+
+
+def periodic_fields(grid, coeffs, T: int, stream=None):
+    """Evolve m coupled fields T steps in place: ``grid`` has shape (m, *dims),
+    ``coeffs`` shape (m, m, *(2r+1,)*ndim); block (i, j) weights field j's
+    neighbours in field i's update."""
+    import torch
+    _check_grid(grid)
+    m, d = grid.shape[0], grid.dim() - 1
+    c = np.ascontiguousarray(coeffs, dtype=np.float64)
+    if c.ndim != d + 2 or c.shape[:2] != (m, m):
+        raise ValueError(f"coefficients must have shape ({m}, {m}) + (2r+1,)*{d}, got {c.shape}")
+    _, r = _coeffs(c[0, 0], d)
+    dims = (ctypes.c_int64 * d)(*grid.shape[1:])
+    with torch.cuda.device(grid.device):
+        _check(_periodic_fields(grid.data_ptr(), _dtype_code(grid), m, d, dims, c.ctypes.data_as(_dp), r, int(T),
+                                _stream(grid, stream)))
     return grid
 
 

@@ -3,8 +3,10 @@
 #include <cstring>
 #include <functional>
 #include <string>
+#include <vector>
 
 #include "../../include/stencil_fft.h"
+#include "sfft_fields.h"
 #include "sfft_kernels.h"
 #include "sfft_runtime.h"
 
@@ -78,6 +80,66 @@ void solve_periodic_dense(void* grid, bool f64, int d, const int64_t* dims, int6
     run_plan(*plan, ws, v, v, keep, sp, st);
 }
 
+// m coupled periodic fields (field-major grid): forward transforms of all fields
+// as one batch, the symbol-matrix power per mode, inverse transforms.
+void solve_periodic_fields(void* grid, bool f64, int m, int d, const int64_t* dims, const double* coeffs, int r,
+                           int64_t T, hipStream_t st) {
+    DevCtx& ctx = device_ctx();
+    auto plan = ctx.plan(d, dims, m, f64, true);
+    void* ws = ctx.workspace(st, (size_t)plan->s.spec_elems * (f64 ? 16 : 8));
+    int nof = 1;
+    for (int a = 0; a < d; ++a) nof *= 2 * r + 1;
+    // K_ij = delta_ij - sum_o c_ij[o] (compensated sum), then the coefficients
+    std::vector<double> cK((size_t)m * m * (1 + nof));
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            const double* c = coeffs + ((size_t)i * m + j) * nof;
+            double sum = i == j ? 1.0 : 0.0, comp = 0.0;
+            for (int o = 0; o < nof; ++o) {
+                const double x = -c[o], t = sum + x;
+                comp += std::fabs(sum) >= std::fabs(x) ? (sum - t) + x : (x - t) + sum;
+                sum = t;
+            }
+            cK[(size_t)i * m + j] = sum + comp;
+        }
+    std::memcpy(cK.data() + (size_t)m * m, coeffs, sizeof(double) * (size_t)m * m * nof);
+    FieldParams fp;
+    fp.m = m;
+    fp.nof = nof;
+    fp.real_sym = 1;
+    for (int b = 0; b < m * m; ++b)
+        for (int o = 0; o < nof; ++o)
+            if (coeffs[(size_t)b * nof + o] != coeffs[(size_t)b * nof + (nof - 1 - o)]) fp.real_sym = 0;
+    fp.fstride = plan->s.spec_elems / m;
+    fp.pitch = plan->s.sym.sdim[d - 1];
+    fp.rows = fp.fstride / fp.pitch;
+    fp.ws = ws;
+    fp.cK = (const double*)ctx.upload(st, 60, cK.data(), sizeof(double) * cK.size());
+    SymParams sp = plan->s.sym;
+    sp.d = d;
+    sp.r = r;
+    sp.T = T;
+    double N = 1.0;
+    for (int a = 0; a < d; ++a) N *= (double)dims[a];
+    sp.scale = 1.0 / N;
+    int64_t cells = 1;
+    for (int a = 0; a < d; ++a) cells *= dims[a];
+    RealView v = dense_view(grid, d, dims);
+    v.boff = cells;
+    KeepRule keep;
+    std::memset(&keep, 0, sizeof(keep));
+    const int at = plan->s.sym_at;
+    run_plan(*plan, ws, v, v, keep, sp, st, 0, (size_t)at);
+    hipEvent_t ev = nullptr;
+    const bool prof = profiling();
+    if (prof) profile_launch_begin(st, &ev);
+    check_hip(launch_fields_symbol(fp, sp, f64, st), "fields symbol launch");
+    if (prof)
+        profile_launch_end(st, ev, f64 ? "fields_symbol_f64" : "fields_symbol_f32",
+                           2 * (int64_t)m * fp.rows * plan->s.sym.hcount * (f64 ? 16 : 8));
+    run_plan(*plan, ws, v, v, keep, sp, st, (size_t)at);
+}
+
 }  // namespace sfft
 
 extern "C" {
@@ -95,6 +157,24 @@ int stencil_fft_periodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* 
                 throw Error(SFFT_EUNSUPPORTED, "extent " + std::to_string(dims[a]) + " has a prime factor above 7");
         if (T == 0) return;
         solve_periodic_dense(grid, dtype == SFFT_F64, ndim, dims, 1, coeffs, radius, T, (hipStream_t)stream);
+    });
+}
+
+int stencil_fft_periodic_fields(void* grid, sfft_dtype dtype, int nfields, int ndim, const int64_t* dims,
+                                const double* coeffs, int radius, int64_t T, void* stream) {
+    return guarded([&] {
+        if (nfields < 1) throw Error(SFFT_EINVAL, "nfields must be >= 1");
+        if (nfields > kMaxFields) throw Error(SFFT_EUNSUPPORTED, "more than 4 fields are not supported");
+        validate(grid, dtype, ndim, dims, coeffs, radius, T);
+        int nof = 1;
+        for (int a = 0; a < ndim; ++a) nof *= 2 * radius + 1;
+        for (int i = 0; i < nfields * nfields * nof; ++i)
+            if (!std::isfinite(coeffs[i])) throw Error(SFFT_EINVAL, "coefficient " + std::to_string(i) + " is not finite");
+        for (int a = 0; a < ndim; ++a)
+            if (!is_7smooth(dims[a]))
+                throw Error(SFFT_EUNSUPPORTED, "extent " + std::to_string(dims[a]) + " has a prime factor above 7");
+        if (T == 0) return;
+        solve_periodic_fields(grid, dtype == SFFT_F64, nfields, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
     });
 }
 

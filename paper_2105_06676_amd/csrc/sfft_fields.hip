@@ -1,0 +1,253 @@
+// Symbol-matrix power for m coupled fields, applied to their spectra.
+//
+// Mode k of field i at time t+1 is sum_j Lambda_ij(k) x_j(k), Lambda_ij the symbol
+// of stencil (i, j) (appendix on vector-valued fields), so the T-step map is the
+// matrix power Lambda(k)^T, taken by binary repeated squaring of the matrix.  As
+// in the scalar path the power is carried in deviation form: D = I - Lambda,
+// squaring I - D gives I - (2D - D^2) and (I - V)(I - D) = I - (V + D - V D); every
+// matrix involved is a polynomial in Lambda, so the products commute.  The
+// deviation entries come from the per-axis phase tables E(m) = exp(2 pi i m / n) - 1
+// (a cell offset o contributes prod_a (1 + E_a) - 1, built axis by axis), so modes
+// near Lambda = I keep their relative accuracy.  One thread per mode, FP64
+// throughout; spectra are read and written in the solve's precision.
+#include <hip/hip_runtime.h>
+
+#include "sfft_device.h"
+#include "sfft_fields.h"
+
+namespace sfft {
+
+namespace {
+
+template <int M>
+__device__ __forceinline__ void matmul(const dcx (&a)[M][M], const dcx (&b)[M][M], dcx (&c)[M][M]) {
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            dcx s = dmul(a[i][0], b[0][j]);
+#pragma unroll
+            for (int k = 1; k < M; ++k) s = dadd(s, dmul(a[i][k], b[k][j]));
+            c[i][j] = s;
+        }
+}
+
+template <int M>
+__device__ __forceinline__ void matmul_real(const double (&a)[M][M], const double (&b)[M][M], double (&c)[M][M]) {
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            double s = a[i][0] * b[0][j];
+#pragma unroll
+            for (int k = 1; k < M; ++k) s = fma(a[i][k], b[k][j], s);
+            c[i][j] = s;
+        }
+}
+
+// Stored position -> frequency along axis a in 32-bit arithmetic (extents below 2^31).
+__device__ __forceinline__ uint32_t pos_to_freq32(const SymParams& sp, int a, uint32_t p) {
+    const int nl = sp.nlev[a];
+    if (nl <= 1) return p;
+    const uint32_t s0 = (uint32_t)sp.sub[a][0], s1 = (uint32_t)sp.sub[a][1];
+    if (nl == 2) {
+        const uint32_t d0 = p / s1, d1 = p - d0 * s1;
+        return d0 + s0 * d1;
+    }
+    const uint32_t s2 = (uint32_t)sp.sub[a][2];
+    const uint32_t d0 = p / (s1 * s2), rem = p - d0 * s1 * s2;
+    const uint32_t d1 = rem / s2, d2 = rem - d1 * s2;
+    return d0 + s0 * (d1 + s1 * d2);
+}
+
+// E(o f) of one axis from its E(f), E(2f): zero for o = 0, conjugate for o < 0.
+__device__ __forceinline__ dcx phase(const dcx (&Ea)[kMaxR + 1], int o) {
+    dcx e = (o == 1 || o == -1) ? Ea[1] : Ea[kMaxR];
+    if (o == 0) e = dcx{0.0, 0.0};
+    if (o < 0) e.y = -e.y;  // E(-m) = conj E(m)
+    return e;
+}
+
+// fn(q, dev) for every offset of the (2r+1)^d box, q row-major over o_0..o_{d-1},
+// dev = prod_a (1 + E_a(o_a f_a)) - 1 built axis by axis.
+template <typename F>
+__device__ __forceinline__ void for_each_offset(const SymParams& sp, const dcx (&E)[3][kMaxR + 1], F&& fn) {
+    const int r0 = sp.r, r1 = sp.d >= 2 ? sp.r : 0, r2 = sp.d >= 3 ? sp.r : 0;
+    int q = 0;
+    for (int o0 = -r0; o0 <= r0; ++o0) {
+        const dcx e0 = phase(E[0], o0);
+        for (int o1 = -r1; o1 <= r1; ++o1) {
+            const dcx e1 = phase(E[1], o1);
+            const dcx d01 = dadd(dadd(e0, e1), dmul(e0, e1));
+            for (int o2 = -r2; o2 <= r2; ++o2) {
+                const dcx e2 = phase(E[2], o2);
+                fn(q++, dadd(dadd(d01, e2), dmul(d01, e2)));
+            }
+        }
+    }
+}
+
+// A workgroup covers 256 consecutive entries of one spectrum row, so the row's
+// position (and its frequencies on axes 0..d-2) is the same for the whole group.
+template <typename R, int M>
+__global__ __launch_bounds__(256) void k_fields_symbol(FieldParams fp, SymParams sp) {
+    const uint32_t cpr = (uint32_t)((sp.hcount + 255) / 256);  // workgroups per row
+    const uint32_t row = blockIdx.x / cpr;
+    const uint32_t kl = (blockIdx.x - row * cpr) * 256 + threadIdx.x;
+    if (kl >= (uint32_t)sp.hcount) return;  // past the half spectrum
+    const int64_t idx = (int64_t)row * fp.pitch + kl;
+
+    // frequency of this position along every axis (stored order -> frequency)
+    uint32_t f[3] = {0, 0, 0};
+    {
+        uint32_t rem = row;
+#pragma unroll
+        for (int a = 1; a >= 0; --a) {
+            if (a <= sp.d - 2) {
+                const uint32_t sd = (uint32_t)sp.sdim[a];
+                const uint32_t q = rem / sd;
+                f[a] = pos_to_freq32(sp, a, rem - q * sd);
+                rem = q;
+            }
+        }
+    }
+    const int last = sp.d - 1;
+    if (last == 0) f[0] = kl;
+    else if (last == 1) f[1] = kl;
+    else f[2] = kl;
+
+    // E_a(o f_a) for o = 1..r on every axis
+    dcx E[3][kMaxR + 1];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int o = 0; o <= kMaxR; ++o) {
+            E[a][o] = dcx{0.0, 0.0};
+            if (a < sp.d && o >= 1 && o <= sp.r)
+                E[a][o] = ((const dcx*)sp.eph[a])[mul_mod_small((uint32_t)o, f[a], (uint32_t)sp.n[a])];
+        }
+
+    const double* cc = fp.cK + M * M;
+    cx<R>* ws = (cx<R>*)fp.ws;
+    dcx x[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+        const cx<R> v = ws[j * fp.fstride + idx];
+        x[j] = dcx{(double)v.x, (double)v.y};
+    }
+
+    if (fp.real_sym) {
+        // Point-symmetric blocks: the imaginary parts of offsets o and -o cancel,
+        // the symbol matrix is real and so are its powers.
+        double D[M][M], V[M][M], P[M][M];
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                D[i][j] = fp.cK[i * M + j];
+                V[i][j] = 0.0;
+            }
+        for_each_offset(sp, E, [&](int q, dcx dev) {
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int j = 0; j < M; ++j) D[i][j] = fma(-cc[(i * M + j) * fp.nof + q], dev.x, D[i][j]);
+        });
+        for (int64_t Rb = sp.T; Rb > 0; Rb >>= 1) {
+            if (Rb & 1) {
+                matmul_real<M>(V, D, P);
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+#pragma unroll
+                    for (int j = 0; j < M; ++j) V[i][j] = (V[i][j] + D[i][j]) - P[i][j];
+            }
+            if (Rb > 1) {
+                matmul_real<M>(D, D, P);
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+#pragma unroll
+                    for (int j = 0; j < M; ++j) D[i][j] = fma(2.0, D[i][j], -P[i][j]);
+            }
+        }
+        // y = (I - V) x * scale
+#pragma unroll
+        for (int i = 0; i < M; ++i) {
+            dcx y = x[i];
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                y.x = fma(-V[i][j], x[j].x, y.x);
+                y.y = fma(-V[i][j], x[j].y, y.y);
+            }
+            ws[i * fp.fstride + idx] = cx<R>{R(y.x * sp.scale), R(y.y * sp.scale)};
+        }
+        return;
+    }
+
+    // D = K - sum_o c_o * dev_o
+    dcx D[M][M], V[M][M], P[M][M];
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            D[i][j] = dcx{fp.cK[i * M + j], 0.0};
+            V[i][j] = dcx{0.0, 0.0};
+        }
+    for_each_offset(sp, E, [&](int q, dcx dev) {
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int j = 0; j < M; ++j) {
+                const double c = cc[(i * M + j) * fp.nof + q];
+                D[i][j].x = fma(-c, dev.x, D[i][j].x);
+                D[i][j].y = fma(-c, dev.y, D[i][j].y);
+            }
+    });
+    // V = I - Lambda^T by repeated squaring of I - D
+    for (int64_t Rb = sp.T; Rb > 0; Rb >>= 1) {
+        if (Rb & 1) {
+            matmul<M>(V, D, P);
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int j = 0; j < M; ++j) V[i][j] = dsub(dadd(V[i][j], D[i][j]), P[i][j]);
+        }
+        if (Rb > 1) {
+            matmul<M>(D, D, P);
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int j = 0; j < M; ++j) D[i][j] = dsub(dcx{2.0 * D[i][j].x, 2.0 * D[i][j].y}, P[i][j]);
+        }
+    }
+    // y = (I - V) x * scale
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        dcx y = x[i];
+#pragma unroll
+        for (int j = 0; j < M; ++j) y = dsub(y, dmul(V[i][j], x[j]));
+        ws[i * fp.fstride + idx] = cx<R>{R(y.x * sp.scale), R(y.y * sp.scale)};
+    }
+}
+
+template <typename R>
+hipError_t launch_m(const FieldParams& fp, const SymParams& sp, hipStream_t st) {
+    const int64_t cpr = (sp.hcount + 255) / 256;
+    if (fp.rows * cpr > 0x7fffffff) return hipErrorInvalidValue;
+    const dim3 g((unsigned)(fp.rows * cpr)), b(256);
+    switch (fp.m) {
+        case 1: hipLaunchKernelGGL((k_fields_symbol<R, 1>), g, b, 0, st, fp, sp); break;
+        case 2: hipLaunchKernelGGL((k_fields_symbol<R, 2>), g, b, 0, st, fp, sp); break;
+        case 3: hipLaunchKernelGGL((k_fields_symbol<R, 3>), g, b, 0, st, fp, sp); break;
+        case 4: hipLaunchKernelGGL((k_fields_symbol<R, 4>), g, b, 0, st, fp, sp); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fields_symbol(const FieldParams& fp, const SymParams& sp, bool f64, hipStream_t st) {
+    return f64 ? launch_m<double>(fp, sp, st) : launch_m<float>(fp, sp, st);
+}
+
+}  // namespace sfft

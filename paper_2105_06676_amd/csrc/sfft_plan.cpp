@@ -211,8 +211,9 @@ static void col_bytes(const Ctx& c, PassPlan& p, int64_t hcount) {
     p.model_bytes = elems * ((pd.in_real ? c.esz : c.csz) + (pd.out_real ? c.esz : c.csz));
 }
 
-int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* S, std::string* why) {
+int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* S, std::string* why, bool unfused) {
     *S = Schedule();
+    S->fused = !unfused;
     S->d = d;
     S->B = B;
     S->f64 = f64;
@@ -234,7 +235,34 @@ int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* S,
     sp.d = d;
     for (int a = 0; a < 3; ++a) sp.n[a] = a < d ? dims[a] : 1;
 
-    if (d == 1) {
+    if (d == 1 && unfused) {
+        // one row: R2C into the workspace, the spectral step, C2R back
+        const int64_t n = dims[0];
+        const bool half = (n % 2) == 0;
+        const int64_t L = half ? n / 2 : n;
+        if (L > row_single) {
+            *why = "1-D extent " + std::to_string(n) + " exceeds one LDS row";
+            return -2;
+        }
+        const int64_t h = n / 2 + 1;
+        const int64_t P = (h + 15) / 16 * 16;
+        sp.sdim[0] = P;
+        sp.hcount = h;
+        sp.nlev[0] = 1;
+        sp.sub[0][0] = n;
+        S->spec_elems = B * P;
+        PassPlan r0 = make_row(c, B, (int)L, half ? RT_HALF : RT_ODD, MODE_FWD, (int)n, (int)h, P);
+        r0.pd.in_real = 1;
+        r0.model_bytes = B * (n * c.esz + h * c.csz);
+        r0.name = "row_fwd_r2c";
+        S->passes.push_back(r0);
+        S->sym_at = 1;
+        PassPlan r1 = make_row(c, B, (int)L, half ? RT_HALF : RT_ODD, MODE_INV, (int)n, (int)h, P);
+        r1.pd.out_real = 1;
+        r1.model_bytes = B * (n * c.esz + h * c.csz);
+        r1.name = "row_inv_c2r";
+        S->passes.push_back(r1);
+    } else if (d == 1) {
         const int64_t n = dims[0];
         const bool half = (n % 2) == 0;
         const int64_t L = half ? n / 2 : n;
@@ -356,9 +384,17 @@ int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* S,
             for (int l = 0; l < (int)lev[a].size(); ++l) S->passes.push_back(level_pass(a, l, MODE_FWD));
         }
         const int n0 = (int)lev[0].size();
-        for (int l = 0; l < n0 - 1; ++l) S->passes.push_back(level_pass(0, l, MODE_FWD));
-        S->passes.push_back(level_pass(0, n0 - 1, MODE_MID));
-        for (int l = n0 - 2; l >= 0; --l) S->passes.push_back(level_pass(0, l, MODE_INV));
+        if (unfused) {
+            if (dims[0] > 1)
+                for (int l = 0; l < n0; ++l) S->passes.push_back(level_pass(0, l, MODE_FWD));
+            S->sym_at = (int)S->passes.size();
+            if (dims[0] > 1)
+                for (int l = n0 - 1; l >= 0; --l) S->passes.push_back(level_pass(0, l, MODE_INV));
+        } else {
+            for (int l = 0; l < n0 - 1; ++l) S->passes.push_back(level_pass(0, l, MODE_FWD));
+            S->passes.push_back(level_pass(0, n0 - 1, MODE_MID));
+            for (int l = n0 - 2; l >= 0; --l) S->passes.push_back(level_pass(0, l, MODE_INV));
+        }
         for (int a = 1; a <= d - 2; ++a) {
             if (dims[a] == 1) continue;
             for (int l = (int)lev[a].size() - 1; l >= 0; --l) S->passes.push_back(level_pass(a, l, MODE_INV));

@@ -43,6 +43,9 @@ struct Schedule {
     int64_t spec_elems = 0;   // complex elements of the spectrum workspace
     SymParams sym{};          // geometry part (n, nlev, sub, sdim, hcount)
     int64_t model_bytes = 0;  // sum over passes
+    bool fused = true;        // the middle pass multiplies by the symbol
+    int sym_at = -1;          // unfused: index of the first inverse pass (the whole
+                              // forward spectrum is in the workspace before it)
 };
 
 struct Tunables {
@@ -55,7 +58,10 @@ Tunables& tunables();
 
 bool is_7smooth(int64_t n);
 // 0 on success; on failure a message in *why.
-int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* out, std::string* why);
+// unfused: forward transform, a gap for an elementwise spectral step, then the
+// inverse transform (no fused middle pass; d = 1 needs a single row).
+int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* out, std::string* why,
+                   bool unfused = false);
 std::string describe_schedule(const Schedule& s);
 
 }  // namespace sfft

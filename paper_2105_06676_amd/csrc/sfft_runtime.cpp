@@ -72,9 +72,9 @@ const double2* DevCtx::phase_table(int64_t n) {
     return E;
 }
 
-std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f64) {
+std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f64, bool unfused) {
     std::ostringstream key;
-    key << d << ":" << B << ":" << f64 << ":" << tunables().col_max << ":" << tunables().no_fast;
+    key << d << ":" << B << ":" << f64 << ":" << tunables().col_max << ":" << tunables().no_fast << ":" << unfused;
     for (int a = 0; a < d; ++a) key << ":" << dims[a];
     {
         std::lock_guard<std::mutex> g(mu);
@@ -83,7 +83,7 @@ std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f
     }
     auto p = std::make_shared<Plan>();
     std::string why;
-    const int rc = build_schedule(d, dims, B, f64, &p->s, &why);
+    const int rc = build_schedule(d, dims, B, f64, &p->s, &why, unfused);
     if (rc) throw Error(rc == -1 ? -1 : -2, why);
     for (auto& pp : p->s.passes) {
         if (pp.lds_bytes > lds_max)
@@ -143,6 +143,26 @@ void* DevCtx::workspace(hipStream_t st, size_t bytes) {
         w.second = bytes;
     }
     return w.first;
+}
+
+void* DevCtx::upload(hipStream_t st, int slot, const void* host, size_t bytes) {
+    void* dev = scratch(st, slot, bytes);
+    std::lock_guard<std::mutex> g(mu);
+    auto& sg = staging[st];
+    if (!sg.second) check_hip(hipEventCreateWithFlags(&sg.second, hipEventDisableTiming), "hipEventCreate(staging)");
+    // the previous upload through this buffer must have been read by the device
+    check_hip(hipEventSynchronize(sg.second), "hipEventSynchronize(staging)");
+    if (sg.first.second < bytes) {
+        if (sg.first.first) check_hip(hipHostFree(sg.first.first), "hipHostFree(staging)");
+        sg.first.first = nullptr;
+        sg.first.second = 0;
+        check_hip(hipHostMalloc(&sg.first.first, bytes), "hipHostMalloc(staging)");
+        sg.first.second = bytes;
+    }
+    std::memcpy(sg.first.first, host, bytes);
+    check_hip(hipMemcpyAsync(dev, sg.first.first, bytes, hipMemcpyHostToDevice, st), "upload");
+    check_hip(hipEventRecord(sg.second, st), "hipEventRecord(staging)");
+    return dev;
 }
 
 hipStream_t DevCtx::side_stream(hipStream_t st, int i) {
@@ -238,7 +258,7 @@ void run_plan(const Plan& p, void* ws, const RealView& in, const RealView& out, 
               const SymParams& sym_in, hipStream_t st, size_t pass_begin, size_t pass_end) {
     const bool f64 = p.s.f64;
     SymParams sym = sym_in;
-    if (sym.d >= 2 && !sym.coltab) {
+    if (p.s.fused && sym.d >= 2 && !sym.coltab) {
         // per-column part of the symbol (axes 1..d-1), once per solve
         int64_t ncol = 1;
         for (int a = 1; a < sym.d; ++a) ncol *= sym.sdim[a];

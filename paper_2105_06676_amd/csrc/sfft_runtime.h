@@ -44,7 +44,7 @@ struct DevCtx {
     size_t lds_max = 0;
     hipStream_t tstream = nullptr;   // table generation
 
-    std::shared_ptr<Plan> plan(int d, const int64_t* dims, int64_t B, bool f64);
+    std::shared_ptr<Plan> plan(int d, const int64_t* dims, int64_t B, bool f64, bool unfused = false);
     const double2* phase_table(int64_t n);
     void* workspace(hipStream_t st, size_t bytes);
     void* scratch(hipStream_t st, int slot, size_t bytes);  // extra per-stream buffers
@@ -52,6 +52,11 @@ struct DevCtx {
     // Helper streams and events owned by a caller stream, for solves that fork
     // independent work off it and join it back (created on first use, default
     // priority, non-blocking).
+    // Copy `bytes` of host data into scratch slot `slot` of stream `st`, in stream
+    // order, through a pinned staging buffer of that stream (the host data may be
+    // released on return); returns the device pointer.
+    void* upload(hipStream_t st, int slot, const void* host, size_t bytes);
+    std::map<hipStream_t, std::pair<std::pair<void*, size_t>, hipEvent_t>> staging;
     hipStream_t side_stream(hipStream_t st, int i);
     hipEvent_t side_event(hipStream_t st, int i);
     std::map<std::pair<hipStream_t, int>, hipStream_t> sides;

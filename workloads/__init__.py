@@ -114,6 +114,7 @@ class Workload:
     aperiodic: bool = False
     dtypes: Tuple[str, ...] = ("f64",)
     notes: str = ""
+    fields: int = 1                # coupled fields (coeffs then (m, m) + (2r+1,)*ndim)
 
     @property
     def storage_dims(self) -> Tuple[int, ...]:
@@ -131,7 +132,12 @@ class Workload:
             v = gaussian(self.seed, "grid", n)
         else:
             raise ValueError(self.init)
-        return v.reshape(dims)
+        v = v.reshape(dims)
+        if self.fields > 1:
+            # every field starts from the same seeded array (a wave field at rest:
+            # the previous step equals the current one)
+            v = np.stack([v] * self.fields)
+        return v
 
 
 def heat1d_coeffs() -> np.ndarray:
@@ -142,6 +148,18 @@ def jacobi5_coeffs() -> np.ndarray:
     c = np.zeros((3, 3), dtype=np.float64)
     c[1, 1] = 0.2
     c[0, 1] = c[2, 1] = c[1, 0] = c[1, 2] = 0.2
+    return c
+
+
+def leapfrog2d_coeffs(kappa: float) -> np.ndarray:
+    """Second-order-in-time 2-D wave update a_{t+1} = 2 a_t - a_{t-1} + kappa * (5-point
+    Laplacian of a_t), as two fields (a_t, a_{t-1}): blocks (0,0) = 2 I + kappa Lap,
+    (0,1) = -I, (1,0) = I, (1,1) = 0.  Stable for kappa <= 1/2."""
+    c = np.zeros((2, 2, 3, 3), dtype=np.float64)
+    c[0, 0, 1, 1] = 2.0 - 4.0 * kappa
+    c[0, 0, 0, 1] = c[0, 0, 2, 1] = c[0, 0, 1, 0] = c[0, 0, 1, 2] = kappa
+    c[0, 1, 1, 1] = -1.0
+    c[1, 0, 1, 1] = 1.0
     return c
 
 
@@ -182,6 +200,10 @@ def config(name: str) -> Workload:
         return Workload("box2d_aperiodic_4096", 2, (4096, 4096), 1, 512, box_random_coeffs(4, 2, 1), 4,
                         "uniform", aperiodic=True, dtypes=("f64", "f32"),
                         notes="2-D aperiodic 9-point box, fixed frame")
+    if name == "wave2d_leapfrog_4096":
+        return Workload("wave2d_leapfrog_4096", 2, (4096, 4096), 1, 2048, leapfrog2d_coeffs(0.25), 6, "uniform",
+                        dtypes=("f32", "f64"), fields=2,
+                        notes="2-D leapfrog wave equation as two coupled periodic fields")
     raise KeyError(name)
 
 
