@@ -68,20 +68,28 @@ __device__ __forceinline__ dcx phase(const dcx (&Ea)[kMaxR + 1], int o) {
     return e;
 }
 
-// fn(q, dev) for every offset of the (2r+1)^d box, q row-major over o_0..o_{d-1},
-// dev = prod_a (1 + E_a(o_a f_a)) - 1 built axis by axis.
-template <typename F>
+// fn(q, dev) for the offsets of the (2r+1)^d box (DIM = d), q row-major over
+// o_0..o_{d-1}, dev = prod_a (1 + E_a(o_a f_a)) - 1 built axis by axis.  HALF:
+// only the offsets after the centre in that order (one of every pair o, -o), for
+// point-symmetric blocks.
+template <int DIM, bool HALF, typename F>
 __device__ __forceinline__ void for_each_offset(const SymParams& sp, const dcx (&E)[3][kMaxR + 1], F&& fn) {
-    const int r0 = sp.r, r1 = sp.d >= 2 ? sp.r : 0, r2 = sp.d >= 3 ? sp.r : 0;
-    int q = 0;
-    for (int o0 = -r0; o0 <= r0; ++o0) {
+    const int r = sp.r, w = 2 * r + 1;
+    const int r1 = DIM >= 2 ? r : 0, r2 = DIM >= 3 ? r : 0;
+    for (int o0 = HALF ? 0 : -r; o0 <= r; ++o0) {
         const dcx e0 = phase(E[0], o0);
-        for (int o1 = -r1; o1 <= r1; ++o1) {
+        for (int o1 = (HALF && o0 == 0) ? 0 : -r1; o1 <= r1; ++o1) {
             const dcx e1 = phase(E[1], o1);
-            const dcx d01 = dadd(dadd(e0, e1), dmul(e0, e1));
-            for (int o2 = -r2; o2 <= r2; ++o2) {
-                const dcx e2 = phase(E[2], o2);
-                fn(q++, dadd(dadd(d01, e2), dmul(d01, e2)));
+            const dcx d01 = DIM >= 2 ? dadd(dadd(e0, e1), dmul(e0, e1)) : e0;
+            const int q01 = DIM >= 2 ? (o0 + r) * w + (o1 + r) : o0 + r;
+            for (int o2 = (HALF && o0 == 0 && o1 == 0) ? (DIM >= 3 ? 1 : 0) : -r2; o2 <= r2; ++o2) {
+                if (HALF && DIM < 3 && o0 == 0 && o1 == 0) continue;  // the centre
+                if (DIM >= 3) {
+                    const dcx e2 = phase(E[2], o2);
+                    fn(q01 * w + (o2 + r), dadd(dadd(d01, e2), dmul(d01, e2)));
+                } else {
+                    fn(q01, d01);
+                }
             }
         }
     }
@@ -89,7 +97,7 @@ __device__ __forceinline__ void for_each_offset(const SymParams& sp, const dcx (
 
 // A workgroup covers 256 consecutive entries of one spectrum row, so the row's
 // position (and its frequencies on axes 0..d-2) is the same for the whole group.
-template <typename R, int M>
+template <typename R, int M, int DIM>
 __global__ __launch_bounds__(256) void k_fields_symbol(FieldParams fp, SymParams sp) {
     const uint32_t cpr = (uint32_t)((sp.hcount + 255) / 256);  // workgroups per row
     const uint32_t row = blockIdx.x / cpr;
@@ -147,11 +155,13 @@ __global__ __launch_bounds__(256) void k_fields_symbol(FieldParams fp, SymParams
                 D[i][j] = fp.cK[i * M + j];
                 V[i][j] = 0.0;
             }
-        for_each_offset(sp, E, [&](int q, dcx dev) {
+        // offsets o and -o share Re(dev) and their coefficient
+        for_each_offset<DIM, true>(sp, E, [&](int q, dcx dev) {
+            const double d2 = 2.0 * dev.x;
 #pragma unroll
             for (int i = 0; i < M; ++i)
 #pragma unroll
-                for (int j = 0; j < M; ++j) D[i][j] = fma(-cc[(i * M + j) * fp.nof + q], dev.x, D[i][j]);
+                for (int j = 0; j < M; ++j) D[i][j] = fma(-cc[(i * M + j) * fp.nof + q], d2, D[i][j]);
         });
         for (int64_t Rb = sp.T; Rb > 0; Rb >>= 1) {
             if (Rb & 1) {
@@ -192,7 +202,7 @@ __global__ __launch_bounds__(256) void k_fields_symbol(FieldParams fp, SymParams
             D[i][j] = dcx{fp.cK[i * M + j], 0.0};
             V[i][j] = dcx{0.0, 0.0};
         }
-    for_each_offset(sp, E, [&](int q, dcx dev) {
+    for_each_offset<DIM, false>(sp, E, [&](int q, dcx dev) {
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
@@ -234,13 +244,21 @@ hipError_t launch_m(const FieldParams& fp, const SymParams& sp, hipStream_t st) 
     const int64_t cpr = (sp.hcount + 255) / 256;
     if (fp.rows * cpr > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 g((unsigned)(fp.rows * cpr)), b(256);
+#define SFFT_FIELDS_M(MM)                                                                       \
+    switch (sp.d) {                                                                              \
+        case 1: hipLaunchKernelGGL((k_fields_symbol<R, MM, 1>), g, b, 0, st, fp, sp); break;      \
+        case 2: hipLaunchKernelGGL((k_fields_symbol<R, MM, 2>), g, b, 0, st, fp, sp); break;      \
+        case 3: hipLaunchKernelGGL((k_fields_symbol<R, MM, 3>), g, b, 0, st, fp, sp); break;      \
+        default: return hipErrorInvalidValue;                                                    \
+    }
     switch (fp.m) {
-        case 1: hipLaunchKernelGGL((k_fields_symbol<R, 1>), g, b, 0, st, fp, sp); break;
-        case 2: hipLaunchKernelGGL((k_fields_symbol<R, 2>), g, b, 0, st, fp, sp); break;
-        case 3: hipLaunchKernelGGL((k_fields_symbol<R, 3>), g, b, 0, st, fp, sp); break;
-        case 4: hipLaunchKernelGGL((k_fields_symbol<R, 4>), g, b, 0, st, fp, sp); break;
+        case 1: SFFT_FIELDS_M(1) break;
+        case 2: SFFT_FIELDS_M(2) break;
+        case 3: SFFT_FIELDS_M(3) break;
+        case 4: SFFT_FIELDS_M(4) break;
         default: return hipErrorInvalidValue;
     }
+#undef SFFT_FIELDS_M
     return hipGetLastError();
 }
 
