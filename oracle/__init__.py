@@ -17,6 +17,14 @@ Contents
     T sweeps of the periodic loop for m coupled scalar fields (the vector-valued
     extension of Sec. 3 and its appendix): field i at t+1 is the sum over j of
     stencil (i, j) applied to field j at t.
+``implicit_periodic(a, q, s, T)``
+    Implicit stencils (appendix on implicit stencils): each step solves
+    ``Q a_{t+1} = S a_t`` with the Moore-Penrose pseudo-inverse of the circulant
+    matrix Q, ``a_{t+1} = Q^+ S a_t`` (the minimum-norm least-squares solution;
+    for circulant Q this is the paper's inverse-or-zero rule per eigenvalue).  The
+    matrices are built from their definition; ``S a`` is one sweep of the loop, the
+    solve is a sparse LU when Q is nonsingular and a dense pseudo-inverse (SVD)
+    otherwise.
 ``symbol(coeffs, dims)``
     Step 1(i) of the periodic algorithm written literally: build the first column
     ``s`` of the circulant matrix and take its N-point DFT (appendix, eigenvalue-FFT
@@ -111,6 +119,58 @@ def periodic_fields(a: np.ndarray, coeffs: np.ndarray, T: int, nthreads: int = 0
     rc = _load().oracle_periodic_fields(x.ctypes.data, m, d, dims, c.ctypes.data, r, int(T), int(nthreads))
     if rc != 0:
         raise RuntimeError(f"oracle_periodic_fields failed ({rc})")
+    return x
+
+
+def stencil_matrix(coeffs: np.ndarray, dims: Sequence[int]):
+    """The N x N periodic stencil matrix (scipy CSR): row i holds c[o] at column
+    (i + o) mod n (the periodic loop's neighbour convention), duplicates summed."""
+    import scipy.sparse as sp
+    c = np.asarray(coeffs, dtype=np.float64)
+    d = len(dims)
+    r = (c.shape[0] - 1) // 2
+    N = int(np.prod(dims))
+    cells = np.arange(N)
+    coords = np.unravel_index(cells, tuple(dims))
+    rows, cols, vals = [], [], []
+    for off in np.ndindex(*c.shape):
+        w = c[off]
+        if w == 0.0:
+            continue
+        nb = tuple((coords[a] + (off[a] - r)) % dims[a] for a in range(d))
+        rows.append(cells)
+        cols.append(np.ravel_multi_index(nb, tuple(dims)))
+        vals.append(np.full(N, w))
+    if not rows:
+        return sp.csr_matrix((N, N))
+    return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N))
+
+
+def implicit_periodic(a: np.ndarray, q: np.ndarray, s: np.ndarray, T: int, rcond: float = 1e-13) -> np.ndarray:
+    """``a_T`` of ``Q a_{t+1} = S a_t`` on a periodic grid: ``a_{t+1} = Q^+ (S a_t)``.
+    ``rcond``: singular values below rcond * (largest) count as zero when Q is singular."""
+    import scipy.sparse.linalg as spla
+    x = np.ascontiguousarray(a, dtype=np.float64).copy()
+    qq = np.ascontiguousarray(q, dtype=np.float64)
+    ss = np.ascontiguousarray(s, dtype=np.float64)
+    _check_coeffs(qq, x.ndim)
+    _check_coeffs(ss, x.ndim)
+    dims = x.shape
+    Q = stencil_matrix(qq, dims).tocsc()
+    solve = None
+    try:
+        lu = spla.splu(Q)
+        # a usable factorisation: no (near-)zero pivot
+        piv = np.abs(lu.U.diagonal())
+        if piv.min() > rcond * max(piv.max(), 1e-300):
+            solve = lu.solve
+    except RuntimeError:
+        solve = None
+    if solve is None:
+        Qp = np.linalg.pinv(Q.toarray(), rcond=rcond)
+        solve = lambda b: Qp @ b  # noqa: E731
+    for _ in range(int(T)):
+        x = solve(periodic(x, ss, 1).reshape(-1)).reshape(dims)
     return x
 
 
