@@ -171,7 +171,11 @@ def time_solve(sfft, torch, w, dtype, reps=5, warmup=1):
     td = torch.float32 if dtype == "f32" else torch.float64
     grid0 = torch.from_numpy(w.grid()).to(device="cuda:0", dtype=td)
     grid = grid0.clone()
-    fn = sfft.aperiodic if w.aperiodic else (sfft.periodic_fields if w.fields > 1 else sfft.periodic)
+    if w.implicit_q is not None:
+        def fn(g, c, T):
+            return sfft.periodic_implicit(g, w.implicit_q, c, T)
+    else:
+        fn = sfft.aperiodic if w.aperiodic else (sfft.periodic_fields if w.fields > 1 else sfft.periodic)
     for _ in range(warmup):
         fn(grid, w.coeffs, w.T)
     ts = []
@@ -195,11 +199,12 @@ def other_workloads(sfft, torch):
     import workloads as wl
     out = {}
     for name, dts in (("heat1d_65536", ("f64",)), ("star3d_512", ("f32",)),
-                      ("box2d_aperiodic_4096", ("f64", "f32")), ("wave2d_leapfrog_4096", ("f32", "f64"))):
+                      ("box2d_aperiodic_4096", ("f64", "f32")), ("wave2d_leapfrog_4096", ("f32", "f64")),
+                      ("heat2d_backward_euler_4096", ("f32", "f64"))):
         w = wl.config(name)
         for dt in dts:
             out[f"{name}_{dt}"] = dict(time_solve(sfft, torch, w, dt), dims=list(w.dims), T=w.T,
-                                       aperiodic=w.aperiodic, fields=w.fields)
+                                       aperiodic=w.aperiodic, fields=w.fields, implicit=w.implicit_q is not None)
     return out
 
 

@@ -120,6 +120,21 @@ int stencil_fft_aperiodic(void* grid, sfft_dtype dtype, int ndim, const int64_t*
 int stencil_fft_periodic_fields(void* grid, sfft_dtype dtype, int nfields, int ndim, const int64_t* dims,
                                 const double* coeffs, int radius, int64_t T, void* stream);
 
+/*
+ * Implicit stencils (the appendix on implicit stencils): the update
+ * Q a_{t+1} = S a_t on a periodic grid, with both Q and S linear stencils.  Every
+ * mode evolves by lambda_R = lambda_S / lambda_Q, and by 0 where lambda_Q vanishes
+ * (the pseudo-inverse of Q; |lambda_Q| at or below 16 * DBL_EPSILON * sum |q| counts
+ * as zero), raised to the power T in FP64.
+ *   q_coeffs, s_coeffs  HOST pointers to (2*radius+1)^ndim doubles each, laid out
+ *                       like the scalar coefficients; copied before return.
+ * Other arguments, extent rules and errors as for stencil_fft_periodic_fields with
+ * one field.
+ */
+int stencil_fft_periodic_implicit(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims,
+                                  const double* q_coeffs, const double* s_coeffs, int radius, int64_t T,
+                                  void* stream);
+
 /* Message describing the last failing call on this thread ("" if none).  The
  * pointer stays valid until the thread's next call into the library. */
 const char* stencil_fft_last_error(void);

@@ -47,6 +47,8 @@ def _sig(name, res, args):
 _periodic = _sig("stencil_fft_periodic", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
 _periodic_fields = _sig("stencil_fft_periodic_fields", ctypes.c_int,
                        [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
+_periodic_implicit = _sig("stencil_fft_periodic_implicit", ctypes.c_int,
+                         [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, _dp, ctypes.c_int, ctypes.c_int64, _vp])
 _aperiodic = _sig("stencil_fft_aperiodic", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
 _last_error = _sig("stencil_fft_last_error", ctypes.c_char_p, [])
 _symbol_power = _sig("stencil_fft_symbol_power", ctypes.c_int, [_vp, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
@@ -142,6 +144,22 @@ def periodic_fields(grid, coeffs, T: int, stream=None):
     with torch.cuda.device(grid.device):
         _check(_periodic_fields(grid.data_ptr(), _dtype_code(grid), m, d, dims, c.ctypes.data_as(_dp), r, int(T),
                                 _stream(grid, stream)))
+    return grid
+
+
+def periodic_implicit(grid, q_coeffs, s_coeffs, T: int, stream=None):
+    """Evolve ``grid`` T steps in place under the implicit update Q a_{t+1} = S a_t
+    (both stencils (2r+1,)*ndim arrays of the same radius)."""
+    import torch
+    _check_grid(grid)
+    q, r = _coeffs(q_coeffs, grid.dim())
+    s_, r2 = _coeffs(s_coeffs, grid.dim())
+    if r != r2:
+        raise ValueError("Q and S must have the same radius (pad the smaller with zeros)")
+    dims = (ctypes.c_int64 * grid.dim())(*grid.shape)
+    with torch.cuda.device(grid.device):
+        _check(_periodic_implicit(grid.data_ptr(), _dtype_code(grid), grid.dim(), dims, q.ctypes.data_as(_dp),
+                                  s_.ctypes.data_as(_dp), r, int(T), _stream(grid, stream)))
     return grid
 
 

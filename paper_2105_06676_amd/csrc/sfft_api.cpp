@@ -82,8 +82,9 @@ void solve_periodic_dense(void* grid, bool f64, int d, const int64_t* dims, int6
 
 // m coupled periodic fields (field-major grid): forward transforms of all fields
 // as one batch, the symbol-matrix power per mode, inverse transforms.
+// q_coeffs (m = 1 only): the implicit part Q of Q a_{t+1} = S a_t, S = coeffs.
 void solve_periodic_fields(void* grid, bool f64, int m, int d, const int64_t* dims, const double* coeffs, int r,
-                           int64_t T, hipStream_t st) {
+                           int64_t T, hipStream_t st, const double* q_coeffs = nullptr) {
     DevCtx& ctx = device_ctx();
     auto plan = ctx.plan(d, dims, m, f64, true);
     void* ws = ctx.workspace(st, (size_t)plan->s.spec_elems * (f64 ? 16 : 8));
@@ -103,10 +104,23 @@ void solve_periodic_fields(void* grid, bool f64, int m, int d, const int64_t* di
             cK[(size_t)i * m + j] = sum + comp;
         }
     std::memcpy(cK.data() + (size_t)m * m, coeffs, sizeof(double) * (size_t)m * m * nof);
+    double qabs = 0.0;
+    if (q_coeffs) {
+        // 1 - sum q (compensated) and q, after S's block
+        double sum = 1.0, comp = 0.0;
+        for (int o = 0; o < nof; ++o) {
+            const double x = -q_coeffs[o], t = sum + x;
+            comp += std::fabs(sum) >= std::fabs(x) ? (sum - t) + x : (x - t) + sum;
+            sum = t;
+            qabs += std::fabs(q_coeffs[o]);
+        }
+        cK.push_back(sum + comp);
+        cK.insert(cK.end(), q_coeffs, q_coeffs + nof);
+    }
     FieldParams fp;
     fp.m = m;
     fp.nof = nof;
-    fp.real_sym = 1;
+    fp.real_sym = q_coeffs ? 0 : 1;
     for (int b = 0; b < m * m; ++b)
         for (int o = 0; o < nof; ++o)
             if (coeffs[(size_t)b * nof + o] != coeffs[(size_t)b * nof + (nof - 1 - o)]) fp.real_sym = 0;
@@ -115,6 +129,10 @@ void solve_periodic_fields(void* grid, bool f64, int m, int d, const int64_t* di
     fp.rows = fp.fstride / fp.pitch;
     fp.ws = ws;
     fp.cK = (const double*)ctx.upload(st, 60, cK.data(), sizeof(double) * cK.size());
+    fp.implicit = q_coeffs ? 1 : 0;
+    fp.qK = q_coeffs ? fp.cK + (size_t)m * m * (1 + nof) : nullptr;
+    // lambda_Q counts as zero below the rounding bound of its evaluation
+    fp.qzero = 16.0 * 2.220446049250313e-16 * qabs;
     SymParams sp = plan->s.sym;
     sp.d = d;
     sp.r = r;
@@ -175,6 +193,21 @@ int stencil_fft_periodic_fields(void* grid, sfft_dtype dtype, int nfields, int n
                 throw Error(SFFT_EUNSUPPORTED, "extent " + std::to_string(dims[a]) + " has a prime factor above 7");
         if (T == 0) return;
         solve_periodic_fields(grid, dtype == SFFT_F64, nfields, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
+    });
+}
+
+int stencil_fft_periodic_implicit(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims,
+                                  const double* q_coeffs, const double* s_coeffs, int radius, int64_t T,
+                                  void* stream) {
+    return guarded([&] {
+        validate(grid, dtype, ndim, dims, s_coeffs, radius, T);
+        validate(grid, dtype, ndim, dims, q_coeffs, radius, T);
+        for (int a = 0; a < ndim; ++a)
+            if (!is_7smooth(dims[a]))
+                throw Error(SFFT_EUNSUPPORTED, "extent " + std::to_string(dims[a]) + " has a prime factor above 7");
+        if (T == 0) return;
+        solve_periodic_fields(grid, dtype == SFFT_F64, 1, ndim, dims, s_coeffs, radius, T, (hipStream_t)stream,
+                              q_coeffs);
     });
 }
 

@@ -21,6 +21,11 @@ struct FieldParams {
     int64_t fstride;   // complex elements per field
     void* ws;          // spectra, field-major
     const double* cK;  // K[i][j] = delta_ij - sum_o c_ij[o] (m*m), then c[i][j][o] (m*m*nof)
+    // Implicit stencil (m = 1): Q a_{t+1} = S a_t, S given by cK; qK = 1 - sum_o q[o],
+    // then q[o]; modes with |lambda_Q| <= qzero take lambda_R = 0 (pseudo-inverse).
+    int implicit;
+    const double* qK;
+    double qzero;
 };
 
 hipError_t launch_fields_symbol(const FieldParams& fp, const SymParams& sp, bool f64, hipStream_t st);

@@ -144,6 +144,34 @@ __global__ __launch_bounds__(256) void k_fields_symbol(FieldParams fp, SymParams
         x[j] = dcx{(double)v.x, (double)v.y};
     }
 
+    if (M == 1 && fp.implicit) {
+        // lambda_R = lambda_S / lambda_Q, or 0 where lambda_Q vanishes; in deviation
+        // form mu_R = 1 - lambda_R = (mu_S - mu_Q) / (1 - mu_Q)
+        dcx muS = {cc[-1], 0.0}, muQ = {fp.qK[0], 0.0};
+        const double* qc = fp.qK + 1;
+        for_each_offset<DIM, false>(sp, E, [&](int q, dcx dev) {
+            muS.x = fma(-cc[q], dev.x, muS.x);
+            muS.y = fma(-cc[q], dev.y, muS.y);
+            muQ.x = fma(-qc[q], dev.x, muQ.x);
+            muQ.y = fma(-qc[q], dev.y, muQ.y);
+        });
+        const dcx lq = {1.0 - muQ.x, -muQ.y};
+        const double lq2 = lq.x * lq.x + lq.y * lq.y;
+        dcx D = {1.0, 0.0};
+        if (lq2 > fp.qzero * fp.qzero) {
+            const dcx num = dsub(muS, muQ);
+            D = dcx{(num.x * lq.x + num.y * lq.y) / lq2, (num.y * lq.x - num.x * lq.y) / lq2};
+        }
+        dcx V = {0.0, 0.0};
+        for (int64_t Rb = sp.T; Rb > 0; Rb >>= 1) {
+            if (Rb & 1) V = dsub(dadd(V, D), dmul(V, D));
+            if (Rb > 1) D = dsub(dcx{2.0 * D.x, 2.0 * D.y}, dmul(D, D));
+        }
+        const dcx y = dsub(x[0], dmul(V, x[0]));
+        ws[idx] = cx<R>{R(y.x * sp.scale), R(y.y * sp.scale)};
+        return;
+    }
+
     if (fp.real_sym) {
         // Point-symmetric blocks: the imaginary parts of offsets o and -o cancel,
         // the symbol matrix is real and so are its powers.

@@ -115,6 +115,7 @@ class Workload:
     dtypes: Tuple[str, ...] = ("f64",)
     notes: str = ""
     fields: int = 1                # coupled fields (coeffs then (m, m) + (2r+1,)*ndim)
+    implicit_q: Optional[np.ndarray] = None  # implicit update Q a_{t+1} = S a_t (coeffs = S)
 
     @property
     def storage_dims(self) -> Tuple[int, ...]:
@@ -148,6 +149,20 @@ def jacobi5_coeffs() -> np.ndarray:
     c = np.zeros((3, 3), dtype=np.float64)
     c[1, 1] = 0.2
     c[0, 1] = c[2, 1] = c[1, 0] = c[1, 2] = 0.2
+    return c
+
+
+def identity_coeffs(ndim: int) -> np.ndarray:
+    c = np.zeros((3,) * ndim, dtype=np.float64)
+    c[(1,) * ndim] = 1.0
+    return c
+
+
+def backward_euler2d_q(kappa: float) -> np.ndarray:
+    """Q = I - kappa * (5-point Laplacian): the implicit side of a backward-Euler heat step."""
+    c = np.zeros((3, 3), dtype=np.float64)
+    c[1, 1] = 1.0 + 4.0 * kappa
+    c[0, 1] = c[2, 1] = c[1, 0] = c[1, 2] = -kappa
     return c
 
 
@@ -200,6 +215,10 @@ def config(name: str) -> Workload:
         return Workload("box2d_aperiodic_4096", 2, (4096, 4096), 1, 512, box_random_coeffs(4, 2, 1), 4,
                         "uniform", aperiodic=True, dtypes=("f64", "f32"),
                         notes="2-D aperiodic 9-point box, fixed frame")
+    if name == "heat2d_backward_euler_4096":
+        return Workload("heat2d_backward_euler_4096", 2, (4096, 4096), 1, 1000, identity_coeffs(2), 7, "uniform",
+                        dtypes=("f32", "f64"), implicit_q=backward_euler2d_q(2.0),
+                        notes="2-D backward-Euler heat step (I - kappa Lap) a_{t+1} = a_t, kappa = 2")
     if name == "wave2d_leapfrog_4096":
         return Workload("wave2d_leapfrog_4096", 2, (4096, 4096), 1, 2048, leapfrog2d_coeffs(0.25), 6, "uniform",
                         dtypes=("f32", "f64"), fields=2,
