@@ -200,7 +200,7 @@ def other_workloads(sfft, torch):
     out = {}
     for name, dts in (("heat1d_65536", ("f64",)), ("star3d_512", ("f32",)),
                       ("box2d_aperiodic_4096", ("f64", "f32")), ("wave2d_leapfrog_4096", ("f32", "f64")),
-                      ("heat2d_backward_euler_4096", ("f32", "f64"))):
+                      ("heat2d_backward_euler_4096", ("f32", "f64")), ("jacobi2d_8191_prime", ("f32",))):
         w = wl.config(name)
         for dt in dts:
             out[f"{name}_{dt}"] = dict(time_solve(sfft, torch, w, dt), dims=list(w.dims), T=w.T,

@@ -39,8 +39,9 @@
  *
  * Errors: SFFT_EINVAL (null pointer, ndim outside 1..3, an extent < 1,
  * radius < 0, T < 0, a non-finite coefficient, an unknown dtype);
- * SFFT_EUNSUPPORTED (a shape the FFT planner cannot handle, e.g. a periodic
- * extent with a prime factor above 7); SFFT_ENOMEM (device workspace);
+ * SFFT_EUNSUPPORTED (a shape the FFT planner cannot handle, e.g. a prime factor
+ * above 7 in an extent of the batched, serving, fields or implicit entry points);
+ * SFFT_ENOMEM (device workspace);
  * SFFT_EHIP (a HIP runtime error; the grid is then unspecified).  When
  * validation fails the grid is untouched.
  *
@@ -75,7 +76,11 @@ enum {
  * d-D grids).  grid holds prod(dims) cells; on return (once the stream has run)
  * it holds a_T = S^T a_0 with periodic wrap on every axis.  Extents smaller than
  * 2*radius+1 are legal; offsets then alias modulo the extent exactly as the
- * periodic loop's modulo does.  Every extent must be 7-smooth (2^a 3^b 5^c 7^d).
+ * periodic loop's modulo does.  Any extent from 1 to 2^30 is accepted: when every
+ * extent is 7-smooth (2^a 3^b 5^c 7^d) the real-to-complex pass schedule runs;
+ * otherwise each axis with a prime factor above 7 takes its DFT by Bluestein's
+ * chirp-z algorithm (a circular convolution of a 7-smooth length >= 2n - 1) and
+ * the others complex transforms, several times slower than a 7-smooth extent.
  * Accuracy: relative L2 error against the exact result about 1e-6 (F32) and
  * 1e-14 (F64) for stable stencils; the symbol power is always FP64.
  */

@@ -16,6 +16,8 @@ void profile_enable(bool on);
 std::string profile_json();
 void solve_aperiodic_cached(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
                      hipStream_t st);
+void solve_periodic_any(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
+                        hipStream_t st);
 }  // namespace sfft
 
 using namespace sfft;
@@ -170,11 +172,16 @@ int stencil_fft_periodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* 
                          int radius, int64_t T, void* stream) {
     return guarded([&] {
         validate(grid, dtype, ndim, dims, coeffs, radius, T);
-        for (int a = 0; a < ndim; ++a)
-            if (!is_7smooth(dims[a]))
-                throw Error(SFFT_EUNSUPPORTED, "extent " + std::to_string(dims[a]) + " has a prime factor above 7");
+        bool smooth = true;
+        for (int a = 0; a < ndim; ++a) {
+            if (dims[a] > ((int64_t)1 << 30)) throw Error(SFFT_EUNSUPPORTED, "extents above 2^30 are not supported");
+            smooth = smooth && is_7smooth(dims[a]);
+        }
         if (T == 0) return;
-        solve_periodic_dense(grid, dtype == SFFT_F64, ndim, dims, 1, coeffs, radius, T, (hipStream_t)stream);
+        if (smooth)
+            solve_periodic_dense(grid, dtype == SFFT_F64, ndim, dims, 1, coeffs, radius, T, (hipStream_t)stream);
+        else
+            solve_periodic_any(grid, dtype == SFFT_F64, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
     });
 }
 

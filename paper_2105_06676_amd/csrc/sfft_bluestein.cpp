@@ -1,0 +1,176 @@
+// Periodic solves on any extents (Sec. 3 Steps 1-4 with the DFT of a length
+// that has a prime factor above 7 taken by Bluestein's chirp-z algorithm).
+//
+// The grid is widened to a complex array; each axis is transformed in turn (a
+// 7-smooth axis by the complex pass kernels in place, digit-reversed across its
+// factor levels; any other axis by chirp-multiply and zero-pad to a 7-smooth
+// length M >= 2n - 1, forward transform, product with the transformed chirp
+// kernel, inverse transform, extract and chirp-multiply: natural order); every
+// spectral element is multiplied by lambda(k)^T / N; the inverse runs the same way
+// in reverse order with conjugate chirps; the real part is stored back.
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "sfft_bluestein.h"
+#include "sfft_runtime.h"
+
+namespace sfft {
+
+namespace {
+
+int64_t smooth_at_least(int64_t n) {
+    while (!is_7smooth(n)) ++n;
+    return n;
+}
+
+// Convolution length for an axis of n points: a power of two (whose transforms
+// run on the register radix-16 kernels, several times faster than the generic
+// mixed-radix ones) unless that pads more than 2x the next 7-smooth length.
+int64_t conv_len(int64_t n) {
+    const int64_t need = 2 * n - 1;
+    int64_t p = 1;
+    while (p < need) p *= 2;
+    const int64_t s = smooth_at_least(need);
+    return p <= 2 * s ? p : s;
+}
+
+struct BlueTables {
+    double2* chirp[2] = {nullptr, nullptr};  // forward (sign -1), inverse (sign +1)
+    void* H[2] = {nullptr, nullptr};         // transformed chirp kernels / M, natural order
+};
+
+std::mutex g_blue_mu;
+std::map<std::tuple<int, int64_t, int64_t, bool>, BlueTables> g_blue;
+
+AxisOrder order_of(const Plan& p) {
+    AxisOrder o;
+    std::memset(&o, 0, sizeof(o));
+    o.nlev = p.s.sym.nlev[0];
+    for (int i = 0; i < 3; ++i) o.sub[i] = p.s.sym.sub[0][i];
+    return o;
+}
+
+// Enqueue one elementwise launch, timed under `name` when profiling is on.
+template <typename F>
+void timed(hipStream_t st, const char* name, bool f64, int64_t bytes, F&& launch) {
+    hipEvent_t ev = nullptr;
+    const bool prof = profiling();
+    if (prof) profile_launch_begin(st, &ev);
+    check_hip(launch(), name);
+    if (prof) profile_launch_end(st, ev, std::string(name) + (f64 ? "_f64" : "_f32"), bytes);
+}
+
+void run_passes(const Plan& p, void* buf, hipStream_t st) {
+    if (p.pd.empty()) return;
+    RealView v;
+    std::memset(&v, 0, sizeof(v));
+    KeepRule keep;
+    std::memset(&keep, 0, sizeof(keep));
+    SymParams sp;
+    std::memset(&sp, 0, sizeof(sp));
+    run_plan(p, buf, v, v, keep, sp, st);
+}
+
+// Tables of an axis of n points convolved at length M (built once per device).
+const BlueTables& blue_tables(int64_t n, int64_t M, bool f64, hipStream_t st) {
+    DevCtx& ctx = device_ctx();
+    const auto key = std::make_tuple(ctx.device, n, M, f64);
+    std::lock_guard<std::mutex> g(g_blue_mu);
+    auto it = g_blue.find(key);
+    if (it != g_blue.end()) return it->second;
+    BlueTables t;
+    const size_t csz = f64 ? 16 : 8;
+    auto fwd = ctx.axis_plan(1, M, 1, f64, false);
+    void* tmp = nullptr;
+    check_hip(hipMalloc(&tmp, (size_t)M * csz), "hipMalloc(chirp kernel)");
+    for (int k = 0; k < 2; ++k) {
+        check_hip(hipMalloc(&t.chirp[k], sizeof(double2) * (size_t)n), "hipMalloc(chirp)");
+        check_hip(hipMalloc(&t.H[k], (size_t)M * csz), "hipMalloc(chirp spectrum)");
+        check_hip(launch_chirp(t.chirp[k], n, k == 0 ? -1 : 1, st), "chirp");
+        check_hip(launch_chirp_kernel(tmp, t.chirp[k], n, M, f64, st), "chirp kernel");
+        run_passes(*fwd, tmp, st);
+        check_hip(launch_reorder_scale(tmp, t.H[k], M, order_of(*fwd), f64, st), "chirp spectrum order");
+    }
+    check_hip(hipStreamSynchronize(st), "hipStreamSynchronize(chirp tables)");
+    check_hip(hipFree(tmp), "hipFree(chirp kernel)");
+    return g_blue.emplace(key, t).first->second;
+}
+
+// Forward (inverse = false) or inverse DFT along axis a of the complex array ws.
+void axis_transform(void* ws, void* tmp, int64_t outer, int64_t n, int64_t inner, bool f64, bool inverse,
+                    SymParams* sp, int a, hipStream_t st) {
+    DevCtx& ctx = device_ctx();
+    if (is_7smooth(n)) {
+        auto p = ctx.axis_plan(outer, n, inner, f64, inverse);
+        run_passes(*p, ws, st);
+        if (sp) {
+            sp->nlev[a] = p->s.sym.nlev[0];
+            for (int i = 0; i < 3; ++i) sp->sub[a][i] = p->s.sym.sub[0][i];
+        }
+        return;
+    }
+    const int64_t M = conv_len(n);
+    const BlueTables& t = blue_tables(n, M, f64, st);
+    const int k = inverse ? 1 : 0;
+    auto fwd = ctx.axis_plan(outer, M, inner, f64, false);
+    auto inv = ctx.axis_plan(outer, M, inner, f64, true);
+    const int64_t csz = f64 ? 16 : 8;
+    timed(st, "chirp_pad", f64, outer * inner * (n + M) * csz,
+          [&] { return launch_pad_chirp(ws, tmp, outer, n, inner, M, t.chirp[k], f64, st); });
+    run_passes(*fwd, tmp, st);
+    timed(st, "chirp_product", f64, 2 * outer * inner * M * csz,
+          [&] { return launch_mul_h(tmp, outer, M, inner, t.H[k], order_of(*fwd), f64, st); });
+    run_passes(*inv, tmp, st);
+    timed(st, "chirp_extract", f64, 2 * outer * inner * n * csz,
+          [&] { return launch_extract_chirp(tmp, ws, outer, n, inner, M, t.chirp[k], f64, st); });
+    if (sp) {
+        sp->nlev[a] = 1;  // natural frequency order
+        sp->sub[a][0] = n;
+    }
+}
+
+}  // namespace
+
+void solve_periodic_any(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
+                        hipStream_t st) {
+    DevCtx& ctx = device_ctx();
+    const size_t csz = f64 ? 16 : 8;
+    int64_t N = 1;
+    for (int a = 0; a < d; ++a) N *= dims[a];
+    int64_t tmp_elems = 1;
+    for (int a = 0; a < d; ++a) {
+        if (is_7smooth(dims[a])) continue;
+        tmp_elems = std::max(tmp_elems, N / dims[a] * conv_len(dims[a]));
+    }
+    void* ws = ctx.workspace(st, (size_t)N * csz);
+    void* tmp = ctx.scratch(st, 70, (size_t)tmp_elems * csz);
+    SymParams sp;
+    std::memset(&sp, 0, sizeof(sp));
+    sp.d = d;
+    for (int a = 0; a < 3; ++a) sp.n[a] = a < d ? dims[a] : 1;
+    fill_symbol(sp, coeffs, r, d, T, 1.0 / (double)N);
+    for (int a = 0; a < d; ++a) sp.eph[a] = ctx.phase_table(dims[a]);
+
+    const int64_t esz = f64 ? 8 : 4;
+    timed(st, "widen", f64, N * (esz + (int64_t)csz), [&] { return launch_widen(grid, ws, N, f64, st); });
+    for (int a = 0; a < d; ++a) {
+        int64_t outer = 1, inner = 1;
+        for (int b = 0; b < a; ++b) outer *= dims[b];
+        for (int b = a + 1; b < d; ++b) inner *= dims[b];
+        axis_transform(ws, tmp, outer, dims[a], inner, f64, false, &sp, a, st);
+    }
+    timed(st, "symbol_full", f64, 2 * N * (int64_t)csz, [&] { return launch_symbol_full(ws, sp, N, f64, st); });
+    for (int a = d - 1; a >= 0; --a) {
+        int64_t outer = 1, inner = 1;
+        for (int b = 0; b < a; ++b) outer *= dims[b];
+        for (int b = a + 1; b < d; ++b) inner *= dims[b];
+        axis_transform(ws, tmp, outer, dims[a], inner, f64, true, nullptr, a, st);
+    }
+    timed(st, "narrow", f64, N * (esz + (int64_t)csz), [&] { return launch_narrow(ws, grid, N, f64, st); });
+}
+
+}  // namespace sfft

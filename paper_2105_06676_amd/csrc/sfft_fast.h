@@ -8,7 +8,7 @@
 namespace sfft {
 
 // fast row pass kinds (PassDesc::fast_kind)
-enum FastRowKind { ROW_R2C = 0, ROW_C2R = 1, ROW_MIDR = 2, ROW_MIDC = 3 };
+enum FastRowKind { ROW_R2C = 0, ROW_C2R = 1, ROW_MIDR = 2, ROW_MIDC = 3, ROW_CFWD = 4, ROW_CINV = 5 };
 
 constexpr int kFastMinL = 16;
 constexpr int kFastMaxRowL = 4096;   // 256 threads x 16 points

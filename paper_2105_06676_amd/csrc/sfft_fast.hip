@@ -16,6 +16,7 @@
 //  k_frow<R, ROW_C2R>   last pass: half spectrum -> real rows (keep rule applied)
 //  k_frow<R, ROW_MIDR>  whole 1-D periodic solve of real rows in one launch
 //  k_frow<R, ROW_MIDC>  complex row middle pass of a split 1-D axis
+//  k_frow<R, ROW_CFWD>, k_frow<R, ROW_CINV>  plain complex forward / inverse rows
 //  k_fcol<R, MODE>      strided-axis forward / inverse / fused middle pass
 #include <hip/hip_runtime.h>
 
@@ -275,7 +276,7 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
     cx<R> xl = {R(0), R(0)};  // X[L] of a half-spectrum row (held by q == 0)
     if (KIND == ROW_C2R) {
         if (q == 0 && active) xl = ((const cx<R>*)pd.buf)[row * pd.ostride + L];
-    } else {
+    } else if (KIND != ROW_CINV) {
         fast_fft<R, false, LOGL>(v, lds, idx, q, tlo, thi);
     }
 
@@ -348,10 +349,10 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
         apply_symbol<R>(v, lds, sp, col, (uint32_t)(fp + M * q), (uint32_t)(M * P));
     }
 
-    fast_fft<R, true, LOGL>(v, lds, idx, q, tlo, thi);
+    if (KIND != ROW_CFWD) fast_fft<R, true, LOGL>(v, lds, idx, q, tlo, thi);
 
     // ---------------- store
-    if (KIND == ROW_MIDC) {
+    if (KIND == ROW_MIDC || KIND == ROW_CFWD || KIND == ROW_CINV) {
         if (active) {
             cx<R>* dst = (cx<R>*)pd.buf + row * pd.ostride + q;
 #pragma unroll
@@ -518,6 +519,8 @@ static void launch_row_l(const PassDesc& pd, const SymParams& sp, size_t lds, hi
     switch (pd.fast_kind) {
         case ROW_R2C: SFFT_ROW(ROW_R2C) break;
         case ROW_C2R: SFFT_ROW(ROW_C2R) break;
+        case ROW_CFWD: SFFT_ROW(ROW_CFWD) break;
+        case ROW_CINV: SFFT_ROW(ROW_CINV) break;
         case ROW_MIDR: SFFT_ROW(ROW_MIDR) break;
         default: SFFT_ROW(ROW_MIDC) break;
     }

@@ -105,7 +105,7 @@ struct Ctx {
 };
 
 static PassPlan make_row(const Ctx& c, int64_t rows, int L, int rowtrans, int mode, int nreal, int hcount,
-                         int64_t ostride) {
+                         int64_t ostride, bool allow_fast = true) {
     PassPlan p;
     PassDesc& pd = p.pd;
     std::memset(&pd, 0, sizeof(pd));
@@ -135,8 +135,8 @@ static PassPlan make_row(const Ctx& c, int64_t rows, int L, int rowtrans, int mo
         pd.st_mul = 1;
     }
     p.lds_bytes = (size_t)W * pd.lds_stride * c.csz;
-    const bool fast_ok = (rowtrans == RT_HALF || rowtrans == RT_C2C) && is_pow2(L) && L >= kFastMinL &&
-                         L <= kFastMaxRowL && !tunables().no_fast;
+    const bool fast_ok = allow_fast && (rowtrans == RT_HALF || rowtrans == RT_C2C) && is_pow2(L) &&
+                         L >= kFastMinL && L <= kFastMaxRowL && !tunables().no_fast;
     if (fast_ok) {
         pd.fast = 1;
         pd.logL = ilog2(L);
@@ -151,7 +151,10 @@ static PassPlan make_row(const Ctx& c, int64_t rows, int L, int rowtrans, int mo
             p.has_half = true;
             two_level(2 * (int64_t)L, &p.h_lo, &p.h_hi);
         }
-        pd.fast_kind = rowtrans == RT_C2C ? ROW_MIDC : mode == MODE_FWD ? ROW_R2C : mode == MODE_INV ? ROW_C2R : ROW_MIDR;
+        if (rowtrans == RT_C2C)
+            pd.fast_kind = mode == MODE_FWD ? ROW_CFWD : mode == MODE_INV ? ROW_CINV : ROW_MIDC;
+        else
+            pd.fast_kind = mode == MODE_FWD ? ROW_R2C : mode == MODE_INV ? ROW_C2R : ROW_MIDR;
     }
     return p;
 }
@@ -410,6 +413,70 @@ int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* S,
         p.pd.B = B;
         for (int a = 0; a < 3; ++a) p.pd.rdims[a] = a < d ? dims[a] : 1;
         S->model_bytes += p.model_bytes;
+    }
+    return 0;
+}
+
+int axis_schedule(int64_t outer, int64_t n, int64_t inner, bool f64, bool inverse, std::vector<PassPlan>* out,
+                  std::vector<int64_t>* levels, std::string* why) {
+    out->clear();
+    levels->clear();
+    if (outer < 1 || n < 1 || inner < 1) { *why = "extents must be >= 1"; return -1; }
+    if (!is_7smooth(n)) { *why = "transform length " + std::to_string(n) + " is not 7-smooth"; return -2; }
+    Ctx c{f64, f64 ? 8 : 4, f64 ? 16 : 8, f64 ? 4096 : 8192};
+    const int64_t col_max = tunables().col_max ? tunables().col_max : 512;
+    const int64_t row_max = 4096, row_single = 8192;
+    std::vector<int64_t> lev;
+    bool last_row = false;  // the last level runs as a row pass (contiguous axis)
+    if (n == 1) {
+        lev.push_back(1);
+    } else if (inner == 1 && n <= row_single && !(is_pow2(n) && n > kFastMaxRowL)) {
+        lev.push_back(n);
+        last_row = true;
+    } else if (inner == 1) {
+        // (a power of two above the register row kernels' limit splits off
+        // strided levels so that its row level stays on them)
+        int64_t nr = 0;
+        for (int64_t s = std::min(n, row_max); s >= 2; --s)
+            if (n % s == 0) { nr = s; break; }
+        if (!nr || !split_axis(n / nr, col_max, &lev) || lev.size() > 2) {
+            *why = "length " + std::to_string(n) + " cannot be split into supported factors";
+            return -2;
+        }
+        lev.push_back(nr);
+        last_row = true;
+    } else if (!split_axis(n, col_max, &lev)) {
+        *why = "length " + std::to_string(n) + " cannot be split into supported factors";
+        return -2;
+    }
+    *levels = lev;
+    if (n == 1) return 0;  // identity
+    const int nl = (int)lev.size();
+    auto level = [&](int l) {
+        int64_t pre = 1, post = 1;
+        for (int i = 0; i < l; ++i) pre *= lev[i];
+        for (int i = l + 1; i < nl; ++i) post *= lev[i];
+        const int mode = inverse ? MODE_INV : MODE_FWD;
+        if (l == nl - 1 && last_row) {
+            PassPlan p = make_row(c, outer * pre, (int)lev[l], RT_C2C, mode, (int)lev[l], (int)lev[l], lev[l]);
+            p.model_bytes = outer * n * 2 * c.csz;
+            p.name = inverse ? "axis_inv_row" : "axis_fwd_row";
+            return p;
+        }
+        const bool tw = l < nl - 1;
+        PassPlan p = make_col(c, outer * pre, (int)lev[l], post * inner, mode, tw ? lev[l] * post : 0, inner, 0);
+        col_bytes(c, p, 0);
+        p.name = inverse ? "axis_inv" : "axis_fwd";
+        return p;
+    };
+    if (!inverse)
+        for (int l = 0; l < nl; ++l) out->push_back(level(l));
+    else
+        for (int l = nl - 1; l >= 0; --l) out->push_back(level(l));
+    for (auto& p : *out) {
+        p.pd.d = 1;
+        p.pd.B = 1;
+        for (int a = 0; a < 3; ++a) p.pd.rdims[a] = 1;
     }
     return 0;
 }

@@ -48,6 +48,14 @@ struct Schedule {
                               // forward spectrum is in the workspace before it)
 };
 
+// Passes of an unnormalised complex DFT of length n along the middle axis of a
+// complex [outer][n][inner] array held in the workspace (any 7-smooth n).  Forward:
+// every factor level, twiddles after each level but the last, output in
+// digit-reversed order across levels; inverse: the mirror, natural order out.
+// levels receives the factorisation (position -> frequency as in the solver).
+int axis_schedule(int64_t outer, int64_t n, int64_t inner, bool f64, bool inverse, std::vector<PassPlan>* out,
+                  std::vector<int64_t>* levels, std::string* why);
+
 struct Tunables {
     int col_max = 0;          // 0: default
     int aperiodic_cutoff = 0; // 0: per-shape default

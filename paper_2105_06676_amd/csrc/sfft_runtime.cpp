@@ -92,6 +92,47 @@ std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f
     for (int a = 0; a < d; ++a) p->s.sym.eph[a] = phase_table(dims[a]);
     {
         std::lock_guard<std::mutex> g(mu);
+        bind_passes(*p, f64);
+        plans[key.str()] = p;
+    }
+    return p;
+}
+
+std::shared_ptr<Plan> DevCtx::axis_plan(int64_t outer, int64_t n, int64_t inner, bool f64, bool inverse) {
+    std::ostringstream key;
+    key << "axis:" << outer << ":" << n << ":" << inner << ":" << f64 << ":" << inverse << ":"
+        << tunables().col_max << ":" << tunables().no_fast;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        auto it = plans.find(key.str());
+        if (it != plans.end()) return it->second;
+    }
+    auto p = std::make_shared<Plan>();
+    std::string why;
+    std::vector<int64_t> levels;
+    const int rc = axis_schedule(outer, n, inner, f64, inverse, &p->s.passes, &levels, &why);
+    if (rc) throw Error(rc == -1 ? -1 : -2, why);
+    for (auto& pp : p->s.passes) {
+        if (pp.lds_bytes > lds_max)
+            throw Error(-2, "pass needs " + std::to_string(pp.lds_bytes) + " bytes of LDS");
+    }
+    p->s.f64 = f64;
+    p->s.fused = false;
+    p->s.sym.nlev[0] = (int)levels.size();
+    for (size_t i = 0; i < levels.size() && i < 3; ++i) p->s.sym.sub[0][i] = levels[i];
+    p->s.spec_elems = outer * n * inner;
+    {
+        std::lock_guard<std::mutex> g(mu);
+        bind_passes(*p, f64);
+        plans[key.str()] = p;
+    }
+    return p;
+}
+
+// Bind the table pointers of every pass (caller holds mu).
+void DevCtx::bind_passes(Plan& plan, bool f64) {
+    auto* p = &plan;
+    {
         for (auto& pp : p->s.passes) {
             PassDesc pd = pp.pd;
             auto st = table(pp.stage_tab);
@@ -117,9 +158,7 @@ std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f
             p->pd.push_back(pd);
             p->lds.push_back(pp.lds_bytes);
         }
-        plans[key.str()] = p;
     }
-    return p;
 }
 
 void* DevCtx::workspace(hipStream_t st, size_t bytes) {

@@ -45,6 +45,10 @@ struct DevCtx {
     hipStream_t tstream = nullptr;   // table generation
 
     std::shared_ptr<Plan> plan(int d, const int64_t* dims, int64_t B, bool f64, bool unfused = false);
+    // Complex transform along the middle axis of [outer][n][inner] (sym.nlev[0] /
+    // sym.sub[0] hold its factor levels).
+    std::shared_ptr<Plan> axis_plan(int64_t outer, int64_t n, int64_t inner, bool f64, bool inverse);
+    void bind_passes(Plan& p, bool f64);
     const double2* phase_table(int64_t n);
     void* workspace(hipStream_t st, size_t bytes);
     void* scratch(hipStream_t st, int slot, size_t bytes);  // extra per-stream buffers

@@ -51,9 +51,15 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
     # zero extent
     z = (ctypes.c_int64 * 2)(0, 8)
     assert f(fake, 0, 2, z, cp, 1, 5, None) == -1
-    # prime factor above 7
-    p = (ctypes.c_int64 * 2)(11, 8)
+    # extents beyond the supported range (any extent up to 2^30 is accepted; those
+    # with a prime factor above 7 take the chirp-z path)
+    p = (ctypes.c_int64 * 2)((1 << 31) + 1, 8)
     assert f(fake, 0, 2, p, cp, 1, 5, None) == -2
+    assert "2^30" in s._binding._last_error().decode()
+    # the fields entry point still needs 7-smooth extents
+    ff = s._binding._periodic_fields
+    p = (ctypes.c_int64 * 2)(11, 8)
+    assert ff(fake, 0, 1, 2, p, cp, 1, 5, None) == -2
     assert "prime factor" in s._binding._last_error().decode()
 
 

@@ -215,6 +215,10 @@ def config(name: str) -> Workload:
         return Workload("box2d_aperiodic_4096", 2, (4096, 4096), 1, 512, box_random_coeffs(4, 2, 1), 4,
                         "uniform", aperiodic=True, dtypes=("f64", "f32"),
                         notes="2-D aperiodic 9-point box, fixed frame")
+    if name == "jacobi2d_8191_prime":
+        return Workload("jacobi2d_8191_prime", 2, (8191, 8191), 1, 4096, jacobi5_coeffs(), 8, "uniform",
+                        dtypes=("f32", "f64"),
+                        notes="2-D periodic 5-point Jacobi on a prime torus (chirp-z transforms)")
     if name == "heat2d_backward_euler_4096":
         return Workload("heat2d_backward_euler_4096", 2, (4096, 4096), 1, 1000, identity_coeffs(2), 7, "uniform",
                         dtypes=("f32", "f64"), implicit_q=backward_euler2d_q(2.0),
