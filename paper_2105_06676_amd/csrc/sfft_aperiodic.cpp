@@ -68,7 +68,16 @@ struct Ap {
     // per-column symbol parts for this solve, per plan and stream
     std::map<std::pair<const Plan*, hipStream_t>, void*> coltab;
     int64_t cutoff;
-    int64_t maxdist;     // largest dist of any interior cell
+    // Entry-time bookkeeping (appendix on l-shells): sig[a] = the stencil's largest
+    // reach along axis a; face (a, side) is active when the stencil reads toward it
+    // (its boundary values then enter the interior sig[a] cells per step at most).
+    // Bands are measured in units of su = the largest reach toward any active face
+    // (su cells of distance per step of entry time; a conservative common scale).
+    int64_t sig[3];
+    bool act[3][2];
+    int64_t su;
+    int64_t maxell;      // largest entry time of any interior cell (LLONG_MAX: none)
+    bool inert;          // no active face: the frame never influences the interior
 };
 
 void* interior_origin(const Ap& a, const void* base) {
@@ -107,6 +116,7 @@ void boxed_periodic(Ap& a, const void* src, void* dst, const int64_t* ext, int64
         sp.ncol = 1;
         for (int k = 1; k < a.d; ++k) sp.ncol *= sp.sdim[k];
     }
+    const KeepRule& kf = keep;
     RealView in;
     std::memset(&in, 0, sizeof(in));
     in.boff = boff;
@@ -118,13 +128,18 @@ void boxed_periodic(Ap& a, const void* src, void* dst, const int64_t* ext, int64
     in.ptr = const_cast<void*>(src);
     out.ptr = dst;
     if (!read_done) {
-        run_plan(*plan, ws, in, out, keep, sp, st);
+        run_plan(*plan, ws, in, out, kf, sp, st);
         return;
     }
-    run_plan(*plan, ws, in, out, keep, sp, st, 0, 1);
+    run_plan(*plan, ws, in, out, kf, sp, st, 0, 1);
     check_hip(hipEventRecord(read_done, st), "hipEventRecord");
-    run_plan(*plan, ws, in, out, keep, sp, st, 1);
+    run_plan(*plan, ws, in, out, kf, sp, st, 1);
 }
+
+// Keep rule for entry times (lo, hi], expressed in the kernels' distance form:
+// distances in cells scale by su, and a face the stencil never reads toward is
+// moved kBig cells away so that it is never the nearest.
+constexpr int64_t kBig = (int64_t)1 << 40;
 
 KeepRule make_keep(const Ap& a, int64_t lo, int64_t hi) {
     KeepRule k;
@@ -132,9 +147,13 @@ KeepRule make_keep(const Ap& a, int64_t lo, int64_t hi) {
     k.enabled = 1;
     k.face_axis = -1;
     k.face_side = -1;
-    k.lo = lo;
-    k.hi = hi;
-    for (int i = 0; i < a.d; ++i) k.gdim[i] = a.n[i];
+    k.lo = lo * a.su;
+    k.hi = hi == LLONG_MAX ? LLONG_MAX : hi * a.su;
+    for (int i = 0; i < a.d; ++i) {
+        const int64_t off_lo = a.act[i][0] ? 0 : kBig, off_hi = a.act[i][1] ? 0 : kBig;
+        k.gdim[i] = a.n[i] + off_lo + off_hi;
+        k.gorg[i] = off_lo;
+    }
     return k;
 }
 
@@ -156,33 +175,49 @@ void join(Ap& a, const Forked& f, hipStream_t st) {
     for (int i = 0; i < f.n; ++i) depend(a, f.s[i], st, f.ev[i]);
 }
 
-// Periodic solves of the slabs of band (0, w] of `src` over `steps`, storing
-// (lo, hi] into `dst`.  The slabs of each axis keep disjoint cells, so each axis
-// runs on a helper stream of recursion level `lev`, forked off `st`.
+// Periodic solves of the slabs of the band of entry times (0, w] of `src` over
+// `steps`, storing entry times (lo, hi] into `dst`.  The slab of an active face
+// spans sig * w cells along its normal and the whole interior along the other
+// axes; the slabs of each axis keep disjoint cells, so each axis runs on a helper
+// stream of recursion level `lev`, forked off `st`.
 Forked slab_solve(Ap& a, const void* src, void* dst, int64_t w, int64_t steps, int64_t lo, int64_t hi, int lev,
                   hipStream_t st) {
     Forked f;
-    if (lo >= a.maxdist || hi <= lo) return f;
+    if (lo >= a.maxell || hi <= lo) return f;
     DevCtx& ctx = device_ctx();
     hipEvent_t fork = ctx.side_event(a.st, 4 * lev + 3);
     check_hip(hipEventRecord(fork, st), "hipEventRecord");
-    const void* s0 = interior_origin(a, src);
-    void* d0 = interior_origin(a, dst);
     for (int ax = 0; ax < a.d; ++ax) {
-        if (lo >= ceil_half(a.n[ax])) continue;  // no cell nearest to this axis' faces is kept
-        const int64_t ta = std::min(w, a.n[ax]);
+        const bool lo_f = a.act[ax][0], hi_f = a.act[ax][1];
+        if (!lo_f && !hi_f) continue;
+        // cells attached to this axis' faces lie within half the axis (both faces
+        // active) or the whole axis (one) of their face
+        const int64_t reach = lo_f && hi_f ? ceil_half(a.n[ax]) : a.n[ax];
+        if (a.su * lo >= reach) continue;  // none of them has an entry time above lo
+        const int64_t ta = std::min(a.su * w, a.n[ax]);
         int64_t ext[3];
         for (int k = 0; k < a.d; ++k) ext[k] = k == ax ? ta : a.n[k];
         KeepRule keep = make_keep(a, lo, hi);
         keep.face_axis = ax;
         int64_t B = 1;
         int64_t boff = 0;
+        int64_t shift = 0;  // cells from the low face to the slab's first cell
         if (ta < a.n[ax]) {
-            B = 2;
-            keep.face_side = 2;
-            keep.gbstep[ax] = a.n[ax] - ta;
-            boff = (a.n[ax] - ta) * a.sstride[ax];
+            if (lo_f && hi_f) {
+                B = 2;
+                keep.face_side = 2;
+                keep.gbstep[ax] = a.n[ax] - ta;
+                boff = (a.n[ax] - ta) * a.sstride[ax];
+            } else if (hi_f) {
+                keep.face_side = 1;
+                shift = a.n[ax] - ta;
+            } else {
+                keep.face_side = 0;
+            }
         }
+        keep.gorg[ax] += shift;
+        const void* s0 = (const char*)interior_origin(a, src) + shift * a.sstride[ax] * (int64_t)a.esz;
+        void* d0 = (char*)interior_origin(a, dst) + shift * a.sstride[ax] * (int64_t)a.esz;
         hipStream_t sa = ctx.side_stream(a.st, 4 * lev + ax);
         check_hip(hipStreamWaitEvent(sa, fork, 0), "hipStreamWaitEvent");
         boxed_periodic(a, s0, d0, ext, B, boff, keep, steps, sa);
@@ -193,7 +228,8 @@ Forked slab_solve(Ap& a, const void* src, void* dst, int64_t w, int64_t steps, i
     return f;
 }
 
-// Loop `tau` steps on the band dist <= 2 r tau of src; store dist <= r tau into dst.
+// Loop `tau` steps on the band of entry times <= 2 tau of src; store entry times
+// <= tau into dst.
 void base_case(Ap& a, const void* src, void* dst, int64_t tau, hipStream_t st) {
     BaseParams bp;
     std::memset(&bp, 0, sizeof(bp));
@@ -207,7 +243,8 @@ void base_case(Ap& a, const void* src, void* dst, int64_t tau, hipStream_t st) {
     for (int k = 0; k < a.d; ++k) {
         bp.n[k + sh] = a.n[k];
         bp.r3[k + sh] = a.r;
-        bp.halo3[k + sh] = a.r * tau;
+        bp.reach3[k + sh] = a.sig[k];
+        bp.halo3[k + sh] = a.sig[k] * tau;
         bp.sstride[k + sh] = a.sstride[k];
     }
     bp.steps = (int)tau;
@@ -234,22 +271,26 @@ void base_case(Ap& a, const void* src, void* dst, int64_t tau, hipStream_t st) {
         ++m;
     }
     bp.ncoef = m;
-    // strips covering dist <= wout without overlap
-    const int64_t wout = a.r * tau;
+    // strips covering entry times <= tau without overlap: face (k, side) covers
+    // wo[k][side] = su * tau cells (0 for an inactive face)
+    int64_t wo[3][2];
+    for (int k = 0; k < a.d; ++k)
+        for (int side = 0; side < 2; ++side) wo[k][side] = a.act[k][side] ? a.su * tau : 0;
     int64_t first = 0;
     size_t lds = 0;
     int ns = 0;
     for (int ax = 0; ax < a.d; ++ax) {
         for (int side = 0; side < 2; ++side) {
+            if (!a.act[ax][side]) continue;
             int64_t lo[3], hi[3];
             bool empty = false;
             for (int k = 0; k < a.d; ++k) {
                 if (k == ax) {
-                    if (side == 0) { lo[k] = 0; hi[k] = std::min(wout, a.n[k]); }
-                    else { lo[k] = std::max(wout, a.n[k] - wout); hi[k] = a.n[k]; }
+                    if (side == 0) { lo[k] = 0; hi[k] = std::min(wo[k][0], a.n[k]); }
+                    else { lo[k] = std::max(wo[k][0], a.n[k] - wo[k][1]); hi[k] = a.n[k]; }
                 } else if (k < ax) {
-                    lo[k] = wout;
-                    hi[k] = a.n[k] - wout;
+                    lo[k] = wo[k][0];
+                    hi[k] = a.n[k] - wo[k][1];
                 } else {
                     lo[k] = 0;
                     hi[k] = a.n[k];
@@ -343,18 +384,18 @@ void recursive_boundary(Ap& a, const void* src, void* dst, int64_t T, int lev, h
         return;
     }
     const int64_t T1 = T / 2, T2 = T - T1;
-    const int64_t s = a.r;
     if ((int)a.level.size() <= lev) {
         void* p = device_ctx().scratch(a.st, 100 + lev, (size_t)a.total * a.esz);
         a.level.push_back(p);
     }
     void* mid = a.level[lev];
-    // step 1: band (0, 2sT] at t0 -> (0, sT + sT2] at t0 + T1
-    Forked f = slab_solve(a, src, mid, 2 * s * T, T1, s * T1, s * T + s * T2, lev, st);
+    // (bands in entry-time units, i.e. the distance form with sigma = 1)
+    // step 1: band (0, 2T] at t0 -> (0, T + T2] at t0 + T1
+    Forked f = slab_solve(a, src, mid, 2 * T, T1, T1, T + T2, lev, st);
     recursive_boundary(a, src, mid, T1, lev + 1, st);
     join(a, f, st);
-    // step 2: band (0, sT + sT2] at t0 + T1 -> (0, sT] at t0 + T
-    f = slab_solve(a, mid, dst, s * T + s * T2, T2, s * T2, s * T, lev, st);
+    // step 2: band (0, T + T2] at t0 + T1 -> (0, T] at t0 + T
+    f = slab_solve(a, mid, dst, T + T2, T2, T2, T, lev, st);
     recursive_boundary(a, mid, dst, T2, lev + 1, st);
     join(a, f, st);
 }
@@ -381,13 +422,46 @@ Ap make_ap(void* grid, bool f64, int d, const int64_t* dims, const double* coeff
         s *= dims[k] + 2 * r;
     }
     a.total = s;
-    a.maxdist = LLONG_MAX;
-    for (int k = 0; k < d; ++k) a.maxdist = std::min(a.maxdist, ceil_half(a.n[k]));
-    // base-case reach: the halo r * cutoff must fit an LDS tile
+    // how far the stencil reads toward each face (non-zero coefficients only)
+    int64_t toward[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    const int w = 2 * r + 1;
+    int nc = 1;
+    for (int k = 0; k < d; ++k) nc *= w;
+    for (int i = 0; i < nc; ++i) {
+        if (coeffs[i] == 0.0) continue;
+        int rem = i;
+        for (int k = d - 1; k >= 0; --k) {
+            const int o = rem % w - r;
+            rem /= w;
+            toward[k][0] = std::max<int64_t>(toward[k][0], -o);
+            toward[k][1] = std::max<int64_t>(toward[k][1], o);
+        }
+    }
+    int64_t sig_max = 0;
+    a.inert = true;
+    a.su = 0;
+    for (int k = 0; k < 3; ++k) {
+        a.sig[k] = k < d ? std::max(toward[k][0], toward[k][1]) : 0;
+        for (int side = 0; side < 2; ++side) {
+            a.act[k][side] = k < d && toward[k][side] > 0;
+            a.inert = a.inert && !a.act[k][side];
+            if (a.act[k][side]) a.su = std::max(a.su, a.sig[k]);
+        }
+        sig_max = std::max(sig_max, a.sig[k]);
+    }
+    a.maxell = LLONG_MAX;
+    for (int k = 0; k < d && !a.inert; ++k) {
+        if (!a.act[k][0] && !a.act[k][1]) continue;
+        // the deepest cell along this axis: half way (two active faces) or at the
+        // inactive end (one)
+        const int64_t depth = a.act[k][0] && a.act[k][1] ? ceil_half(a.n[k]) : a.n[k];
+        a.maxell = std::min(a.maxell, (depth + a.su - 1) / a.su);
+    }
+    // base-case reach: the halo sig * cutoff must fit an LDS tile
     const int64_t reach = d == 1 ? 256 : d == 2 ? 16 : 4;
-    a.cutoff = r == 0 ? 0
-                      : tunables().aperiodic_cutoff > 0 ? tunables().aperiodic_cutoff
-                                                         : std::max<int64_t>(1, reach / r);
+    a.cutoff = a.inert ? 0
+                       : tunables().aperiodic_cutoff > 0 ? tunables().aperiodic_cutoff
+                                                          : std::max<int64_t>(1, reach / sig_max);
     return a;
 }
 
@@ -395,57 +469,56 @@ Ap make_ap(void* grid, bool f64, int d, const int64_t* dims, const double* coeff
 // enqueued on `ls` (the caller's stream, or a capturing stream).
 void recursive_path(Ap& a, int64_t T, hipStream_t ls) {
     DevCtx& ctx = device_ctx();
-    const int64_t r = a.r, sT = r * T;
     hipStream_t si = ctx.side_stream(a.st, -1);  // the interior solve's helper stream
     // RecursiveBoundary step 1 reads the initial band before the interior solve
-    // overwrites dist > sT; step 2 writes dist <= sT only after the interior
-    // solve's first pass has read the whole initial interior.
+    // overwrites entry times > T; step 2 writes entry times <= T only after the
+    // interior solve's first pass has read the whole initial interior.
     const int64_t T1 = T / 2, T2 = T - T1;
     void* mid = ctx.scratch(a.st, 100, (size_t)a.total * a.esz);
     a.level.push_back(mid);
-    Forked f = slab_solve(a, a.grid, mid, 2 * sT, T1, r * T1, sT + r * T2, 0, ls);
+    Forked f = slab_solve(a, a.grid, mid, 2 * T, T1, T1, T + T2, 0, ls);
     recursive_boundary(a, a.grid, mid, T1, 1, ls);
     join(a, f, ls);
-    const bool interior = sT < a.maxdist;
+    const bool interior = T < a.maxell;
     if (interior) {
         depend(a, ls, si, -1);
-        KeepRule keep = make_keep(a, sT, LLONG_MAX);
+        KeepRule keep = make_keep(a, T, LLONG_MAX);
         hipEvent_t read_done = ctx.side_event(a.st, -3);
         boxed_periodic(a, interior_origin(a, a.grid), interior_origin(a, a.grid), a.n, 1, 0, keep, T, si,
                        read_done);
         check_hip(hipStreamWaitEvent(ls, read_done, 0), "hipStreamWaitEvent");
     }
-    f = slab_solve(a, mid, a.grid, sT + r * T2, T2, r * T2, sT, 0, ls);
+    f = slab_solve(a, mid, a.grid, T + T2, T2, T2, T, 0, ls);
     recursive_boundary(a, mid, a.grid, T2, 1, ls);
     join(a, f, ls);
     if (interior) depend(a, si, ls, -2);
 }
 
-// Solves of T <= cutoff or r == 0 (few launches; always enqueued directly).
+// Solves of T <= cutoff or with an inert frame (few launches; always enqueued
+// directly).
 void short_path(Ap& a, int64_t T) {
     DevCtx& ctx = device_ctx();
     hipStream_t st = a.st;
     void* grid = a.grid;
-    if (a.r == 0) {
-        // no neighbours: the frame is never read and every cell scales by c0^T
+    if (a.inert) {
+        // the stencil reads no neighbour along any axis: the frame is never read
         KeepRule keep = make_keep(a, 0, LLONG_MAX);
         keep.enabled = 0;
         boxed_periodic(a, interior_origin(a, grid), interior_origin(a, grid), a.n, 1, 0, keep, T, st);
         return;
     }
-    const int64_t sT = (int64_t)a.r * T;
     hipStream_t si = ctx.side_stream(st, -1);
-    // The base case reads dist <= 2 sT of the initial array while the result is
-    // stored in place, so both parts read from a copy and run side by side.
+    // The base case reads entry times <= 2T of the initial array while the result
+    // is stored in place, so both parts read from a copy and run side by side.
     void* tmp = ctx.scratch(st, 99, (size_t)a.total * a.esz);
     check_hip(hipMemcpyAsync(tmp, grid, (size_t)a.total * a.esz, hipMemcpyDeviceToDevice, st), "copy");
-    if (sT < a.maxdist) {
+    if (T < a.maxell) {
         depend(a, st, si, -1);
-        KeepRule keep = make_keep(a, sT, LLONG_MAX);
+        KeepRule keep = make_keep(a, T, LLONG_MAX);
         boxed_periodic(a, interior_origin(a, tmp), interior_origin(a, grid), a.n, 1, 0, keep, T, si);
     }
     base_case(a, tmp, grid, T, st);
-    if (sT < a.maxdist) depend(a, si, st, -2);
+    if (T < a.maxell) depend(a, si, st, -2);
 }
 
 // Captured graphs of repeated recursive solves.  A solve is a pure function of
@@ -489,7 +562,7 @@ void drop_graph(GraphEntry& e) {
 void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
                      hipStream_t st) {
     Ap a = make_ap(grid, f64, d, dims, coeffs, r, st);
-    if (r == 0 || T <= a.cutoff)
+    if (a.inert || T <= a.cutoff)
         short_path(a, T);
     else
         recursive_path(a, T, st);
@@ -502,7 +575,7 @@ void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const dou
 void solve_aperiodic_cached(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
                             int64_t T, hipStream_t st) {
     Ap a = make_ap(grid, f64, d, dims, coeffs, r, st);
-    if (r == 0 || T <= a.cutoff) {
+    if (a.inert || T <= a.cutoff) {
         short_path(a, T);
         return;
     }

@@ -23,7 +23,8 @@ struct BaseParams {
     int nstrip, steps, ncoef, pad_;
     int64_t n[3];              // interior extents (padded to 3 axes)
     int64_t r3[3];             // frame width per axis (0 on unused axes)
-    int64_t halo3[3];          // radius * steps per axis (0 on unused axes)
+    int64_t reach3[3];         // the stencil's largest offset along each axis
+    int64_t halo3[3];          // reach * steps per axis (0 on unused axes)
     int64_t sstride[3];        // element strides of the stored array
     const void* src;           // values at the start time (interior)
     const void* frame;         // array whose frame holds the boundary values

@@ -1,14 +1,15 @@
 // Base case of RecursiveBoundary (Sec. 4): loop `steps` stencil steps near the
-// fixed frame, in LDS, and store the cells within `wout` of the frame.
+// fixed frame, in LDS, and store the cells of entry time <= steps.
 //
-// The band to produce (dist <= wout) is cut into disjoint boxes ("strips", one
-// per face, later faces excluding what earlier faces cover) and each strip into
-// tiles.  A workgroup loads its tile plus a halo of radius*steps cells (clipped to
-// the stored array, whose frame is fixed and read from the frame source), runs the
-// steps in LDS (cells whose neighbourhood is not loaded keep stale values; the
-// stale margin grows by `radius` per step and never reaches the tile), and
-// stores the tile.  Reads stay inside dist <= 2 * wout, as the recursion
-// guarantees valid input there.
+// The band to produce (face f's cells within sig_f * steps of it, for every face
+// the stencil reads toward) is cut into disjoint boxes ("strips", one per such
+// face, later faces excluding what earlier faces cover) and each strip into
+// tiles.  A workgroup loads its tile plus a halo of reach * steps cells per axis
+// (clipped to the stored array, whose frame is fixed and read from the frame
+// source), runs the steps in LDS (cells whose neighbourhood is not loaded keep
+// stale values; the stale margin grows by at most the reach per step and never
+// reaches the tile), and stores the tile.  Reads stay inside entry times
+// <= 2 * steps, where the recursion guarantees valid input.
 #include <hip/hip_runtime.h>
 
 #include "sfft_base.h"
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
             for (int a = 0; a < 3; ++a) {
                 const int64_t g = rlo[a] + xs[a];
                 if (g < bp.r3[a] || g >= bp.n[a] + bp.r3[a]) ok = false;             // frame cell: fixed
-                if (xs[a] < bp.r3[a] || xs[a] + bp.r3[a] >= rext[a]) ok = false;     // neighbourhood not loaded
+                if (xs[a] < bp.reach3[a] || xs[a] + bp.reach3[a] >= rext[a]) ok = false;  // neighbourhood not loaded
             }
             upd[k] = ok;
         }

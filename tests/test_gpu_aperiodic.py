@@ -132,3 +132,44 @@ def test_box2d_aperiodic_4096_full_size_sampled(dtype):
     ref = oracle.aperiodic(box, w.coeffs, w.T)
     rows = slice(1, 1 + s + h)
     assert rel_l2(got[rows, c0 - h + 1: c0 + h + 1], ref[rows, s + 1: s + 1 + K]) <= TOL[dtype]
+
+
+def _biased(shape_offsets, seed):
+    """Coefficients on a (2r+1)^d box that are non-zero only at the listed offsets
+    (positive weights of sum 1): asymmetric reach per face."""
+    offs, r, d = shape_offsets
+    c = np.zeros((2 * r + 1,) * d)
+    w = wl.uniform(seed, "coef", len(offs)) + 0.1
+    for o, x in zip(offs, w / w.sum()):
+        c[tuple(oi + r for oi in o)] = x
+    return c
+
+
+# (name, dims, (offsets, r, d), T, cutoff)
+BIASED = [
+    ("upwind_1d", (300,), ([(-1,), (0,)], 1, 1), 150, 8),
+    ("upwind_1d_r2", (257,), ([(-2,), (-1,), (0,)], 2, 1), 90, 4),
+    ("upwind_2d", (120, 100), ([(-1, 0), (0, -1), (0, 0)], 1, 2), 60, 0),
+    ("downwind_2d", (90, 110), ([(1, 0), (0, 1), (0, 0), (1, 1)], 1, 2), 45, 3),
+    ("axis0_only_2d", (96, 80), ([(-2, 0), (-1, 0), (0, 0), (1, 0), (2, 0)], 2, 2), 40, 0),
+    ("biased_axis0_2d", (100, 90), ([(-2, 0), (-1, -1), (0, 0), (1, 1), (0, 1)], 2, 2), 33, 2),
+    ("radius2_reach1_2d", (70, 60), ([(-1, 0), (1, 0), (0, -1), (0, 1), (0, 0)], 2, 2), 50, 0),
+    ("upwind_3d", (20, 18, 16), ([(-1, 0, 0), (0, -1, 0), (0, 0, -1), (0, 0, 0)], 1, 3), 24, 0),
+    ("axis2_only_3d", (12, 10, 40), ([(0, 0, -1), (0, 0, 1), (0, 0, 0)], 1, 3), 30, 2),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("name,dims,spec,T,cut", BIASED, ids=[b[0] for b in BIASED])
+def test_aperiodic_biased_stencils(name, dims, spec, T, cut, dtype):
+    """Stencils that reach unevenly (or not at all) toward some faces: entry-time
+    bookkeeping (appendix on l-shells) drops the slabs and base-case strips of faces
+    the stencil never reads toward and scales the others by the reach of their axis."""
+    c = _biased(spec, 70 + len(dims))
+    r = spec[1]
+    store = tuple(n + 2 * r for n in dims)
+    a = wl.uniform(71 + sum(dims), "grid", int(np.prod(store))).reshape(store)
+    ref = oracle.aperiodic(rounded_input(a, dtype), c, T)
+    with cutoff(cut):
+        got = gpu_aperiodic(a, c, T, dtype)
+    assert rel_l2(got, ref) <= TOL[dtype], name
