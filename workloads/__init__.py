@@ -215,6 +215,11 @@ def config(name: str) -> Workload:
         return Workload("box2d_aperiodic_4096", 2, (4096, 4096), 1, 512, box_random_coeffs(4, 2, 1), 4,
                         "uniform", aperiodic=True, dtypes=("f64", "f32"),
                         notes="2-D aperiodic 9-point box, fixed frame")
+    if name == "upwind2d_aperiodic_4096":
+        c = np.zeros((3, 3), dtype=np.float64)
+        c[1, 1], c[0, 1], c[1, 0] = 0.5, 0.25, 0.25
+        return Workload("upwind2d_aperiodic_4096", 2, (4096, 4096), 1, 512, c, 9, "uniform", aperiodic=True,
+                        dtypes=("f64", "f32"), notes="2-D aperiodic upwind 3-point stencil, fixed frame")
     if name == "jacobi2d_8191_prime":
         return Workload("jacobi2d_8191_prime", 2, (8191, 8191), 1, 4096, jacobi5_coeffs(), 8, "uniform",
                         dtypes=("f32", "f64"),
