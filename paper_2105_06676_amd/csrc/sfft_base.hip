@@ -16,7 +16,8 @@
 
 namespace sfft {
 
-template <typename R>
+// MAXC: LDS cells per thread, at least the largest loaded region / kBaseThreads.
+template <typename R, int MAXC>
 __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R* A = reinterpret_cast<R*>(smem_raw);
@@ -67,7 +68,6 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
     }
     // per-thread cells and whether they are updated (interior cell whose whole
     // neighbourhood lies inside the loaded region)
-    constexpr int MAXC = kBaseMaxCells / kBaseThreads;
     int idx[MAXC];
     bool upd[MAXC];
 #pragma unroll
@@ -119,12 +119,22 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
     }
 }
 
-hipError_t launch_base(const BaseParams& bp, bool f64, int64_t nblocks, size_t lds, hipStream_t st) {
-    if (f64)
-        hipLaunchKernelGGL(k_base<double>, dim3((unsigned)nblocks), dim3(kBaseThreads), lds, st, bp);
-    else
-        hipLaunchKernelGGL(k_base<float>, dim3((unsigned)nblocks), dim3(kBaseThreads), lds, st, bp);
+template <typename R>
+hipError_t launch_r(const BaseParams& bp, int64_t nblocks, size_t lds, hipStream_t st) {
+    // per-thread slots for the largest region (lds bytes of R cells): unused slots
+    // still cost issue slots in the unrolled step loop, so use the smallest that fits
+    const int64_t cells = (int64_t)(lds / sizeof(R));
+    const dim3 g((unsigned)nblocks), b(kBaseThreads);
+    if (cells <= 4 * kBaseThreads) hipLaunchKernelGGL((k_base<R, 4>), g, b, lds, st, bp);
+    else if (cells <= 8 * kBaseThreads) hipLaunchKernelGGL((k_base<R, 8>), g, b, lds, st, bp);
+    else if (cells <= 16 * kBaseThreads) hipLaunchKernelGGL((k_base<R, 16>), g, b, lds, st, bp);
+    else if (cells <= kBaseMaxCells) hipLaunchKernelGGL((k_base<R, kBaseMaxCells / kBaseThreads>), g, b, lds, st, bp);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+hipError_t launch_base(const BaseParams& bp, bool f64, int64_t nblocks, size_t lds, hipStream_t st) {
+    return f64 ? launch_r<double>(bp, nblocks, lds, st) : launch_r<float>(bp, nblocks, lds, st);
 }
 
 }  // namespace sfft
