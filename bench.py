@@ -194,8 +194,9 @@ def time_solve(sfft, torch, w, dtype, reps=5, warmup=1):
     return {"ms": ms, "cell_updates_per_s": cells * w.T / (ms * 1e-3)}
 
 
-def other_workloads(sfft, torch):
-    """The other workloads of the method, timed the same way (context for the headline)."""
+def other_workloads(sfft, torch, only=None):
+    """The other workloads of the method, timed the same way (context for the headline);
+    `only`: a set of "<workload>_<dtype>" keys to restrict the list to."""
     import workloads as wl
     out = {}
     for name, dts in (("heat1d_65536", ("f64",)), ("star3d_512", ("f32",)),
@@ -204,6 +205,8 @@ def other_workloads(sfft, torch):
                       ("heat2d_backward_euler_4096", ("f32", "f64")), ("jacobi2d_8191_prime", ("f32",))):
         w = wl.config(name)
         for dt in dts:
+            if only is not None and f"{name}_{dt}" not in only:
+                continue
             out[f"{name}_{dt}"] = dict(time_solve(sfft, torch, w, dt), dims=list(w.dims), T=w.T,
                                        aperiodic=w.aperiodic, fields=w.fields, implicit=w.implicit_q is not None)
     return out
@@ -259,6 +262,8 @@ def main():
     ap.add_argument("--serving", type=int, default=10000, help="serving-mix requests (0 = skip)")
     ap.add_argument("--no-copy", action="store_true", help="skip the device-copy bandwidth reference")
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads")
+    ap.add_argument("--others", default=None,
+                    help="comma-separated <workload>_<dtype> keys: time only these other workloads")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -322,7 +327,8 @@ def main():
                             "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in k32.items()},
         "f64": res64,
         "copy_reference": None if args.no_copy else copy_reference(torch, N * 4 * 2),
-        "other_workloads": None if args.no_others else other_workloads(sfft, torch),
+        "other_workloads": None if args.no_others else other_workloads(
+            sfft, torch, None if args.others is None else set(args.others.split(","))),
         "cpu_baseline": None if args.no_cpu else cpu_baseline(w),
         "serving": serving_bench(sfft, torch, args.serving) if args.serving > 0 else None,
     }

@@ -460,6 +460,45 @@ __device__ __forceinline__ double symbol_mu_real(const SymParams& sp, const SymC
     return mu;
 }
 
+// The same two quantities for G frequencies f + k * fstep (k < G) of one column,
+// for a stencil of radius exactly RR, from phase-table entries fetched by
+// phases_n.  The table lives in L2: fetching all RR * G entries of a group at
+// once (and ahead of use) costs one round trip per group instead of one per mode.
+// The arithmetic is that of symbol_mu / symbol_mu_real, term for term.
+template <int G, int RR>
+__device__ __forceinline__ void phases_n(const SymParams& sp, uint32_t f, uint32_t fstep, dcx (*e)[G]) {
+    const uint32_t n = (uint32_t)sp.n[0];
+    const dcx* t = (const dcx*)sp.eph[0];
+#pragma unroll
+    for (int o = 1; o <= RR; ++o)
+#pragma unroll
+        for (int k = 0; k < G; ++k) e[o - 1][k] = t[mul_mod_small((uint32_t)o, f + fstep * (uint32_t)k, n)];
+}
+
+template <int G, int RR>
+__device__ __forceinline__ void symbol_mu_real_e(const SymCol& col, const dcx (*e)[G], double* mu) {
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        mu[k] = col.K.x;
+#pragma unroll
+        for (int o = 1; o <= RR; ++o)
+            mu[k] -= 2.0 * fma(e[o - 1][k].x, col.Gp[o].x, -e[o - 1][k].y * col.Gp[o].y);
+    }
+}
+
+template <int G, int RR>
+__device__ __forceinline__ void symbol_mu_e(const SymCol& col, const dcx (*e)[G], dcx* mu) {
+#pragma unroll
+    for (int k = 0; k < G; ++k) {
+        mu[k] = col.K;
+#pragma unroll
+        for (int o = 1; o <= RR; ++o) {
+            const dcx ec = {e[o - 1][k].x, -e[o - 1][k].y};
+            mu[k] = dsub(mu[k], dadd(dmul(e[o - 1][k], col.Gp[o]), dmul(ec, col.Gm[o])));
+        }
+    }
+}
+
 // (1 - mu)^T by binary repeated squaring (Sec. 3 Step 2), in deviation form:
 // a factor 1 - m squares to 1 - (2m - m^2) and (1 - v)(1 - m) = 1 - (v + m - vm);
 // a factor leaves the deviation form once |m| > 1/2, where plain products are
