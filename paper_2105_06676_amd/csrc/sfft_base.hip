@@ -66,25 +66,34 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
         const int64_t gi = g0 * bp.sstride[0] + g1 * bp.sstride[1] + g2 * bp.sstride[2];
         A[i] = fr ? frame[gi] : src[gi];
     }
-    // per-thread cells and whether they are updated (interior cell whose whole
-    // neighbourhood lies inside the loaded region)
+    // per-thread cells and the last step at which each is updated (-1: never).
+    // An interior cell whose whole neighbourhood is loaded is updated while it
+    // can still reach the tile: a cell delta_a cells outside the tile along axis
+    // a influences the tile's values after the last step only through steps
+    // 0 .. steps - 1 - max_a ceil(delta_a / reach_a).  The cells such a cell reads
+    // are at most one reach further out, so they are updated one step longer,
+    // and every value a kept cell reads is current.
     int idx[MAXC];
-    bool upd[MAXC];
+    int lim[MAXC];
 #pragma unroll
     for (int k = 0; k < MAXC; ++k) {
         const int i = threadIdx.x + k * kBaseThreads;
         idx[k] = i;
-        upd[k] = false;
+        lim[k] = -1;
         if (i < cells) {
             const int x0 = i / le0, rem = i - x0 * le0, x1 = rem / le1, x2 = rem - x1 * le1;
             const int64_t xs[3] = {x0, x1, x2};
             bool ok = true;
+            int64_t need = 0;
             for (int a = 0; a < 3; ++a) {
                 const int64_t g = rlo[a] + xs[a];
                 if (g < bp.r3[a] || g >= bp.n[a] + bp.r3[a]) ok = false;             // frame cell: fixed
                 if (xs[a] < bp.reach3[a] || xs[a] + bp.reach3[a] >= rext[a]) ok = false;  // neighbourhood not loaded
+                const int64_t t0 = org[a] + bp.r3[a], t1 = t0 + ext[a] - 1;
+                const int64_t delta = g < t0 ? t0 - g : (g > t1 ? g - t1 : 0);
+                if (delta > 0 && bp.reach3[a] > 0) need = max(need, (delta + bp.reach3[a] - 1) / bp.reach3[a]);
             }
-            upd[k] = ok;
+            if (ok) lim[k] = bp.steps - 1 - (int)need;
         }
     }
     __syncthreads();
@@ -93,7 +102,7 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
         R nv[MAXC];
 #pragma unroll
         for (int k = 0; k < MAXC; ++k) {
-            if (upd[k]) {
+            if (step <= lim[k]) {
                 R acc = R(0);
                 for (int j = 0; j < bp.ncoef; ++j) acc += coef[j] * A[idx[k] + offs[j]];
                 nv[k] = acc;
@@ -102,7 +111,7 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < MAXC; ++k)
-            if (upd[k]) A[idx[k]] = nv[k];
+            if (step <= lim[k]) A[idx[k]] = nv[k];
         __syncthreads();
     }
 

@@ -282,6 +282,20 @@ __device__ __forceinline__ bool keep_last(const KeepRule& kr, const RowKeep& rk,
     return side < 0 || (first & 1) == side;
 }
 
+// May any cell of a row along the last axis pass keep_last?  False only when none
+// can: every cell's distance is at most dpre, and a last-axis face is the first
+// face only when it is strictly nearer than dpre.
+__device__ __forceinline__ bool row_may_keep(const KeepRule& kr, const RowKeep& rk, int d, int64_t b) {
+    if (rk.dpre <= kr.lo) return false;
+    if (kr.face_axis >= 0 && kr.face_axis != d - 1) {
+        if (rk.dpre > kr.hi) return false;
+        if (rk.fpre / 2 != kr.face_axis) return false;
+        const int side = kr.face_side == 2 ? (int)b : kr.face_side;
+        if (side >= 0 && (rk.fpre & 1) != side) return false;
+    }
+    return true;
+}
+
 __device__ __forceinline__ bool keep_cell(const KeepRule& kr, int d, int64_t b, const int64_t* i) {
     if (!kr.enabled) return true;
     return keep_last(kr, keep_row(kr, d, b, i), d, b, pick3(i, d - 1));

@@ -267,7 +267,7 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
     const int rr = threadIdx.x / P;
     const int q = threadIdx.x % P;
     const int64_t row = (int64_t)bid * NTR + rr;
-    const bool active = row < pd.outer;
+    bool active = row < pd.outer;
     const RowIdx idx{rr * LS};
     const cx<R>* tlo = (const cx<R>*)pd.f_lo;
     const cx<R>* thi = (const cx<R>*)pd.f_hi;
@@ -277,6 +277,10 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
 
     int64_t ii[3] = {0, 0, 0};
     const int64_t b = active ? row_split(pd, row, ii) : 0;
+    // last pass under a keep rule: a row none of whose cells is kept is neither
+    // read nor written (it still takes part in the tile's barriers)
+    if (KIND == ROW_C2R && active && pd.keep.enabled && !row_may_keep(pd.keep, keep_row(pd.keep, pd.d, b, ii), pd.d, b))
+        active = false;
 
     // ---------------- load
     if (KIND == ROW_R2C || KIND == ROW_MIDR) {

@@ -69,6 +69,22 @@ def test_periodic_multi_tile_and_split_axes(dtype, dims):
     assert rel_l2(gpu_periodic(a0, c, T, dtype), ref) <= TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("r", [0, 1, 2])
+@pytest.mark.parametrize("sym", [True, False])
+@pytest.mark.parametrize("dims", [(2048,), (32768,), (128, 96), (512, 40), (16, 32, 24)])
+def test_fused_symbol_every_radius(dtype, r, sym, dims):
+    """The fused middle passes evaluate the symbol with code specialised on the
+    radius (0, 1, 2) and on whether lambda is real: every combination, on a fused
+    1-D row, a split 1-D axis, and strided-axis middle passes of 2-D and 3-D grids."""
+    seed = 900 + r * 10 + sym + len(dims)
+    c = _coeffs(len(dims), r, sym, seed)
+    a0 = wl.uniform(seed, "grid", int(np.prod(dims))).reshape(dims)
+    T = 45
+    ref = oracle.periodic(rounded_input(a0, dtype), c, T)
+    assert rel_l2(gpu_periodic(a0, c, T, dtype), ref) <= TOL[dtype], (dims, r, sym)
+
+
 def test_T_zero_is_identity_and_r0_is_pointwise():
     a0 = wl.uniform(3, "grid", 12 * 10).reshape(12, 10)
     c = _coeffs(2, 1, False, 3)
