@@ -90,50 +90,67 @@ void* interior_origin(const Ap& a, const void* base) {
 // (both at the interior origin), zero-padded to FFT-friendly extents, on stream
 // `st`.  With `read_done` set, that event is recorded once the first pass has
 // read all of `src`.
-void boxed_periodic(Ap& a, const void* src, void* dst, const int64_t* ext, int64_t B, int64_t boff,
-                    const KeepRule& keep, int64_t steps, hipStream_t st, hipEvent_t read_done = nullptr) {
+// A periodic solve of boxes of `src` (plan, workspace, symbol and views
+// prepared), enqueued in one piece or pass by pass.
+struct Boxed {
+    std::shared_ptr<Plan> plan;
+    void* ws = nullptr;
+    SymParams sp;
+    RealView in, out;
+    KeepRule keep;
+    size_t npass = 0;
+};
+
+Boxed boxed_prepare(Ap& a, const void* src, void* dst, const int64_t* ext, int64_t B, int64_t boff,
+                    const KeepRule& keep, int64_t steps, hipStream_t st) {
+    Boxed b;
     int64_t pd[3];
     for (int k = 0; k < a.d; ++k) pd[k] = pad_fft(ext[k]);
     DevCtx& ctx = device_ctx();
-    auto plan = ctx.plan(a.d, pd, B, a.f64);
-    void* ws = ctx.workspace(st, (size_t)plan->s.spec_elems * (a.f64 ? 16 : 8));
-    SymParams sp = plan->s.sym;
+    b.plan = ctx.plan(a.d, pd, B, a.f64);
+    b.npass = b.plan->pd.size();
+    b.ws = ctx.workspace(st, (size_t)b.plan->s.spec_elems * (a.f64 ? 16 : 8));
+    b.sp = b.plan->s.sym;
     double N = 1.0;
     for (int k = 0; k < a.d; ++k) N *= (double)pd[k];
-    fill_symbol(sp, a.coeffs, a.r, a.d, steps, 1.0 / N);
+    fill_symbol(b.sp, a.coeffs, a.r, a.d, steps, 1.0 / N);
     if (a.d >= 2) {
         // the column part of the symbol depends on the plan and the coefficients
         // only (not on the step count): build it once per plan within this solve
-        auto it = a.coltab.find({plan.get(), st});
+        auto it = a.coltab.find({b.plan.get(), st});
         if (it == a.coltab.end()) {
             int64_t ncol = 1;
-            for (int k = 1; k < a.d; ++k) ncol *= sp.sdim[k];
+            for (int k = 1; k < a.d; ++k) ncol *= b.sp.sdim[k];
             void* tab = ctx.scratch(st, 300 + (int)a.coltab.size(), (size_t)ncol * symbol_column_bytes());
-            build_symbol_columns(sp, tab, a.f64, st);
-            it = a.coltab.emplace(std::make_pair(plan.get(), st), tab).first;
+            build_symbol_columns(b.sp, tab, a.f64, st);
+            it = a.coltab.emplace(std::make_pair(b.plan.get(), st), tab).first;
         }
-        sp.coltab = it->second;
-        sp.ncol = 1;
-        for (int k = 1; k < a.d; ++k) sp.ncol *= sp.sdim[k];
+        b.sp.coltab = it->second;
+        b.sp.ncol = 1;
+        for (int k = 1; k < a.d; ++k) b.sp.ncol *= b.sp.sdim[k];
     }
-    const KeepRule& kf = keep;
-    RealView in;
-    std::memset(&in, 0, sizeof(in));
-    in.boff = boff;
+    b.keep = keep;
+    std::memset(&b.in, 0, sizeof(b.in));
+    b.in.boff = boff;
     for (int k = 0; k < a.d; ++k) {
-        in.stride[k] = a.sstride[k];
-        in.ext[k] = ext[k];
+        b.in.stride[k] = a.sstride[k];
+        b.in.ext[k] = ext[k];
     }
-    RealView out = in;
-    in.ptr = const_cast<void*>(src);
-    out.ptr = dst;
-    if (!read_done) {
-        run_plan(*plan, ws, in, out, kf, sp, st);
-        return;
-    }
-    run_plan(*plan, ws, in, out, kf, sp, st, 0, 1);
-    check_hip(hipEventRecord(read_done, st), "hipEventRecord");
-    run_plan(*plan, ws, in, out, kf, sp, st, 1);
+    b.out = b.in;
+    b.in.ptr = const_cast<void*>(src);
+    b.out.ptr = dst;
+    return b;
+}
+
+// Passes [p0, p1) of a prepared solve.
+void boxed_run(const Boxed& b, hipStream_t st, size_t p0, size_t p1) {
+    if (p0 < p1) run_plan(*b.plan, b.ws, b.in, b.out, b.keep, b.sp, st, p0, p1);
+}
+
+void boxed_periodic(Ap& a, const void* src, void* dst, const int64_t* ext, int64_t B, int64_t boff,
+                    const KeepRule& keep, int64_t steps, hipStream_t st) {
+    const Boxed b = boxed_prepare(a, src, dst, ext, B, boff, keep, steps, st);
+    boxed_run(b, st, 0, b.npass);
 }
 
 // Keep rule for entry times (lo, hi], expressed in the kernels' distance form:
@@ -180,13 +197,13 @@ void join(Ap& a, const Forked& f, hipStream_t st) {
 // spans sig * w cells along its normal and the whole interior along the other
 // axes; the slabs of each axis keep disjoint cells, so each axis runs on a helper
 // stream of recursion level `lev`, forked off `st`.
+// The helper streams start after `fork`, an event recorded on the caller's stream
+// where the slabs' input is complete.
 Forked slab_solve(Ap& a, const void* src, void* dst, int64_t w, int64_t steps, int64_t lo, int64_t hi, int lev,
-                  hipStream_t st) {
+                  hipEvent_t fork) {
     Forked f;
     if (lo >= a.maxell || hi <= lo) return f;
     DevCtx& ctx = device_ctx();
-    hipEvent_t fork = ctx.side_event(a.st, 4 * lev + 3);
-    check_hip(hipEventRecord(fork, st), "hipEventRecord");
     for (int ax = 0; ax < a.d; ++ax) {
         const bool lo_f = a.act[ax][0], hi_f = a.act[ax][1];
         if (!lo_f && !hi_f) continue;
@@ -389,14 +406,21 @@ void recursive_boundary(Ap& a, const void* src, void* dst, int64_t T, int lev, h
         a.level.push_back(p);
     }
     void* mid = a.level[lev];
+    // The recursion is the critical path (its leaves run one after another), so it
+    // is enqueued before the slabs that run beside it: a replayed graph then
+    // dispatches the chain of leaves first and fills the device with slab work
+    // around it.
+    hipEvent_t fork = device_ctx().side_event(a.st, 4 * lev + 3);
     // (bands in entry-time units, i.e. the distance form with sigma = 1)
     // step 1: band (0, 2T] at t0 -> (0, T + T2] at t0 + T1
-    Forked f = slab_solve(a, src, mid, 2 * T, T1, T1, T + T2, lev, st);
+    check_hip(hipEventRecord(fork, st), "hipEventRecord");
     recursive_boundary(a, src, mid, T1, lev + 1, st);
+    Forked f = slab_solve(a, src, mid, 2 * T, T1, T1, T + T2, lev, fork);
     join(a, f, st);
     // step 2: band (0, T + T2] at t0 + T1 -> (0, T] at t0 + T
-    f = slab_solve(a, mid, dst, T + T2, T2, T2, T, lev, st);
+    check_hip(hipEventRecord(fork, st), "hipEventRecord");
     recursive_boundary(a, mid, dst, T2, lev + 1, st);
+    f = slab_solve(a, mid, dst, T + T2, T2, T2, T, lev, fork);
     join(a, f, st);
 }
 
@@ -470,26 +494,41 @@ Ap make_ap(void* grid, bool f64, int d, const int64_t* dims, const double* coeff
 void recursive_path(Ap& a, int64_t T, hipStream_t ls) {
     DevCtx& ctx = device_ctx();
     hipStream_t si = ctx.side_stream(a.st, -1);  // the interior solve's helper stream
-    // RecursiveBoundary step 1 reads the initial band before the interior solve
-    // overwrites entry times > T; step 2 writes entry times <= T only after the
-    // interior solve's first pass has read the whole initial interior.
+    // The interior solve reads the initial interior and stores entry times > T in
+    // place.  All but its last pass work in its own workspace and start at once;
+    // the last pass stores only after RecursiveBoundary step 1 has read the
+    // initial band, and step 2 stores entry times <= T only after the interior's
+    // first pass has read the whole initial interior.
     const int64_t T1 = T / 2, T2 = T - T1;
     void* mid = ctx.scratch(a.st, 100, (size_t)a.total * a.esz);
     a.level.push_back(mid);
-    Forked f = slab_solve(a, a.grid, mid, 2 * T, T1, T1, T + T2, 0, ls);
-    recursive_boundary(a, a.grid, mid, T1, 1, ls);
-    join(a, f, ls);
     const bool interior = T < a.maxell;
+    hipEvent_t read_done = ctx.side_event(a.st, -3);
+    Boxed in;
     if (interior) {
         depend(a, ls, si, -1);
-        KeepRule keep = make_keep(a, T, LLONG_MAX);
-        hipEvent_t read_done = ctx.side_event(a.st, -3);
-        boxed_periodic(a, interior_origin(a, a.grid), interior_origin(a, a.grid), a.n, 1, 0, keep, T, si,
-                       read_done);
+        in = boxed_prepare(a, interior_origin(a, a.grid), interior_origin(a, a.grid), a.n, 1, 0,
+                           make_keep(a, T, LLONG_MAX), T, si);
+        if (in.npass > 1) {
+            boxed_run(in, si, 0, 1);
+            check_hip(hipEventRecord(read_done, si), "hipEventRecord");
+            boxed_run(in, si, 1, in.npass - 1);
+        }
+    }
+    hipEvent_t fork = ctx.side_event(a.st, 3);
+    check_hip(hipEventRecord(fork, ls), "hipEventRecord");
+    recursive_boundary(a, a.grid, mid, T1, 1, ls);
+    Forked f = slab_solve(a, a.grid, mid, 2 * T, T1, T1, T + T2, 0, fork);
+    join(a, f, ls);
+    if (interior) {
+        depend(a, ls, si, -4);
+        boxed_run(in, si, in.npass - 1, in.npass);
+        if (in.npass == 1) check_hip(hipEventRecord(read_done, si), "hipEventRecord");
         check_hip(hipStreamWaitEvent(ls, read_done, 0), "hipStreamWaitEvent");
     }
-    f = slab_solve(a, mid, a.grid, T + T2, T2, T2, T, 0, ls);
+    check_hip(hipEventRecord(fork, ls), "hipEventRecord");
     recursive_boundary(a, mid, a.grid, T2, 1, ls);
+    f = slab_solve(a, mid, a.grid, T + T2, T2, T2, T, 0, fork);
     join(a, f, ls);
     if (interior) depend(a, si, ls, -2);
 }

@@ -411,6 +411,17 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
         return;
     }
     const RowKeep rk = keep_row(pd.keep, pd.d, b, ii);
+    // A slab whose face axis is not the last axis keeps, in a row that reaches
+    // this point (row_may_keep held), exactly the cells whose last-axis faces
+    // are no nearer than dpre: one interval [mlo, mhi] of the row.
+    const bool interval = KIND == ROW_C2R && pd.keep.enabled && pd.keep.face_axis >= 0 && pd.keep.face_axis != pd.d - 1;
+    int64_t mlo = 0, mhi = -1;
+    if (interval) {
+        const int la = pd.d - 1;
+        const int64_t goff = pick3(pd.keep.gorg, la) + b * pick3(pd.keep.gbstep, la);
+        mlo = rk.dpre - 1 - goff;
+        mhi = pick3(pd.keep.gdim, la) - rk.dpre - goff;
+    }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int m = q + P * i;
@@ -418,7 +429,11 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
         for (int h = 0; h < 2; ++h) {
             const int64_t mm = 2 * m + h;
             if (mm >= el) continue;
-            if (pd.keep.enabled && !keep_last(pd.keep, rk, pd.d, b, mm)) continue;
+            if (interval) {
+                if (mm < mlo || mm > mhi) continue;
+            } else if (pd.keep.enabled && !keep_last(pd.keep, rk, pd.d, b, mm)) {
+                continue;
+            }
             out[base + mm * sl] = h ? v[i].y : v[i].x;
         }
     }
