@@ -146,7 +146,10 @@ __device__ __forceinline__ void fast_fft(cx<R>* v, cx<R>* lds, IDX idx, int q, c
                                          const cx<R>* thi) {
     constexpr int REM = LOGL - DONE;
     if constexpr (REM > 0) {
-        constexpr int LR = REM >= 4 ? 4 : REM;
+        // the first stage is always radix 16 (the thread's 16 points); five bits
+        // left after it go as radix 8 then 4, since a final radix-2 stage costs
+        // more registers than it saves
+        constexpr int LR = (DONE > 0 && REM == 5) ? 3 : (REM >= 4 ? 4 : REM);
         fstage<R, (1 << LR), INV, (1 << LOGL), (1 << DONE), DONE == 0, REM == LR>(v, lds, idx, q, tlo, thi);
         fast_fft<R, INV, LOGL, DONE + LR>(v, lds, idx, q, tlo, thi);
     }
