@@ -86,6 +86,22 @@ static int ilog2(int64_t x) {
     return l;
 }
 
+// Row length of a contiguous axis too long for one row pass: the largest divisor
+// up to row_max, except that a power-of-two split keeps its strided cofactor at
+// least kFastMinL long (shorter strided levels would run on the generic kernels,
+// several times slower than a shorter register row pass).
+static int64_t split_row(int64_t n, int64_t row_max) {
+    int64_t first = 0;
+    for (int64_t s = std::min(n, row_max); s >= 2; --s) {
+        if (n % s) continue;
+        if (!first) first = s;
+        const int64_t co = n / s;
+        if (is_pow2(s) && is_pow2(co) && co < kFastMinL) continue;
+        return s;
+    }
+    return first;
+}
+
 static void two_level(int64_t N, TwiddleReq* lo, TwiddleReq* hi) {
     *lo = {N, 64, 1};
     *hi = {N, std::max<int64_t>(1, N / 64), 64};
@@ -280,9 +296,7 @@ int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* S,
             sp.sdim[0] = n;
             S->spec_elems = 0;
         } else {
-            int64_t nr = 0;
-            for (int64_t s = std::min(n, row_max); s >= 2; --s)
-                if (n % s == 0) { nr = s; break; }
+            const int64_t nr = split_row(n, row_max);
             std::vector<int64_t> lev;
             if (!nr || !split_axis(n / nr, col_max, &lev) || lev.size() > 2) {
                 *why = "1-D extent " + std::to_string(n) + " cannot be split into supported factors";
@@ -436,9 +450,7 @@ int axis_schedule(int64_t outer, int64_t n, int64_t inner, bool f64, bool invers
     } else if (inner == 1) {
         // (a power of two above the register row kernels' limit splits off
         // strided levels so that its row level stays on them)
-        int64_t nr = 0;
-        for (int64_t s = std::min(n, row_max); s >= 2; --s)
-            if (n % s == 0) { nr = s; break; }
+        const int64_t nr = split_row(n, row_max);
         if (!nr || !split_axis(n / nr, col_max, &lev) || lev.size() > 2) {
             *why = "length " + std::to_string(n) + " cannot be split into supported factors";
             return -2;
