@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "sfft_bluestein.h"
+#include "sfft_kernels.h"
 #include "sfft_runtime.h"
 
 namespace sfft {
@@ -100,6 +101,26 @@ const BlueTables& blue_tables(int64_t n, int64_t M, bool f64, hipStream_t st) {
     return g_blue.emplace(key, t).first->second;
 }
 
+// The transformed kernel H of direction k laid out in the position order `o` of
+// the length-M forward transform (built once per device and order), so that the
+// product reads it contiguously.
+std::map<std::tuple<int, int64_t, int64_t, bool, int, int, int64_t, int64_t, int64_t>, void*> g_hpos;
+
+const void* h_positions(const BlueTables& t, int k, int64_t n, int64_t M, bool f64, const AxisOrder& o,
+                        hipStream_t st) {
+    if (o.nlev <= 1) return t.H[k];
+    DevCtx& ctx = device_ctx();
+    const auto key = std::make_tuple(ctx.device, n, M, f64, k, o.nlev, o.sub[0], o.sub[1], o.sub[2]);
+    std::lock_guard<std::mutex> g(g_blue_mu);
+    auto it = g_hpos.find(key);
+    if (it != g_hpos.end()) return it->second;
+    void* d = nullptr;
+    check_hip(hipMalloc(&d, (size_t)M * (f64 ? 16 : 8)), "hipMalloc(chirp spectrum positions)");
+    check_hip(launch_gather_order(t.H[k], d, M, o, f64, st), "chirp spectrum positions");
+    check_hip(hipStreamSynchronize(st), "hipStreamSynchronize(chirp spectrum positions)");
+    return g_hpos.emplace(key, d).first->second;
+}
+
 // Forward (inverse = false) or inverse DFT along axis a of the complex array ws.
 void axis_transform(void* ws, void* tmp, int64_t outer, int64_t n, int64_t inner, bool f64, bool inverse,
                     SymParams* sp, int a, hipStream_t st) {
@@ -122,8 +143,11 @@ void axis_transform(void* ws, void* tmp, int64_t outer, int64_t n, int64_t inner
     timed(st, "chirp_pad", f64, outer * inner * (n + M) * csz,
           [&] { return launch_pad_chirp(ws, tmp, outer, n, inner, M, t.chirp[k], f64, st); });
     run_passes(*fwd, tmp, st);
+    const void* Hp = h_positions(t, k, n, M, f64, order_of(*fwd), st);
+    AxisOrder natural;
+    std::memset(&natural, 0, sizeof(natural));
     timed(st, "chirp_product", f64, 2 * outer * inner * M * csz,
-          [&] { return launch_mul_h(tmp, outer, M, inner, t.H[k], order_of(*fwd), f64, st); });
+          [&] { return launch_mul_h(tmp, outer, M, inner, Hp, natural, f64, st); });
     run_passes(*inv, tmp, st);
     timed(st, "chirp_extract", f64, 2 * outer * inner * n * csz,
           [&] { return launch_extract_chirp(tmp, ws, outer, n, inner, M, t.chirp[k], f64, st); });
@@ -162,6 +186,13 @@ void solve_periodic_any(void* grid, bool f64, int d, const int64_t* dims, const 
         for (int b = 0; b < a; ++b) outer *= dims[b];
         for (int b = a + 1; b < d; ++b) inner *= dims[b];
         axis_transform(ws, tmp, outer, dims[a], inner, f64, false, &sp, a, st);
+    }
+    if (d >= 2) {
+        // the part of the symbol that depends on axes 1..d-1, once per column
+        for (int a = 0; a < d; ++a) sp.sdim[a] = dims[a];
+        int64_t ncol = 1;
+        for (int a = 1; a < d; ++a) ncol *= dims[a];
+        build_symbol_columns(sp, ctx.scratch(st, 71, (size_t)ncol * symbol_column_bytes()), f64, st);
     }
     timed(st, "symbol_full", f64, 2 * N * (int64_t)csz, [&] { return launch_symbol_full(ws, sp, N, f64, st); });
     for (int a = d - 1; a >= 0; --a) {

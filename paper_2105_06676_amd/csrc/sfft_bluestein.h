@@ -25,10 +25,12 @@ hipError_t launch_chirp(double2* c, int64_t n, int sign, hipStream_t st);
 hipError_t launch_chirp_kernel(void* h, const double2* c, int64_t n, int64_t M, bool f64, hipStream_t st);
 // dst[f(p)] = src[p] / M along a length-M digit-reversed transform (natural order out)
 hipError_t launch_reorder_scale(const void* src, void* dst, int64_t M, AxisOrder ord, bool f64, hipStream_t st);
+// dst[p] = src[f(p)]: a natural-order table laid out in a transform's position order
+hipError_t launch_gather_order(const void* src, void* dst, int64_t M, AxisOrder ord, bool f64, hipStream_t st);
 // [outer][n][inner] -> [outer][M][inner]: multiply by the chirp, zero-pad
 hipError_t launch_pad_chirp(const void* src, void* dst, int64_t outer, int64_t n, int64_t inner, int64_t M,
                             const double2* c, bool f64, hipStream_t st);
-// buf[o][p][i] *= H[f(p)] (H in natural order)
+// buf[o][p][i] *= H[f(p)] (f: position -> frequency by `ord`; identity for nlev <= 1)
 hipError_t launch_mul_h(void* buf, int64_t outer, int64_t M, int64_t inner, const void* H, AxisOrder ord, bool f64,
                         hipStream_t st);
 // [outer][M][inner] -> [outer][n][inner]: first n entries times the chirp
