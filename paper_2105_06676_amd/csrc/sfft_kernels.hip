@@ -314,7 +314,17 @@ __device__ __forceinline__ int batch_find_g(const BatchItem* it, int n, uint32_t
 
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_row(PassDesc pd, SymParams sp) {
-    row_tile<R>(pd, sp, blockIdx.x);
+    // The tile code indexes the descriptors' arrays with run-time indices; on the
+    // kernel-argument copies that costs a private copy and several hundred VGPRs
+    // (one wave per SIMD), on an LDS copy it is an LDS read.
+    __shared__ PassDesc spd;
+    __shared__ SymParams ssp;
+    if (threadIdx.x == 0) {
+        spd = pd;
+        ssp = sp;
+    }
+    __syncthreads();
+    row_tile<R>(spd, ssp, blockIdx.x);
 }
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_row_b(const BatchItem* it, int n, const SymParams* sy) {
@@ -323,7 +333,14 @@ __global__ __launch_bounds__(kThreads) void k_row_b(const BatchItem* it, int n, 
 }
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_col(PassDesc pd, SymParams sp) {
-    col_tile<R>(pd, sp, blockIdx.x);
+    __shared__ PassDesc spd;  // see k_row
+    __shared__ SymParams ssp;
+    if (threadIdx.x == 0) {
+        spd = pd;
+        ssp = sp;
+    }
+    __syncthreads();
+    col_tile<R>(spd, ssp, blockIdx.x);
 }
 template <typename R>
 __global__ __launch_bounds__(kThreads) void k_col_b(const BatchItem* it, int n, const SymParams* sy) {
