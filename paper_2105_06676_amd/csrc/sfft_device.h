@@ -161,12 +161,12 @@ __device__ __forceinline__ void stage(cx<R>* lds, int L, int ntrans, int ts, int
                                       const cx<R>* __restrict__ tab, int tmul) {
     const int nb = L / RAD;
     const int total = nb * ntrans;
-    constexpr int MAXIT = (kTileElems + RAD * kGenThreads - 1) / (RAD * kGenThreads);
+    constexpr int MAXIT = (kTileElems + RAD * gen_threads<R>() - 1) / (RAD * gen_threads<R>());
     cx<R> v[MAXIT][RAD];
     const int step = (L / (Ns * RAD)) * tmul;
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
-        const int e = threadIdx.x + it * kGenThreads;
+        const int e = threadIdx.x + it * gen_threads<R>();
         if (e < total) {
             int tr, j;
             if (TFAST) { tr = e % ntrans; j = e / ntrans; }
@@ -190,7 +190,7 @@ __device__ __forceinline__ void stage(cx<R>* lds, int L, int ntrans, int ts, int
     __syncthreads();
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
-        const int e = threadIdx.x + it * kGenThreads;
+        const int e = threadIdx.x + it * gen_threads<R>();
         if (e < total) {
             int tr, j;
             if (TFAST) { tr = e % ntrans; j = e / ntrans; }

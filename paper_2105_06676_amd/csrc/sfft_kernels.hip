@@ -52,7 +52,7 @@ __device__ void r2c_untangle(cx<R>* lds, int nrows, int LS, int L, const cx<R>* 
     // X[k] = (Z[k] + conj Z[L-k]) / 2 - i w^k (Z[k] - conj Z[L-k]) / 2, w = exp(-2 pi i / 2L)
     // tab holds exp(-2 pi i m / 2L).
     const int per = L / 2 + 1;
-    for (int e = threadIdx.x; e < nrows * per; e += kGenThreads) {
+    for (int e = threadIdx.x; e < nrows * per; e += gen_threads<R>()) {
         const int rr = e / per, k = e - rr * per;
         cx<R>* row = lds + rr * LS;
         const int kk = (L - k) % L;
@@ -83,7 +83,7 @@ template <typename R>
 __device__ void c2r_tangle(cx<R>* lds, int nrows, int LS, int L, const cx<R>* tab) {
     // Z'[k] = (X[k] + conj X[L-k]) + i conj(w^k) (X[k] - conj X[L-k]), w as above.
     const int per = L / 2 + 1;
-    for (int e = threadIdx.x; e < nrows * per; e += kGenThreads) {
+    for (int e = threadIdx.x; e < nrows * per; e += gen_threads<R>()) {
         const int rr = e / per, k = e - rr * per;
         cx<R>* row = lds + rr * LS;
         const int kk = L - k;
@@ -117,7 +117,7 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
     if (pd.in_real) {
         const int64_t sl = pd.rv.stride[pd.d - 1];
         const int64_t el = pd.rv.ext[pd.d - 1];
-        for (int e = threadIdx.x; e < nrows * L; e += kGenThreads) {
+        for (int e = threadIdx.x; e < nrows * L; e += gen_threads<R>()) {
             const int rr = e / L, m = e - rr * L;
             int64_t idx[3];
             const int64_t b = row_coords(pd, row0 + rr, idx);
@@ -135,7 +135,7 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
         }
     } else {
         const int cnt = pd.rowtrans == RT_HALF ? L + 1 : L;
-        for (int e = threadIdx.x; e < nrows * cnt; e += kGenThreads) {
+        for (int e = threadIdx.x; e < nrows * cnt; e += gen_threads<R>()) {
             const int rr = e / cnt, m = e - rr * cnt;
             const cx<R>* src = buf + (row0 + rr) * pd.ostride;
             cx<R> v;
@@ -162,7 +162,7 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
         // 1-D problems: axis 0 is the only axis, G[o] = c[o], K = 1 - sum c.
         const SymCol col = symbol_column_1d(sp);
         const int cnt = half ? L + 1 : L;
-        for (int e = threadIdx.x; e < nrows * cnt; e += kGenThreads) {
+        for (int e = threadIdx.x; e < nrows * cnt; e += gen_threads<R>()) {
             const int rr = e / cnt, k = e - rr * cnt;
             const int64_t p0 = ((row0 + rr) % pd.q_mod) * L + k;
             const int64_t f0 = pos_to_freq(sp, 0, p0);
@@ -185,7 +185,7 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
         const int64_t sl = pd.rvo.stride[pd.d - 1];
         const int64_t el = pd.rvo.ext[pd.d - 1];
         const int per = half ? 2 * L : L;
-        for (int e = threadIdx.x; e < nrows * per; e += kGenThreads) {
+        for (int e = threadIdx.x; e < nrows * per; e += gen_threads<R>()) {
             const int rr = e / per, m = e - rr * per;
             if (m >= el) continue;
             int64_t idx[3];
@@ -199,7 +199,7 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
     } else {
         cx<R>* dst = (cx<R>*)pd.buf;
         const int cnt = pd.rowtrans == RT_C2C ? L : pd.hcount;
-        for (int e = threadIdx.x; e < nrows * cnt; e += kGenThreads) {
+        for (int e = threadIdx.x; e < nrows * cnt; e += gen_threads<R>()) {
             const int rr = e / cnt, m = e - rr * cnt;
             dst[(row0 + rr) * pd.ostride + m] = lds[rr * LS + m];
         }
@@ -227,7 +227,7 @@ __device__ __forceinline__ void col_tile(const PassDesc& pd, const SymParams& sp
     };
 
     // ---- load (inverse passes multiply by the conjugate split twiddle first)
-    for (int e = threadIdx.x; e < L * W; e += kGenThreads) {
+    for (int e = threadIdx.x; e < L * W; e += gen_threads<R>()) {
         const int k = e / W, cc = e - k * W;
         const int64_t c = c0 + cc;
         cx<R> v = {R(0), R(0)};
@@ -250,7 +250,7 @@ __device__ __forceinline__ void col_tile(const PassDesc& pd, const SymParams& sp
         __shared__ SymCol Cs[64];
         __shared__ int Vs[64];
         // per-column part of the symbol (axes 1..d-1 fixed along a column)
-        for (int cc = threadIdx.x; cc < W; cc += kGenThreads) {
+        for (int cc = threadIdx.x; cc < W; cc += gen_threads<R>()) {
             const int64_t c = c0 + cc;
             int valid = col_valid(c) ? 1 : 0;
             int64_t f[3] = {0, 0, 0};
@@ -268,7 +268,7 @@ __device__ __forceinline__ void col_tile(const PassDesc& pd, const SymParams& sp
         }
         __syncthreads();
         const int64_t qpre = (o % pd.q_mod) * L;
-        for (int e = threadIdx.x; e < L * W; e += kGenThreads) {
+        for (int e = threadIdx.x; e < L * W; e += gen_threads<R>()) {
             const int k = e / W, cc = e - k * W;
             if (!Vs[cc]) continue;
             const int64_t f0 = pos_to_freq(sp, 0, qpre + k);
@@ -283,7 +283,7 @@ __device__ __forceinline__ void col_tile(const PassDesc& pd, const SymParams& sp
     if (pd.mode != MODE_FWD) tile_fft<R, true, true>(lds, pd, W, 1, W);
 
     // ---- store (forward passes multiply by the split twiddle last)
-    for (int e = threadIdx.x; e < L * W; e += kGenThreads) {
+    for (int e = threadIdx.x; e < L * W; e += gen_threads<R>()) {
         const int k = e / W, cc = e - k * W;
         const int64_t c = c0 + cc;
         if (!col_valid(c)) continue;
@@ -313,7 +313,7 @@ __device__ __forceinline__ int batch_find_g(const BatchItem* it, int n, uint32_t
 }
 
 template <typename R>
-__global__ __launch_bounds__(kGenThreads) void k_row(PassDesc pd, SymParams sp) {
+__global__ __launch_bounds__(gen_threads<R>()) void k_row(PassDesc pd, SymParams sp) {
     // The tile code indexes the descriptors' arrays with run-time indices; on the
     // kernel-argument copies that costs a private copy and several hundred VGPRs
     // (one wave per SIMD), on an LDS copy it is an LDS read.
@@ -327,12 +327,12 @@ __global__ __launch_bounds__(kGenThreads) void k_row(PassDesc pd, SymParams sp) 
     row_tile<R>(spd, ssp, blockIdx.x);
 }
 template <typename R>
-__global__ __launch_bounds__(kGenThreads) void k_row_b(const BatchItem* it, int n, const SymParams* sy) {
+__global__ __launch_bounds__(gen_threads<R>()) void k_row_b(const BatchItem* it, int n, const SymParams* sy) {
     const int i = batch_find_g(it, n, blockIdx.x);
     row_tile<R>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
 }
 template <typename R>
-__global__ __launch_bounds__(kGenThreads) void k_col(PassDesc pd, SymParams sp) {
+__global__ __launch_bounds__(gen_threads<R>()) void k_col(PassDesc pd, SymParams sp) {
     __shared__ PassDesc spd;  // see k_row
     __shared__ SymParams ssp;
     if (threadIdx.x == 0) {
@@ -343,7 +343,7 @@ __global__ __launch_bounds__(kGenThreads) void k_col(PassDesc pd, SymParams sp) 
     col_tile<R>(spd, ssp, blockIdx.x);
 }
 template <typename R>
-__global__ __launch_bounds__(kGenThreads) void k_col_b(const BatchItem* it, int n, const SymParams* sy) {
+__global__ __launch_bounds__(gen_threads<R>()) void k_col_b(const BatchItem* it, int n, const SymParams* sy) {
     const int i = batch_find_g(it, n, blockIdx.x);
     col_tile<R>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
 }
@@ -409,9 +409,9 @@ __global__ void k_symbol_power(double2* out, SymParams sp, int64_t total) {
 template <typename R>
 static hipError_t launch_pass_t(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st) {
     if (pd.kind == PASS_ROW)
-        hipLaunchKernelGGL(k_row<R>, dim3((unsigned)pd.ntiles), dim3(kGenThreads), lds, st, pd, sp);
+        hipLaunchKernelGGL(k_row<R>, dim3((unsigned)pd.ntiles), dim3(gen_threads<R>()), lds, st, pd, sp);
     else
-        hipLaunchKernelGGL(k_col<R>, dim3((unsigned)pd.ntiles), dim3(kGenThreads), lds, st, pd, sp);
+        hipLaunchKernelGGL(k_col<R>, dim3((unsigned)pd.ntiles), dim3(gen_threads<R>()), lds, st, pd, sp);
     return hipGetLastError();
 }
 
@@ -423,7 +423,7 @@ hipError_t launch_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t
 hipError_t launch_pass_batch(const PassDesc& proto, const BatchItem* items, int n, const SymParams* syms,
                              int64_t tiles, bool f64, size_t lds, hipStream_t st) {
     if (proto.fast) return launch_fast_batch(proto, items, n, syms, tiles, f64, lds, st);
-    const dim3 g((unsigned)tiles), b(kGenThreads);
+    const dim3 g((unsigned)tiles), b(f64 ? gen_threads<double>() : gen_threads<float>());
     if (proto.kind == PASS_ROW) {
         if (f64) hipLaunchKernelGGL(k_row_b<double>, g, b, lds, st, items, n, syms);
         else hipLaunchKernelGGL(k_row_b<float>, g, b, lds, st, items, n, syms);

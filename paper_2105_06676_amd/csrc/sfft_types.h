@@ -18,7 +18,10 @@
 namespace sfft {
 
 constexpr int kThreads = 256;     // threads per FFT workgroup (four wave64s)
-constexpr int kGenThreads = 512;  // threads per generic (mixed-radix) tile: 16 of its 8192 points each
+// threads per generic (mixed-radix) tile of up to 8192 points: 16 points each in
+// FP32, 8 in FP64 (the registers a stage holds across its barrier)
+template <typename R>
+constexpr int gen_threads() { return sizeof(R) == 8 ? 1024 : 512; }
 constexpr int kMaxStages = 16;    // radix stages per sub-transform
 constexpr int kMaxCoef = 125;     // (2r+1)^d for r <= 2, d <= 3
 constexpr int kMaxR = 2;          // largest stencil radius with a fused symbol
