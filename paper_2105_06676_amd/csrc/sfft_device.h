@@ -627,6 +627,35 @@ __device__ __forceinline__ void power_complex_dev(dcx* mu, dcx* out, int64_t T) 
     for (int e = 0; e < N; ++e) out[e] = dcx{1.0 - v[e].x, -v[e].y};
 }
 
+// lambda^T * scale for G modes of one column at axis-0 frequencies f[g] (below
+// 2^31), for a stencil of radius exactly RR: the RR * G phase reads are issued
+// before the first is used; the arithmetic is that of symbol_power_n.
+template <int G, int RR>
+__device__ __forceinline__ void symbol_power_g(const SymParams& sp, const SymCol& col, const uint32_t* f, dcx* out) {
+    const uint32_t n = (uint32_t)sp.n[0];
+    const dcx* t = (const dcx*)sp.eph[0];
+    dcx e[RR > 0 ? RR : 1][G];
+#pragma unroll
+    for (int o = 1; o <= RR; ++o)
+#pragma unroll
+        for (int k = 0; k < G; ++k) e[o - 1][k] = t[mul_mod_small((uint32_t)o, f[k], n)];
+    dcx mu[G];
+    symbol_mu_e<G, RR>(col, e, mu);
+    if (sp.real_sym) {
+        double m[G], o[G];
+#pragma unroll
+        for (int k = 0; k < G; ++k) m[k] = mu[k].x;
+        power_real_dev<G>(m, o, sp.T);
+#pragma unroll
+        for (int k = 0; k < G; ++k) out[k] = dcx{o[k] * sp.scale, 0.0};
+    } else {
+        dcx o[G];
+        power_complex_dev<G>(mu, o, sp.T);
+#pragma unroll
+        for (int k = 0; k < G; ++k) out[k] = dcx{o[k].x * sp.scale, o[k].y * sp.scale};
+    }
+}
+
 // lambda^T * scale for N modes of one column at axis-0 frequencies f0[e].
 template <int N>
 __device__ __forceinline__ void symbol_power_n(const SymParams& sp, const SymCol& col, const int64_t* f0, dcx* out) {

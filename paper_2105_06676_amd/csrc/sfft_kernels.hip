@@ -209,6 +209,34 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
 // ---------------------------------------------------------------------------
 // Column pass
 // ---------------------------------------------------------------------------
+// Multiply a column tile (W <= threads columns) by lambda^T * scale: tpc =
+// threads / W threads share a column (the first tpc * W threads take part); each
+// reads the column's part of the symbol once and takes every tpc-th row, four
+// rows at a time as independent chains.
+template <typename R, int RR>
+__device__ __forceinline__ void symbol_cols(cx<R>* lds, const SymParams& sp, const SymCol* Cs, const int* Vs, int L,
+                                            int W, int64_t qpre) {
+    constexpr int G = 4;
+    const int tpc = gen_threads<R>() / W;
+    if ((int)threadIdx.x >= tpc * W) return;
+    const int cc = threadIdx.x % W, k0 = threadIdx.x / W;
+    if (!Vs[cc]) return;
+    const SymCol col = Cs[cc];
+    for (int k = k0; k < L; k += G * tpc) {
+        uint32_t f[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) f[g] = (uint32_t)pos_to_freq(sp, 0, qpre + min(k + g * tpc, L - 1));
+        dcx v[G];
+        symbol_power_g<G, RR>(sp, col, f, v);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int kg = k + g * tpc;
+            if (kg >= L) continue;
+            cx<R>& x = lds[kg * W + cc];
+            x = cmul(x, cx<R>{R(v[g].x), R(v[g].y)});
+        }
+    }
+}
 template <typename R>
 __device__ __forceinline__ void col_tile(const PassDesc& pd, const SymParams& sp, uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -268,15 +296,9 @@ __device__ __forceinline__ void col_tile(const PassDesc& pd, const SymParams& sp
         }
         __syncthreads();
         const int64_t qpre = (o % pd.q_mod) * L;
-        for (int e = threadIdx.x; e < L * W; e += gen_threads<R>()) {
-            const int k = e / W, cc = e - k * W;
-            if (!Vs[cc]) continue;
-            const int64_t f0 = pos_to_freq(sp, 0, qpre + k);
-            dcx v;
-            symbol_power_n<1>(sp, Cs[cc], &f0, &v);
-            cx<R>& x = lds[k * W + cc];
-            x = cmul(x, cx<R>{R(v.x), R(v.y)});
-        }
+        if (sp.r <= 0) symbol_cols<R, 0>(lds, sp, Cs, Vs, L, W, qpre);
+        else if (sp.r == 1) symbol_cols<R, 1>(lds, sp, Cs, Vs, L, W, qpre);
+        else symbol_cols<R, 2>(lds, sp, Cs, Vs, L, W, qpre);
         __syncthreads();
     }
 
