@@ -113,17 +113,37 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
     const R* rin = (const R*)pd.rv.ptr;
     const cx<R>* htab = (const cx<R>*)pd.st_tab;  // exp(-2 pi i m / (L * st_mul))
 
+    // Real views: each row's base offset (-1: outside the view) once per row when
+    // the tile has few rows, instead of 64-bit divisions per element.
+    constexpr int kRowCache = 64;
+    __shared__ int64_t base_in[kRowCache], base_out[kRowCache];
+    const bool cached = nrows <= kRowCache && (pd.in_real || pd.out_real);
+    if (cached) {
+        for (int rr = threadIdx.x; rr < nrows; rr += gen_threads<R>()) {
+            int64_t idx[3];
+            const int64_t b = row_coords(pd, row0 + rr, idx);
+            if (pd.in_real) base_in[rr] = prefix_inside(pd.rv, pd.d, idx) ? prefix_offset(pd.rv, pd.d, b, idx) : -1;
+            if (pd.out_real) base_out[rr] = prefix_inside(pd.rvo, pd.d, idx) ? prefix_offset(pd.rvo, pd.d, b, idx) : -1;
+        }
+        __syncthreads();
+    }
+
     // ---- load
     if (pd.in_real) {
         const int64_t sl = pd.rv.stride[pd.d - 1];
         const int64_t el = pd.rv.ext[pd.d - 1];
         for (int e = threadIdx.x; e < nrows * L; e += gen_threads<R>()) {
             const int rr = e / L, m = e - rr * L;
-            int64_t idx[3];
-            const int64_t b = row_coords(pd, row0 + rr, idx);
+            int64_t base;
+            if (cached) {
+                base = base_in[rr];
+            } else {
+                int64_t idx[3];
+                const int64_t b = row_coords(pd, row0 + rr, idx);
+                base = prefix_inside(pd.rv, pd.d, idx) ? prefix_offset(pd.rv, pd.d, b, idx) : -1;
+            }
             cx<R> v = {R(0), R(0)};
-            if (prefix_inside(pd.rv, pd.d, idx)) {
-                const int64_t base = prefix_offset(pd.rv, pd.d, b, idx);
+            if (base >= 0) {
                 if (pd.rowtrans == RT_HALF) {
                     if (2 * m < el) v.x = rin[base + (int64_t)(2 * m) * sl];
                     if (2 * m + 1 < el) v.y = rin[base + (int64_t)(2 * m + 1) * sl];
@@ -188,13 +208,20 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
         for (int e = threadIdx.x; e < nrows * per; e += gen_threads<R>()) {
             const int rr = e / per, m = e - rr * per;
             if (m >= el) continue;
-            int64_t idx[3];
-            const int64_t b = row_coords(pd, row0 + rr, idx);
-            if (!prefix_inside(pd.rvo, pd.d, idx)) continue;
-            idx[pd.d - 1] = m;
-            if (!keep_cell(pd.keep, pd.d, b, idx)) continue;
+            int64_t base;
+            if (cached && !pd.keep.enabled) {
+                base = base_out[rr];
+                if (base < 0) continue;
+            } else {
+                int64_t idx[3];
+                const int64_t b = row_coords(pd, row0 + rr, idx);
+                if (!prefix_inside(pd.rvo, pd.d, idx)) continue;
+                idx[pd.d - 1] = m;
+                if (!keep_cell(pd.keep, pd.d, b, idx)) continue;
+                base = prefix_offset(pd.rvo, pd.d, b, idx);
+            }
             const cx<R> z = lds[rr * LS + (half ? (m >> 1) : m)];
-            rout[prefix_offset(pd.rvo, pd.d, b, idx) + (int64_t)m * sl] = half ? ((m & 1) ? z.y : z.x) : z.x;
+            rout[base + (int64_t)m * sl] = half ? ((m & 1) ? z.y : z.x) : z.x;
         }
     } else {
         cx<R>* dst = (cx<R>*)pd.buf;
