@@ -281,19 +281,44 @@ __device__ __forceinline__ void col_tile(const PassDesc& pd, const SymParams& sp
         return true;
     };
 
+    // Per-column validity and split-twiddle step once per tile column when the
+    // tile is narrow enough, instead of 64-bit divisions per element (twj < 0:
+    // column not valid).
+    constexpr int kColCache = 256;
+    __shared__ int64_t col_twj[kColCache];
+    const bool cached = W <= kColCache;
+    if (cached) {
+        for (int cc = threadIdx.x; cc < W; cc += gen_threads<R>()) {
+            const int64_t c = c0 + cc;
+            col_twj[cc] = col_valid(c) ? (pd.tw ? c / pd.tw_div : 0) : -1;
+        }
+        __syncthreads();
+    }
+    auto column = [&](int cc, int64_t* twj) -> bool {
+        if (cached) {
+            *twj = col_twj[cc];
+            return *twj >= 0;
+        }
+        const int64_t c = c0 + cc;
+        if (!col_valid(c)) return false;
+        *twj = pd.tw ? c / pd.tw_div : 0;
+        return true;
+    };
+
     // ---- load (inverse passes multiply by the conjugate split twiddle first)
     for (int e = threadIdx.x; e < L * W; e += gen_threads<R>()) {
         const int k = e / W, cc = e - k * W;
         const int64_t c = c0 + cc;
         cx<R> v = {R(0), R(0)};
-        if (col_valid(c)) {
+        int64_t twj;
+        if (column(cc, &twj)) {
             if (pd.in_real) {
                 const int64_t m = (int64_t)k * pd.kstride + c;
                 if (m < pd.rv.ext[0]) v.x = ((const R*)pd.rv.ptr)[o * pd.rv.boff + m * pd.rv.stride[0]];
             } else {
                 v = buf[o * pd.ostride + (int64_t)k * pd.kstride + c];
             }
-            if (pd.mode == MODE_INV && pd.tw) v = cmulc(v, step_twiddle<R>(pd, (int64_t)k * (c / pd.tw_div)));
+            if (pd.mode == MODE_INV && pd.tw) v = cmulc(v, step_twiddle<R>(pd, (int64_t)k * twj));
         }
         lds[k * W + cc] = v;
     }
@@ -335,9 +360,10 @@ __device__ __forceinline__ void col_tile(const PassDesc& pd, const SymParams& sp
     for (int e = threadIdx.x; e < L * W; e += gen_threads<R>()) {
         const int k = e / W, cc = e - k * W;
         const int64_t c = c0 + cc;
-        if (!col_valid(c)) continue;
+        int64_t twj;
+        if (!column(cc, &twj)) continue;
         cx<R> v = lds[k * W + cc];
-        if (pd.mode == MODE_FWD && pd.tw) v = cmul(v, step_twiddle<R>(pd, (int64_t)k * (c / pd.tw_div)));
+        if (pd.mode == MODE_FWD && pd.tw) v = cmul(v, step_twiddle<R>(pd, (int64_t)k * twj));
         if (pd.out_real) {
             const int64_t m = (int64_t)k * pd.kstride + c;
             if (m >= pd.rvo.ext[0]) continue;
