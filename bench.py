@@ -202,7 +202,8 @@ def other_workloads(sfft, torch, only=None):
     for name, dts in (("heat1d_65536", ("f64",)), ("star3d_512", ("f32",)),
                       ("box2d_aperiodic_4096", ("f64", "f32")), ("upwind2d_aperiodic_4096", ("f64", "f32")),
                       ("wave2d_leapfrog_4096", ("f32", "f64")),
-                      ("heat2d_backward_euler_4096", ("f32", "f64")), ("jacobi2d_8191_prime", ("f32",))):
+                      ("heat2d_backward_euler_4096", ("f32", "f64")), ("jacobi2d_6300x6720_smooth", ("f32",)),
+                      ("jacobi2d_8191_prime", ("f32",))):
         w = wl.config(name)
         for dt in dts:
             if only is not None and f"{name}_{dt}" not in only:

@@ -220,6 +220,11 @@ def config(name: str) -> Workload:
         c[1, 1], c[0, 1], c[1, 0] = 0.5, 0.25, 0.25
         return Workload("upwind2d_aperiodic_4096", 2, (4096, 4096), 1, 512, c, 9, "uniform", aperiodic=True,
                         dtypes=("f64", "f32"), notes="2-D aperiodic upwind 3-point stencil, fixed frame")
+    if name == "jacobi2d_6300x6720_smooth":
+        return Workload("jacobi2d_6300x6720_smooth", 2, (6300, 6720), 1, 4096, jacobi5_coeffs(), 8, "uniform",
+                        dtypes=("f32", "f64"),
+                        notes="2-D periodic 5-point Jacobi on a 7-smooth, non-power-of-two torus "
+                              "(6300 = 2^2 3^2 5^2 7, 6720 = 2^6 3 5 7; mixed-radix transforms)")
     if name == "jacobi2d_8191_prime":
         return Workload("jacobi2d_8191_prime", 2, (8191, 8191), 1, 4096, jacobi5_coeffs(), 8, "uniform",
                         dtypes=("f32", "f64"),
