@@ -45,8 +45,10 @@
  * SFFT_EHIP (a HIP runtime error; the grid is then unspecified).  When
  * validation fails the grid is untouched.
  *
- * The library owns its device workspace, FFT plans and twiddle/phase tables,
- * kept in an implicit per-device context and released at process exit.
+ * The library owns its device workspace, FFT plans and twiddle/phase/chirp-z
+ * tables, kept in an implicit per-device context and released at process exit;
+ * the first call that needs a new table or a larger workspace allocates it (and
+ * chirp-z tables synchronise the stream once while they are built).
  * Workspace is per (device, stream): calls on one stream are ordered by the
  * stream; calls on different streams of one device may run concurrently.
  */
