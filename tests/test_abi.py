@@ -91,3 +91,15 @@ def test_plan_schedule_shape(dims, dtype):
     for q in p["passes"]:
         assert int(np.prod(q["radices"] or [1])) == q["L"]
         assert q["lds_bytes"] <= 160 * 1024
+
+
+@pytest.mark.parametrize("n", [32768, 65536, 1 << 17, 1 << 20])
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_long_power_of_two_axes_stay_on_register_kernels(n, dtype):
+    """A 1-D power-of-two extent too long for one row pass is split so that every
+    level (the strided cofactor included) runs on the register kernels: the strided
+    levels are at least 16 points long."""
+    import paper_2105_06676_amd as s
+    p = s.plan_describe((n,), dtype)
+    assert all(q["fast"] == 1 for q in p["passes"]), [(q["name"], q["L"], q["fast"]) for q in p["passes"]]
+    assert all(q["L"] >= 16 for q in p["passes"])
