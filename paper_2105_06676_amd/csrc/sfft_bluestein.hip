@@ -142,11 +142,11 @@ __global__ void k_symbol_full(cx<R>* w, SymParams sp, int64_t N) {
         double m[G], o[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) m[g] = mu[g].x;
-        power_real_dev<G>(m, o, sp.T);
+        power_real_dev<G>(m, o, sp.T, sp.switching);
 #pragma unroll
         for (int g = 0; g < G; ++g) out[g] = dcx{o[g] * sp.scale, 0.0};
     } else {
-        power_complex_dev<G>(mu, out, sp.T);
+        power_complex_dev<G>(mu, out, sp.T, sp.switching);
 #pragma unroll
         for (int g = 0; g < G; ++g) out[g] = dcx{out[g].x * sp.scale, out[g].y * sp.scale};
     }
@@ -177,11 +177,11 @@ __global__ void k_symbol_rows(cx<R>* w, SymParams sp, int64_t rows, int64_t ncol
             double m[G], o[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) m[g] = mu[g].x;
-            power_real_dev<G>(m, o, sp.T);
+            power_real_dev<G>(m, o, sp.T, sp.switching);
 #pragma unroll
             for (int g = 0; g < G; ++g) out[g] = dcx{o[g] * sp.scale, 0.0};
         } else {
-            power_complex_dev<G>(mu, out, sp.T);
+            power_complex_dev<G>(mu, out, sp.T, sp.switching);
 #pragma unroll
             for (int g = 0; g < G; ++g) out[g] = dcx{out[g].x * sp.scale, out[g].y * sp.scale};
         }

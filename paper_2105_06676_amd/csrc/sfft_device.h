@@ -585,12 +585,20 @@ __device__ __forceinline__ dcx symbol_power_at(const SymParams& sp, const SymCol
 // Branch-free form for the solver's middle passes: the deviations of the running
 // square (1 - lambda^(2^k)) and of the product are updated for N modes at once
 // (independent chains for instruction-level parallelism) over the bits of T,
-// which are the same for every lane.  This keeps lambda^T within a few ulps of
-// absolute error for every mode (relative accuracy near lambda = 1, where the
-// surviving modes are); a mode that decays to a tiny value only loses relative
-// accuracy of that tiny value.
+// which are the same for every lane.  Every mode keeps lambda^T within a few
+// ulps of absolute error, which is relative accuracy for the dominant modes as
+// long as the largest |lambda| is 1: the host guarantees that by dividing
+// coefficients of one sign by lambda(0) = sum(c) (then |lambda(k)| <= lambda(0))
+// and folding lambda(0)^T into the scale.  Stencils of mixed sign have no such
+// bound and take the switching form per mode instead (SWITCHING = true), which
+// keeps every mode's relative accuracy at the price of divergent branches.
 template <int N>
-__device__ __forceinline__ void power_real_dev(double* mu, double* out, int64_t T) {
+__device__ __forceinline__ void power_real_dev(double* mu, double* out, int64_t T, bool switching) {
+    if (switching) {
+#pragma unroll
+        for (int e = 0; e < N; ++e) out[e] = power_real(mu[e], T);
+        return;
+    }
     double v[N];
 #pragma unroll
     for (int e = 0; e < N; ++e) v[e] = 0.0;
@@ -609,7 +617,12 @@ __device__ __forceinline__ void power_real_dev(double* mu, double* out, int64_t 
 }
 
 template <int N>
-__device__ __forceinline__ void power_complex_dev(dcx* mu, dcx* out, int64_t T) {
+__device__ __forceinline__ void power_complex_dev(dcx* mu, dcx* out, int64_t T, bool switching) {
+    if (switching) {
+#pragma unroll
+        for (int e = 0; e < N; ++e) out[e] = power_complex(mu[e], T);
+        return;
+    }
     dcx v[N];
 #pragma unroll
     for (int e = 0; e < N; ++e) v[e] = dcx{0.0, 0.0};
@@ -645,12 +658,12 @@ __device__ __forceinline__ void symbol_power_g(const SymParams& sp, const SymCol
         double m[G], o[G];
 #pragma unroll
         for (int k = 0; k < G; ++k) m[k] = mu[k].x;
-        power_real_dev<G>(m, o, sp.T);
+        power_real_dev<G>(m, o, sp.T, sp.switching);
 #pragma unroll
         for (int k = 0; k < G; ++k) out[k] = dcx{o[k] * sp.scale, 0.0};
     } else {
         dcx o[G];
-        power_complex_dev<G>(mu, o, sp.T);
+        power_complex_dev<G>(mu, o, sp.T, sp.switching);
 #pragma unroll
         for (int k = 0; k < G; ++k) out[k] = dcx{o[k].x * sp.scale, o[k].y * sp.scale};
     }
@@ -666,12 +679,12 @@ __device__ __forceinline__ void symbol_power_n(const SymParams& sp, const SymCol
         double m[N], o[N];
 #pragma unroll
         for (int e = 0; e < N; ++e) m[e] = mu[e].x;
-        power_real_dev<N>(m, o, sp.T);
+        power_real_dev<N>(m, o, sp.T, sp.switching);
 #pragma unroll
         for (int e = 0; e < N; ++e) out[e] = dcx{o[e] * sp.scale, 0.0};
     } else {
         dcx o[N];
-        power_complex_dev<N>(mu, o, sp.T);
+        power_complex_dev<N>(mu, o, sp.T, sp.switching);
 #pragma unroll
         for (int e = 0; e < N; ++e) out[e] = dcx{o[e].x * sp.scale, o[e].y * sp.scale};
     }

@@ -224,7 +224,7 @@ __device__ __forceinline__ void apply_symbol_r(cx<R>* v, cx<R>* lds, const SymPa
             fetch(g);
             double m[G], o[G];
             symbol_mu_real_e<G, RR>(col, ec, m);
-            power_real_dev<G>(m, o, sp.T);
+            power_real_dev<G>(m, o, sp.T, sp.switching);
 #pragma unroll
             for (int e = 0; e < G; ++e) sl[threadIdx.x + NTH * (g + e)] = R(o[e] * sp.scale);
             advance();
@@ -237,7 +237,7 @@ __device__ __forceinline__ void apply_symbol_r(cx<R>* v, cx<R>* lds, const SymPa
             fetch(g);
             dcx m[G], o[G];
             symbol_mu_e<G, RR>(col, ec, m);
-            power_complex_dev<G>(m, o, sp.T);
+            power_complex_dev<G>(m, o, sp.T, sp.switching);
 #pragma unroll
             for (int e = 0; e < G; ++e) lds[threadIdx.x + NTH * (g + e)] = cx<R>{R(o[e].x * sp.scale), R(o[e].y * sp.scale)};
             advance();

@@ -3,13 +3,15 @@
 // Mode k of field i at time t+1 is sum_j Lambda_ij(k) x_j(k), Lambda_ij the symbol
 // of stencil (i, j) (appendix on vector-valued fields), so the T-step map is the
 // matrix power Lambda(k)^T, taken by binary repeated squaring of the matrix.  As
-// in the scalar path the power is carried in deviation form: D = I - Lambda,
+// in the scalar path the power starts in deviation form: D = I - Lambda,
 // squaring I - D gives I - (2D - D^2) and (I - V)(I - D) = I - (V + D - V D); every
 // matrix involved is a polynomial in Lambda, so the products commute.  The
 // deviation entries come from the per-axis phase tables E(m) = exp(2 pi i m / n) - 1
 // (a cell offset o contributes prod_a (1 + E_a) - 1, built axis by axis), so modes
-// near Lambda = I keep their relative accuracy.  One thread per mode, FP64
-// throughout; spectra are read and written in the solve's precision.
+// near Lambda = I keep their relative accuracy; a running square or product leaves
+// the deviation form once its deviation is far from 0 (largest row sum above 1/2),
+// so modes that decay keep theirs too.  One thread per mode, FP64 throughout;
+// spectra are read and written in the solve's precision.
 #include <hip/hip_runtime.h>
 
 #include "sfft_device.h"
@@ -43,6 +45,104 @@ __device__ __forceinline__ void matmul_real(const double (&a)[M][M], const doubl
             for (int k = 1; k < M; ++k) s = fma(a[i][k], b[k][j], s);
             c[i][j] = s;
         }
+}
+
+// Element operations shared by the real and the complex matrix power.
+__device__ __forceinline__ double e_add(double a, double b) { return a + b; }
+__device__ __forceinline__ dcx e_add(dcx a, dcx b) { return dadd(a, b); }
+__device__ __forceinline__ double e_sub(double a, double b) { return a - b; }
+__device__ __forceinline__ dcx e_sub(dcx a, dcx b) { return dsub(a, b); }
+__device__ __forceinline__ double e_abs(double a) { return fabs(a); }
+__device__ __forceinline__ double e_abs(dcx a) { return fabs(a.x) + fabs(a.y); }
+__device__ __forceinline__ void e_set(double& a, double v) { a = v; }
+__device__ __forceinline__ void e_set(dcx& a, double v) { a = dcx{v, 0.0}; }
+template <int M>
+__device__ __forceinline__ void mm(const double (&a)[M][M], const double (&b)[M][M], double (&c)[M][M]) { matmul_real<M>(a, b, c); }
+template <int M>
+__device__ __forceinline__ void mm(const dcx (&a)[M][M], const dcx (&b)[M][M], dcx (&c)[M][M]) { matmul<M>(a, b, c); }
+
+// Largest row sum of |entries| (|re| + |im| for complex entries): a bound on the
+// deviation's size that decides when to leave the deviation form.
+template <int M, typename E>
+__device__ __forceinline__ double row_norm(const E (&a)[M][M]) {
+    double m = 0.0;
+#pragma unroll
+    for (int i = 0; i < M; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) s += e_abs(a[i][j]);
+        m = fmax(m, s);
+    }
+    return m;
+}
+
+// a <- I - a
+template <int M, typename E>
+__device__ __forceinline__ void one_minus(E (&a)[M][M]) {
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+            E id;
+            e_set(id, i == j ? 1.0 : 0.0);
+            a[i][j] = e_sub(id, a[i][j]);
+        }
+}
+
+// P = (I - D)^T by binary repeated squaring (Sec. 3 Step 2 on the symbol
+// matrix).  The running square and the product are kept as deviations from I
+// while both are close to I (2D - D^2 and V + D - V D) and as plain matrices
+// from the point where a deviation's row sum exceeds 1/2.  D is overwritten.
+template <int M, typename E>
+__device__ __forceinline__ void mat_power(E (&D)[M][M], E (&P)[M][M], int64_t T) {
+    E V[M][M], Q[M][M];
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int j = 0; j < M; ++j) e_set(V[i][j], 0.0);
+    bool sd = true, vd = true;
+    if (row_norm<M>(D) > 0.5) { one_minus<M>(D); sd = false; }
+    for (int64_t Rb = T; Rb > 0; Rb >>= 1) {
+        if (Rb & 1) {
+            if (vd && sd) {
+                mm(V, D, Q);
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+#pragma unroll
+                    for (int j = 0; j < M; ++j) V[i][j] = e_sub(e_add(V[i][j], D[i][j]), Q[i][j]);
+            } else {
+                if (vd) one_minus<M>(V);
+                if (sd) one_minus<M>(D);
+                mm(V, D, Q);
+                if (sd) one_minus<M>(D);
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+#pragma unroll
+                    for (int j = 0; j < M; ++j) V[i][j] = Q[i][j];
+                vd = false;
+            }
+        }
+        if (Rb > 1) {
+            mm(D, D, Q);
+            if (sd) {
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+#pragma unroll
+                    for (int j = 0; j < M; ++j) D[i][j] = e_sub(e_add(D[i][j], D[i][j]), Q[i][j]);
+                if (row_norm<M>(D) > 0.5) { one_minus<M>(D); sd = false; }
+            } else {
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+#pragma unroll
+                    for (int j = 0; j < M; ++j) D[i][j] = Q[i][j];
+            }
+        }
+    }
+    if (vd) one_minus<M>(V);
+#pragma unroll
+    for (int i = 0; i < M; ++i)
+#pragma unroll
+        for (int j = 0; j < M; ++j) P[i][j] = V[i][j];
 }
 
 // Stored position -> frequency along axis a in 32-bit arithmetic (extents below 2^31).
@@ -162,12 +262,7 @@ __global__ __launch_bounds__(256) void k_fields_symbol(FieldParams fp, SymParams
             const dcx num = dsub(muS, muQ);
             D = dcx{(num.x * lq.x + num.y * lq.y) / lq2, (num.y * lq.x - num.x * lq.y) / lq2};
         }
-        dcx V = {0.0, 0.0};
-        for (int64_t Rb = sp.T; Rb > 0; Rb >>= 1) {
-            if (Rb & 1) V = dsub(dadd(V, D), dmul(V, D));
-            if (Rb > 1) D = dsub(dcx{2.0 * D.x, 2.0 * D.y}, dmul(D, D));
-        }
-        const dcx y = dsub(x[0], dmul(V, x[0]));
+        const dcx y = dmul(power_complex(D, sp.T), x[0]);
         ws[idx] = cx<R>{R(y.x * sp.scale), R(y.y * sp.scale)};
         return;
     }
@@ -175,14 +270,11 @@ __global__ __launch_bounds__(256) void k_fields_symbol(FieldParams fp, SymParams
     if (fp.real_sym) {
         // Point-symmetric blocks: the imaginary parts of offsets o and -o cancel,
         // the symbol matrix is real and so are its powers.
-        double D[M][M], V[M][M], P[M][M];
+        double D[M][M], P[M][M];
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
-            for (int j = 0; j < M; ++j) {
-                D[i][j] = fp.cK[i * M + j];
-                V[i][j] = 0.0;
-            }
+            for (int j = 0; j < M; ++j) D[i][j] = fp.cK[i * M + j];
         // offsets o and -o share Re(dev) and their coefficient
         for_each_offset<DIM, true>(sp, E, [&](int q, dcx dev) {
             const double d2 = 2.0 * dev.x;
@@ -191,30 +283,15 @@ __global__ __launch_bounds__(256) void k_fields_symbol(FieldParams fp, SymParams
 #pragma unroll
                 for (int j = 0; j < M; ++j) D[i][j] = fma(-cc[(i * M + j) * fp.nof + q], d2, D[i][j]);
         });
-        for (int64_t Rb = sp.T; Rb > 0; Rb >>= 1) {
-            if (Rb & 1) {
-                matmul_real<M>(V, D, P);
-#pragma unroll
-                for (int i = 0; i < M; ++i)
-#pragma unroll
-                    for (int j = 0; j < M; ++j) V[i][j] = (V[i][j] + D[i][j]) - P[i][j];
-            }
-            if (Rb > 1) {
-                matmul_real<M>(D, D, P);
-#pragma unroll
-                for (int i = 0; i < M; ++i)
-#pragma unroll
-                    for (int j = 0; j < M; ++j) D[i][j] = fma(2.0, D[i][j], -P[i][j]);
-            }
-        }
-        // y = (I - V) x * scale
+        mat_power<M>(D, P, sp.T);
+        // y = Lambda^T x * scale
 #pragma unroll
         for (int i = 0; i < M; ++i) {
-            dcx y = x[i];
+            dcx y = {0.0, 0.0};
 #pragma unroll
             for (int j = 0; j < M; ++j) {
-                y.x = fma(-V[i][j], x[j].x, y.x);
-                y.y = fma(-V[i][j], x[j].y, y.y);
+                y.x = fma(P[i][j], x[j].x, y.x);
+                y.y = fma(P[i][j], x[j].y, y.y);
             }
             ws[i * fp.fstride + idx] = cx<R>{R(y.x * sp.scale), R(y.y * sp.scale)};
         }
@@ -222,14 +299,11 @@ __global__ __launch_bounds__(256) void k_fields_symbol(FieldParams fp, SymParams
     }
 
     // D = K - sum_o c_o * dev_o
-    dcx D[M][M], V[M][M], P[M][M];
+    dcx D[M][M], P[M][M];
 #pragma unroll
     for (int i = 0; i < M; ++i)
 #pragma unroll
-        for (int j = 0; j < M; ++j) {
-            D[i][j] = dcx{fp.cK[i * M + j], 0.0};
-            V[i][j] = dcx{0.0, 0.0};
-        }
+        for (int j = 0; j < M; ++j) D[i][j] = dcx{fp.cK[i * M + j], 0.0};
     for_each_offset<DIM, false>(sp, E, [&](int q, dcx dev) {
 #pragma unroll
         for (int i = 0; i < M; ++i)
@@ -240,29 +314,14 @@ __global__ __launch_bounds__(256) void k_fields_symbol(FieldParams fp, SymParams
                 D[i][j].y = fma(-c, dev.y, D[i][j].y);
             }
     });
-    // V = I - Lambda^T by repeated squaring of I - D
-    for (int64_t Rb = sp.T; Rb > 0; Rb >>= 1) {
-        if (Rb & 1) {
-            matmul<M>(V, D, P);
-#pragma unroll
-            for (int i = 0; i < M; ++i)
-#pragma unroll
-                for (int j = 0; j < M; ++j) V[i][j] = dsub(dadd(V[i][j], D[i][j]), P[i][j]);
-        }
-        if (Rb > 1) {
-            matmul<M>(D, D, P);
-#pragma unroll
-            for (int i = 0; i < M; ++i)
-#pragma unroll
-                for (int j = 0; j < M; ++j) D[i][j] = dsub(dcx{2.0 * D[i][j].x, 2.0 * D[i][j].y}, P[i][j]);
-        }
-    }
-    // y = (I - V) x * scale
+    // P = Lambda^T by repeated squaring of I - D
+    mat_power<M>(D, P, sp.T);
+    // y = Lambda^T x * scale
 #pragma unroll
     for (int i = 0; i < M; ++i) {
-        dcx y = x[i];
+        dcx y = {0.0, 0.0};
 #pragma unroll
-        for (int j = 0; j < M; ++j) y = dsub(y, dmul(V[i][j], x[j]));
+        for (int j = 0; j < M; ++j) y = dadd(y, dmul(P[i][j], x[j]));
         ws[i * fp.fstride + idx] = cx<R>{R(y.x * sp.scale), R(y.y * sp.scale)};
     }
 }

@@ -248,23 +248,46 @@ void fill_symbol(SymParams& sp, const double* coeffs, int r, int d, int64_t T, d
     sp.r = r;
     sp.ncoef = nc;
     sp.T = T;
-    sp.scale = scale;
-    // 1 - sum(c) with the sum carried as hi + lo (Neumaier's compensated sum); when
-    // the sum is close to 1, 1 - hi is exact and only the final subtraction rounds.
+    // sum(c) carried as s + comp (Neumaier's compensated sum): lambda(0) exactly
+    // to double-double precision.
     double s = 0.0, comp = 0.0;
+    bool nonneg = true, nonpos = true;
     for (int i = 0; i < nc; ++i) {
-        sp.c[i] = coeffs[i];
         const double t = s + coeffs[i];
         if (std::fabs(s) >= std::fabs(coeffs[i])) comp += (s - t) + coeffs[i];
         else comp += (coeffs[i] - t) + s;
         s = t;
+        nonneg = nonneg && coeffs[i] >= 0.0;
+        nonpos = nonpos && coeffs[i] <= 0.0;
     }
-    sp.one_minus_sum = (1.0 - s) - comp;
     // point symmetric coefficients (c[o] == c[-o]) give a real symbol
     int sym = 1;
     for (int i = 0; i < nc; ++i)
         if (coeffs[i] != coeffs[nc - 1 - i]) { sym = 0; break; }
     sp.real_sym = sym;
+    if ((nonneg || nonpos) && s != 0.0) {
+        // One sign: |lambda(k)| <= |sum c| = |lambda(0)| for every k.  Solve with
+        // c / lambda(0), whose symbol is exactly 1 at k = 0 (so 1 - sum = 0), and
+        // multiply the result by lambda(0)^T, formed here in extended precision as
+        // exp(T log|lambda(0)|) with log(s + comp) = log s + log1p(comp / s).
+        const long double rho = (long double)s + (long double)comp;
+        for (int i = 0; i < nc; ++i) sp.c[i] = (double)((long double)coeffs[i] / rho);
+        sp.one_minus_sum = 0.0;
+        const long double as = std::fabs((long double)s);
+        const long double lg = std::log(as) + std::log1p((long double)comp / (long double)s);
+        long double p = std::exp((long double)T * lg);
+        if (s < 0.0 && (T & 1)) p = -p;
+        sp.scale = (double)((long double)scale * p);
+        sp.switching = 0;
+    } else {
+        // Mixed signs (or sum 0): no bound on |lambda| from lambda(0); every mode
+        // takes the switching power.  1 - sum(c): when the sum is close to 1,
+        // 1 - s is exact and only the final subtraction rounds.
+        for (int i = 0; i < nc; ++i) sp.c[i] = coeffs[i];
+        sp.one_minus_sum = (1.0 - s) - comp;
+        sp.scale = scale;
+        sp.switching = 1;
+    }
 }
 
 RealView dense_view(void* ptr, int d, const int64_t* dims) {

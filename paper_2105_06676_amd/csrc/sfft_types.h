@@ -66,9 +66,16 @@ struct KeepRule {
 // Everything the fused middle pass needs to form lambda(k)^T / N in FP64.
 struct SymParams {
     int d, r, ncoef, real_sym;
+    // 0: coefficients of one sign, normalised on the host by lambda(0) = sum(c)
+    //    (the largest |lambda| of all modes), so the branch-free deviation-form
+    //    power keeps the accuracy of the dominant modes; 1: mixed signs, every
+    //    mode leaves the deviation form once it is far from 1 (relative accuracy
+    //    per mode, data-dependent branches)
+    int switching;
+    int pad_sym;
     int64_t T;
-    double one_minus_sum;     // 1 - sum(c), exact (host TwoSum)
-    double scale;             // 1 / prod(n)
+    double one_minus_sum;     // 1 - sum(c), exact (host TwoSum); 0 after normalisation
+    double scale;             // lambda(0)^T / prod(n) after normalisation, else 1 / prod(n)
     int64_t n[3];             // transform extents per axis
     int nlev[3];              // sub-transform levels per axis
     int64_t sub[3][3];        // sub-lengths per axis in pass order

@@ -43,5 +43,27 @@ def rel_l2(y: np.ndarray, ref: np.ndarray) -> float:
     return float(num / den) if den > 0 else float(num)
 
 
-# Tolerances stated for the path: relative L2 against the FP64 oracle.
+def max_abs_rel(y: np.ndarray, ref: np.ndarray) -> float:
+    """max |y - ref| / max |ref|: the largest single-cell error on the scale of the result."""
+    den = float(np.max(np.abs(ref))) if ref.size else 0.0
+    num = float(np.max(np.abs(y - ref))) if ref.size else 0.0
+    return num / den if den > 0 else num
+
+
+def errors(y: np.ndarray, ref: np.ndarray) -> dict:
+    return {"rel_l2": rel_l2(y, ref), "max_abs": float(np.max(np.abs(y - ref))) if ref.size else 0.0,
+            "max_abs_rel": max_abs_rel(y, ref)}
+
+
+def assert_close(y: np.ndarray, ref: np.ndarray, tol: float, what=None) -> None:
+    """Both gates: relative L2 error and the largest cell error relative to max |ref|
+    are each at most tol (a norm alone would hide a few bad cells in a large grid)."""
+    assert y.shape == ref.shape, (y.shape, ref.shape, what)
+    assert np.all(np.isfinite(y)), ("non-finite output", what)
+    e = errors(y, ref)
+    assert e["rel_l2"] <= tol and e["max_abs_rel"] <= tol, (e, tol, what)
+
+
+# Tolerances stated for the path against the FP64 oracle (relative L2 and the
+# largest cell error relative to max |ref|).
 TOL = {"f32": 1e-5, "f64": 1e-12}

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_util import TOL, gpu_aperiodic, rel_l2, rounded_input
+from gpu_util import TOL, assert_close, gpu_aperiodic, rel_l2, rounded_input
 
 pytestmark = pytest.mark.gpu
 
@@ -48,7 +48,7 @@ def test_aperiodic_small(dtype, dims, r, T, cut):
     ref = oracle.aperiodic(rounded_input(a, dtype), c, T)
     with cutoff(cut):
         got = gpu_aperiodic(a, c, T, dtype)
-    assert rel_l2(got, ref) <= TOL[dtype], (dims, r, T, cut)
+    assert_close(got, ref, TOL[dtype], (dims, r, T, cut))
     # the frame is read-only
     inner = tuple(slice(r, r + n) for n in dims)
     mask = np.ones(got.shape, bool)
@@ -65,13 +65,13 @@ def test_aperiodic_deep_recursion(dtype, dims, T, cut):
     ref = oracle.aperiodic(rounded_input(a, dtype), c, T)
     with cutoff(cut):
         got = gpu_aperiodic(a, c, T, dtype)
-    assert rel_l2(got, ref) <= TOL[dtype]
+    assert_close(got, ref, TOL[dtype])
 
 
 def test_aperiodic_non_smooth_extents_and_r0():
     c, a = _case((41, 43), 1, 5)
     ref = oracle.aperiodic(a, c, 9)
-    assert rel_l2(gpu_aperiodic(a, c, 9, "f64"), ref) <= 1e-12
+    assert_close(gpu_aperiodic(a, c, 9, "f64"), ref, 1e-12)
     c0 = np.array([[0.5]])
     b = wl.uniform(6, "grid", 11 * 13).reshape(11, 13)
     np.testing.assert_allclose(gpu_aperiodic(b, c0, 5, "f64"), 0.5 ** 5 * b, rtol=1e-13)
@@ -100,7 +100,7 @@ def test_box2d_aperiodic_reduced_sizes(dtype):
         a = wl.uniform(w.seed, "grid", store[0] * store[1]).reshape(store)
         ref = oracle.aperiodic(rounded_input(a, dtype), w.coeffs, T)
         got = gpu_aperiodic(a, w.coeffs, T, dtype)
-        assert rel_l2(got, ref) <= TOL[dtype], (n, T)
+        assert_close(got, ref, TOL[dtype], (n, T))
 
 
 @pytest.mark.slow
@@ -119,11 +119,11 @@ def test_box2d_aperiodic_4096_full_size_sampled(dtype):
     # top-left corner: interior cells [0, K)^2 (stored [1, K+1)); box up to K + s beyond
     box = src[: K + s + 2, : K + s + 2]
     ref = oracle.aperiodic(box, w.coeffs, w.T)
-    assert rel_l2(got[1:K + 1, 1:K + 1], ref[1:K + 1, 1:K + 1]) <= TOL[dtype]
+    assert_close(got[1:K + 1, 1:K + 1], ref[1:K + 1, 1:K + 1], TOL[dtype])
     # bottom-right corner
     box = src[-(K + s + 2):, -(K + s + 2):]
     ref = oracle.aperiodic(box, w.coeffs, w.T)
-    assert rel_l2(got[-(K + 1):-1, -(K + 1):-1], ref[-(K + 1):-1, -(K + 1):-1]) <= TOL[dtype]
+    assert_close(got[-(K + 1):-1, -(K + 1):-1], ref[-(K + 1):-1, -(K + 1):-1], TOL[dtype])
     # an edge strip straddling the band boundary (depth r*T from the top face),
     # away from corners; the box reaches r*T + 1 cells beyond every checked cell
     # except at the real frame
@@ -131,7 +131,7 @@ def test_box2d_aperiodic_4096_full_size_sampled(dtype):
     box = src[: 2 * s + h + 2, c0 - h - s: c0 + h + s + 2]
     ref = oracle.aperiodic(box, w.coeffs, w.T)
     rows = slice(1, 1 + s + h)
-    assert rel_l2(got[rows, c0 - h + 1: c0 + h + 1], ref[rows, s + 1: s + 1 + K]) <= TOL[dtype]
+    assert_close(got[rows, c0 - h + 1: c0 + h + 1], ref[rows, s + 1: s + 1 + K], TOL[dtype])
 
 
 def _biased(shape_offsets, seed):
@@ -172,4 +172,4 @@ def test_aperiodic_biased_stencils(name, dims, spec, T, cut, dtype):
     ref = oracle.aperiodic(rounded_input(a, dtype), c, T)
     with cutoff(cut):
         got = gpu_aperiodic(a, c, T, dtype)
-    assert rel_l2(got, ref) <= TOL[dtype], name
+    assert_close(got, ref, TOL[dtype], name)

@@ -13,7 +13,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_util import TOL, rel_l2, rounded_input, to_dev
+from gpu_util import TOL, assert_close, rel_l2, rounded_input, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -69,7 +69,7 @@ def test_replays_match_direct(dims, r, T, dtype):
         assert torch.equal(g, ref), rep
         _other_work()
     want = oracle.aperiodic(rounded_input(host, dtype), c, T)
-    assert rel_l2(g.cpu().numpy().astype(np.float64), want) <= TOL[dtype]
+    assert_close(g.cpu().numpy().astype(np.float64), want, TOL[dtype])
 
 
 def test_changed_key_is_not_replayed():

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_util import TOL, rel_l2, rounded_input, to_dev
+from gpu_util import TOL, assert_close, rel_l2, rounded_input, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -53,7 +53,7 @@ def test_batch_equals_alone_and_oracle():
         assert torch.equal(g, al)
         if a.size <= 70000:
             ref = oracle.periodic(rounded_input(a, dt), c, T)
-            assert rel_l2(g.cpu().numpy().astype(np.float64), ref) <= TOL[dt]
+            assert_close(g.cpu().numpy().astype(np.float64), ref, TOL[dt])
 
 
 def test_batch_with_aperiodic_members():
@@ -65,8 +65,8 @@ def test_batch_with_aperiodic_members():
     ga, gp = to_dev(ap, "f64"), to_dev(pe, "f64")
     sfft.batch([(ga, c, 21, True), (gp, c, 33)])
     torch.cuda.synchronize()
-    assert rel_l2(ga.cpu().numpy(), oracle.aperiodic(ap, c, 21)) <= 1e-12
-    assert rel_l2(gp.cpu().numpy(), oracle.periodic(pe, c, 33)) <= 1e-12
+    assert_close(ga.cpu().numpy(), oracle.aperiodic(ap, c, 21), 1e-12)
+    assert_close(gp.cpu().numpy(), oracle.periodic(pe, c, 33), 1e-12)
 
 
 def test_batch_rejects_invalid_member_without_running():

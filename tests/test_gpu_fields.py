@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_util import TOL, rel_l2, rounded_input, to_dev
+from gpu_util import TOL, assert_close, rel_l2, rounded_input, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -57,14 +57,14 @@ def test_fields_match_oracle(dims, m, r, T, sym, dtype):
     a = wl.uniform(7 + len(dims) + m, "grid", m * int(np.prod(dims))).reshape((m,) + dims)
     got = _gpu(a, c, T, dtype)
     want = oracle.periodic_fields(rounded_input(a, dtype), c, T)
-    assert rel_l2(got, want) <= TOL[dtype]
+    assert_close(got, want, TOL[dtype])
 
 
 def test_one_field_is_the_scalar_stencil():
     c = wl.box_random_coeffs(11, 2, 1)
     a = wl.uniform(11, "grid", 72 * 60).reshape(1, 72, 60)
     got = _gpu(a, c[None, None], 250, "f64")
-    assert rel_l2(got[0], oracle.periodic(a[0], c, 250)) <= 1e-12
+    assert_close(got[0], oracle.periodic(a[0], c, 250), 1e-12)
 
 
 def test_block_diagonal_fields_are_independent():
@@ -80,7 +80,7 @@ def test_block_diagonal_fields_are_independent():
         g = to_dev(a[i], "f64")
         sfft.periodic(g, cs[i], 640)
         torch.cuda.synchronize()
-        assert rel_l2(got[i], g.cpu().numpy()) <= 1e-12
+        assert_close(got[i], g.cpu().numpy(), 1e-12)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
@@ -105,8 +105,8 @@ def test_leapfrog_wave_cosine_mode_full_size(dtype):
     # T * eps / sin(phi) * log2(T) ~ 2e-10 (the reference's own arccos near 1 adds
     # ~1e-11).  FP32 passes keep their 1e-5 budget.
     tol = 1e-5 if dtype == "f32" else 2e-9
-    assert rel_l2(got[0], np.cos(T * phi) * mode) <= tol
-    assert rel_l2(got[1], np.cos((T - 1) * phi) * mode) <= tol
+    assert_close(got[0], np.cos(T * phi) * mode, tol)
+    assert_close(got[1], np.cos((T - 1) * phi) * mode, tol)
 
 
 def test_affine_update_through_a_constant_field():
@@ -119,7 +119,7 @@ def test_affine_update_through_a_constant_field():
     a0 = wl.uniform(13, "grid", 80 * 70).reshape(80, 70)
     a = np.stack([a0, np.full_like(a0, 0.375)])
     got = _gpu(a, c, 123, "f64")
-    assert rel_l2(got, oracle.periodic_fields(a, c, 123)) <= 1e-12
+    assert_close(got, oracle.periodic_fields(a, c, 123), 1e-12)
     assert np.allclose(got[1], 0.375, rtol=0, atol=1e-13)
 
 

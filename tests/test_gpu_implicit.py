@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_util import TOL, rel_l2, rounded_input, to_dev
+from gpu_util import TOL, assert_close, rel_l2, rounded_input, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -60,7 +60,7 @@ def test_implicit_matches_oracle(name, dims, make, T, dtype):
     a = wl.uniform(30 + len(dims), "grid", int(np.prod(dims))).reshape(dims)
     got = _gpu(a, q, s, T, dtype)
     want = oracle.implicit_periodic(rounded_input(a, dtype), q, s, T)
-    assert rel_l2(got, want) <= TOL[dtype]
+    assert_close(got, want, TOL[dtype])
 
 
 @pytest.mark.parametrize("dims", [(64,), (16, 12)])
@@ -77,7 +77,7 @@ def test_singular_q_uses_the_pseudo_inverse(dims):
     # so both sides agree to about T * eps * sum|q| / lambda_min relative.
     lam_min = 4 * min(np.sin(np.pi / n) ** 2 for n in dims)
     tol = 10 * T * np.finfo(float).eps * np.abs(q).sum() / lam_min
-    assert rel_l2(got, want) <= tol
+    assert_close(got, want, tol)
     assert abs(got.mean()) <= 1e-12 * np.abs(got).max()
 
 
@@ -90,7 +90,7 @@ def test_identity_q_is_the_explicit_stencil():
     g = to_dev(a, "f64")
     sfft.periodic(g, s, 333)
     torch.cuda.synchronize()
-    assert rel_l2(got, g.cpu().numpy()) <= 1e-12
+    assert_close(got, g.cpu().numpy(), 1e-12)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])

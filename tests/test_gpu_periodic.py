@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads as wl
-from gpu_util import TOL, gpu_periodic, rel_l2, rounded_input
+from gpu_util import TOL, assert_close, gpu_periodic, rel_l2, rounded_input
 
 pytestmark = pytest.mark.gpu
 
@@ -43,7 +43,7 @@ def test_periodic_small_grids(dtype, dims, r, T, sym):
     a0 = wl.uniform(seed, "grid", int(np.prod(dims))).reshape(dims)
     ref = oracle.periodic(rounded_input(a0, dtype), c, T)
     got = gpu_periodic(a0, c, T, dtype)
-    assert rel_l2(got, ref) <= TOL[dtype], (dims, r, T, sym)
+    assert_close(got, ref, TOL[dtype], (dims, r, T, sym))
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
@@ -53,7 +53,7 @@ def test_periodic_long_T(dtype, T):
     c = _coeffs(2, 1, False, 7)
     a0 = wl.uniform(7, "grid", int(np.prod(dims))).reshape(dims)
     ref = oracle.periodic(rounded_input(a0, dtype), c, T)
-    assert rel_l2(gpu_periodic(a0, c, T, dtype), ref) <= TOL[dtype]
+    assert_close(gpu_periodic(a0, c, T, dtype), ref, TOL[dtype])
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
@@ -66,7 +66,7 @@ def test_periodic_multi_tile_and_split_axes(dtype, dims):
     a0 = wl.uniform(11, "grid", int(np.prod(dims))).reshape(dims)
     T = 37
     ref = oracle.periodic(rounded_input(a0, dtype), c, T)
-    assert rel_l2(gpu_periodic(a0, c, T, dtype), ref) <= TOL[dtype]
+    assert_close(gpu_periodic(a0, c, T, dtype), ref, TOL[dtype])
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
@@ -82,7 +82,7 @@ def test_fused_symbol_every_radius(dtype, r, sym, dims):
     a0 = wl.uniform(seed, "grid", int(np.prod(dims))).reshape(dims)
     T = 45
     ref = oracle.periodic(rounded_input(a0, dtype), c, T)
-    assert rel_l2(gpu_periodic(a0, c, T, dtype), ref) <= TOL[dtype], (dims, r, sym)
+    assert_close(gpu_periodic(a0, c, T, dtype), ref, TOL[dtype], (dims, r, sym))
 
 
 def test_T_zero_is_identity_and_r0_is_pointwise():
@@ -121,7 +121,7 @@ def test_single_mode_full_jacobi2d_8192():
     a0 = np.cos(2 * np.pi * (k0 * m0 / n0 + k1 * m1 / n1))
     lam = 0.2 * (1 + 2 * np.cos(2 * np.pi * k0 / n0) + 2 * np.cos(2 * np.pi * k1 / n1))
     got = gpu_periodic(a0, w.coeffs, w.T, "f64")
-    assert rel_l2(got, lam ** w.T * a0) <= 1e-12
+    assert_close(got, lam ** w.T * a0, 1e-12)
 
 
 def test_semigroup_and_translation():
@@ -130,9 +130,9 @@ def test_semigroup_and_translation():
     a0 = wl.uniform(8, "grid", int(np.prod(dims))).reshape(dims)
     whole = gpu_periodic(a0, c, 300, "f64")
     parts = gpu_periodic(gpu_periodic(a0, c, 123, "f64"), c, 177, "f64")
-    assert rel_l2(parts, whole) <= 1e-13
+    assert_close(parts, whole, 1e-13)
     sh = gpu_periodic(np.roll(a0, (5, -7), axis=(0, 1)), c, 300, "f64")
-    assert rel_l2(sh, np.roll(whole, (5, -7), axis=(0, 1))) <= 1e-13
+    assert_close(sh, np.roll(whole, (5, -7), axis=(0, 1)), 1e-13)
 
 
 def test_symbol_power_matches_definition():
@@ -166,14 +166,14 @@ def test_heat1d_65536_full_against_oracle_and_binomial():
     a0 = w.grid()
     got = gpu_periodic(a0, w.coeffs, w.T, "f64")
     ref = oracle.periodic(a0, w.coeffs, w.T)
-    assert rel_l2(got, ref) <= 1e-12
+    assert_close(got, ref, 1e-12)
     from fractions import Fraction
     from math import comb
     T = w.T
     expect = np.zeros_like(a0)
     for m in range(2 * T + 1):
         expect += float(Fraction(comb(2 * T, m), 4 ** T)) * np.roll(a0, -(m - T))
-    assert rel_l2(got, expect) <= 1e-12
+    assert_close(got, expect, 1e-12)
 
 
 @pytest.mark.slow
@@ -184,7 +184,7 @@ def test_jacobi2d_crop_instance(dtype):
     w = wl.config("jacobi2d_8192")
     a0 = wl.crop_grid(w, 256)
     ref = oracle.periodic(rounded_input(a0, dtype), w.coeffs, w.T)
-    assert rel_l2(gpu_periodic(a0, w.coeffs, w.T, dtype), ref) <= TOL[dtype]
+    assert_close(gpu_periodic(a0, w.coeffs, w.T, dtype), ref, TOL[dtype])
 
 
 @pytest.mark.slow
@@ -197,7 +197,7 @@ def test_jacobi2d_8192_full_invariants():
     g32 = gpu_periodic(a0, w.coeffs, w.T, "f32")
     s0 = a0.sum()
     assert abs(g64.sum() - s0) <= 1e-12 * abs(s0)
-    assert rel_l2(g32, g64) <= 1e-5
+    assert_close(g32, g64, 1e-5)
 
 
 @pytest.mark.slow
@@ -205,11 +205,11 @@ def test_star3d_instance_and_full_size():
     w = wl.config("star3d_512")
     a0 = wl.crop_grid(w, 64)
     ref = oracle.periodic(rounded_input(a0, "f32"), w.coeffs, w.T)
-    assert rel_l2(gpu_periodic(a0, w.coeffs, w.T, "f32"), ref) <= TOL["f32"]
+    assert_close(gpu_periodic(a0, w.coeffs, w.T, "f32"), ref, TOL["f32"])
     full = w.grid()
     g32 = gpu_periodic(full, w.coeffs, w.T, "f32")
     g64 = gpu_periodic(rounded_input(full, "f32"), w.coeffs, w.T, "f64")
-    assert rel_l2(g32, g64) <= TOL["f32"]
+    assert_close(g32, g64, TOL["f32"])
 
 
 @pytest.mark.slow
@@ -220,4 +220,4 @@ def test_largest_1d_extent():
     T = 3
     for dtype in ("f32", "f64"):
         ref = oracle.periodic(rounded_input(a0, dtype), c, T)
-        assert rel_l2(gpu_periodic(a0, c, T, dtype), ref) <= TOL[dtype]
+        assert_close(gpu_periodic(a0, c, T, dtype), ref, TOL[dtype])
