@@ -142,6 +142,29 @@ int stencil_fft_periodic_implicit(void* grid, sfft_dtype dtype, int ndim, const 
                                   const double* q_coeffs, const double* s_coeffs, int radius, int64_t T,
                                   void* stream);
 
+/*
+ * Periodic solve that allocates no device memory.  For callers that cannot
+ * allocate: code under graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, result and validation as stencil_fft_periodic, for
+ * 7-smooth extents only (others: SFFT_EUNSUPPORTED); the result is bit-identical
+ * to stencil_fft_periodic's on the same input.
+ * Everything the solve needs besides the caller's grid (twiddle and phase tables,
+ * the per-column symbol table, the spectrum workspace) lives in one fixed device
+ * array of STENCIL_FFT_NOALLOC_MAX_BYTES per GPU, held from the first call on that
+ * GPU until the process ends; the tables are regenerated by small kernels on
+ * `stream` at every call, and nothing in the array needs to start at zero.
+ * A shape whose tables and workspace exceed the array is rejected with
+ * SFFT_ENOMEM before anything is enqueued (for instance 2048 x 2048 fits in FP32
+ * and FP64; 4096 x 4096 FP64 does not).
+ * Every call on one GPU uses that GPU's single array: calls whose work may
+ * overlap on one GPU (different streams, or different host threads, without
+ * ordering between them) race and give wrong results.  Order them, e.g. by
+ * issuing all such calls on one stream.
+ */
+#define STENCIL_FFT_NOALLOC_MAX_BYTES (64ull << 20)
+int stencil_fft_periodic_noalloc(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims,
+                                 const double* coeffs, int radius, int64_t T, void* stream);
+
 /* Message describing the last failing call on this thread ("" if none).  The
  * pointer stays valid until the thread's next call into the library. */
 const char* stencil_fft_last_error(void);

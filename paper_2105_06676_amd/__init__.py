@@ -16,6 +16,7 @@ from ._binding import (  # noqa: F401
     library_path,
     periodic,
     periodic_fields,
+    periodic_noalloc,
     periodic_implicit,
     plan_describe,
     profile_read,

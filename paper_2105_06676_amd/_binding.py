@@ -45,6 +45,8 @@ def _sig(name, res, args):
 
 
 _periodic = _sig("stencil_fft_periodic", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
+_periodic_noalloc = _sig("stencil_fft_periodic_noalloc", ctypes.c_int,
+                         [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
 _periodic_fields = _sig("stencil_fft_periodic_fields", ctypes.c_int,
                        [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
 _periodic_implicit = _sig("stencil_fft_periodic_implicit", ctypes.c_int,
@@ -126,6 +128,19 @@ def periodic(grid, coeffs, T: int, stream=None):
     with torch.cuda.device(grid.device):
         _check(_periodic(grid.data_ptr(), _dtype_code(grid), grid.dim(), dims,
                          c.ctypes.data_as(_dp), r, int(T), _stream(grid, stream)))
+    return grid
+
+
+def periodic_noalloc(grid, coeffs, T: int, stream=None):
+    """``periodic`` through the entry point that allocates no device memory
+    (7-smooth extents; tables and workspace in the library's fixed device array)."""
+    import torch
+    _check_grid(grid)
+    c, r = _coeffs(coeffs, grid.dim())
+    dims = (ctypes.c_int64 * grid.dim())(*grid.shape)
+    with torch.cuda.device(grid.device):
+        _check(_periodic_noalloc(grid.data_ptr(), _dtype_code(grid), grid.dim(), dims,
+                                 c.ctypes.data_as(_dp), r, int(T), _stream(grid, stream)))
     return grid
 
 

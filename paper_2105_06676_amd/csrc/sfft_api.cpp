@@ -18,6 +18,8 @@ void solve_aperiodic_cached(void* grid, bool f64, int d, const int64_t* dims, co
                      hipStream_t st);
 void solve_periodic_any(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
                         hipStream_t st);
+void solve_periodic_noalloc(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
+                            int64_t T, hipStream_t st);
 }  // namespace sfft
 
 using namespace sfft;
@@ -182,6 +184,20 @@ int stencil_fft_periodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* 
             solve_periodic_dense(grid, dtype == SFFT_F64, ndim, dims, 1, coeffs, radius, T, (hipStream_t)stream);
         else
             solve_periodic_any(grid, dtype == SFFT_F64, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
+    });
+}
+
+int stencil_fft_periodic_noalloc(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims, const double* coeffs,
+                                 int radius, int64_t T, void* stream) {
+    return guarded([&] {
+        validate(grid, dtype, ndim, dims, coeffs, radius, T);
+        for (int a = 0; a < ndim; ++a)
+            if (!is_7smooth(dims[a]))
+                throw Error(SFFT_EUNSUPPORTED, "extent " + std::to_string(dims[a]) +
+                                                   " has a prime factor above 7 (the no-allocation entry point "
+                                                   "takes 7-smooth extents only)");
+        if (T == 0) return;
+        solve_periodic_noalloc(grid, dtype == SFFT_F64, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
     });
 }
 
