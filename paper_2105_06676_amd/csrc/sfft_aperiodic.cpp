@@ -65,8 +65,17 @@ struct Ap {
     void* grid;
     int64_t total;       // stored elements
     std::vector<void*> level;
-    // per-column symbol parts for this solve, per plan and stream
-    std::map<std::pair<const Plan*, hipStream_t>, void*> coltab;
+    // per-column symbol parts for this solve, per transform shape and stream
+    std::map<std::tuple<int64_t, int64_t, int64_t, int64_t, hipStream_t>, void*> coltab;
+    // Where the solve's device buffers come from: the device context's
+    // per-stream buffers (pool == nullptr and !dry), or a region of pool_cap
+    // bytes at `pool` handed out in order (a server request's own block of its
+    // HBM budget).  With `dry` set nothing is allocated or enqueued: the solve
+    // only adds up, on the host, the bytes its buffers would take (pool_used).
+    char* pool = nullptr;
+    size_t pool_cap = 0, pool_used = 0;
+    bool dry = false;
+    std::map<std::pair<hipStream_t, int>, std::pair<void*, size_t>> bufs;
     int64_t cutoff;
     // Entry-time bookkeeping (appendix on l-shells): sig[a] = the stencil's largest
     // reach along axis a; face (a, side) is active when the stencil reads toward it
@@ -79,6 +88,36 @@ struct Ap {
     int64_t maxell;      // largest entry time of any interior cell (LLONG_MAX: none)
     bool inert;          // no active face: the frame never influences the interior
 };
+
+constexpr int kWsSlot = -1;  // the spectrum workspace of a stream
+
+// The device buffer of (stream, slot) with at least `bytes` bytes; one buffer per
+// key, as the context's per-stream buffers (work on one stream is ordered, so a
+// stream's buffer is free again once its earlier user's work is enqueued).
+void* ap_buf(Ap& a, hipStream_t st, int slot, size_t bytes) {
+    if (!a.pool && !a.dry)
+        return slot == kWsSlot ? device_ctx().workspace(st, bytes) : device_ctx().scratch(st, slot, bytes);
+    auto& b = a.bufs[{st, slot}];
+    if (b.first && b.second >= bytes) return b.first;
+    const size_t at = (a.pool_used + 255) & ~size_t(255);
+    if (!a.dry && at + bytes > a.pool_cap)
+        throw Error(-3, "aperiodic solve needs more than its " + std::to_string(a.pool_cap) + " reserved bytes");
+    a.pool_used = at + bytes;
+    b = {a.dry ? (void*)(uintptr_t)(at + 256) : (void*)(a.pool + at), bytes};
+    return b.first;
+}
+
+// Helper stream / event i of the solve (stand-in handles when dry).
+hipStream_t ap_side(Ap& a, int i) {
+    return a.dry ? (hipStream_t)(uintptr_t)(0x100000 + i) : device_ctx().side_stream(a.st, i);
+}
+hipEvent_t ap_event(Ap& a, int i) { return a.dry ? nullptr : device_ctx().side_event(a.st, i); }
+void ap_record(const Ap& a, hipEvent_t e, hipStream_t st) {
+    if (!a.dry) check_hip(hipEventRecord(e, st), "hipEventRecord");
+}
+void ap_wait(const Ap& a, hipStream_t st, hipEvent_t e) {
+    if (!a.dry) check_hip(hipStreamWaitEvent(st, e, 0), "hipStreamWaitEvent");
+}
 
 void* interior_origin(const Ap& a, const void* base) {
     int64_t off = 0;
@@ -104,12 +143,27 @@ struct Boxed {
 Boxed boxed_prepare(Ap& a, const void* src, void* dst, const int64_t* ext, int64_t B, int64_t boff,
                     const KeepRule& keep, int64_t steps, hipStream_t st) {
     Boxed b;
-    int64_t pd[3];
+    int64_t pd[3] = {1, 1, 1};
     for (int k = 0; k < a.d; ++k) pd[k] = pad_fft(ext[k]);
+    const auto ckey = std::make_tuple(pd[0], pd[1], pd[2], B, st);
+    if (a.dry) {
+        // sizes only: the host-side schedule of the same shape
+        Schedule s;
+        std::string why;
+        const int rc = build_schedule(a.d, pd, B, a.f64, &s, &why);
+        if (rc) throw Error(rc == -1 ? -1 : -2, why);
+        ap_buf(a, st, kWsSlot, (size_t)s.spec_elems * (a.f64 ? 16 : 8));
+        if (a.d >= 2 && !a.coltab.count(ckey)) {
+            int64_t ncol = 1;
+            for (int k = 1; k < a.d; ++k) ncol *= s.sym.sdim[k];
+            a.coltab[ckey] = ap_buf(a, st, 300 + (int)a.coltab.size(), (size_t)ncol * symbol_column_bytes());
+        }
+        return b;
+    }
     DevCtx& ctx = device_ctx();
     b.plan = ctx.plan(a.d, pd, B, a.f64);
     b.npass = b.plan->pd.size();
-    b.ws = ctx.workspace(st, (size_t)b.plan->s.spec_elems * (a.f64 ? 16 : 8));
+    b.ws = ap_buf(a, st, kWsSlot, (size_t)b.plan->s.spec_elems * (a.f64 ? 16 : 8));
     b.sp = b.plan->s.sym;
     double N = 1.0;
     for (int k = 0; k < a.d; ++k) N *= (double)pd[k];
@@ -117,13 +171,13 @@ Boxed boxed_prepare(Ap& a, const void* src, void* dst, const int64_t* ext, int64
     if (a.d >= 2) {
         // the column part of the symbol depends on the plan and the coefficients
         // only (not on the step count): build it once per plan within this solve
-        auto it = a.coltab.find({b.plan.get(), st});
+        auto it = a.coltab.find(ckey);
         if (it == a.coltab.end()) {
             int64_t ncol = 1;
             for (int k = 1; k < a.d; ++k) ncol *= b.sp.sdim[k];
-            void* tab = ctx.scratch(st, 300 + (int)a.coltab.size(), (size_t)ncol * symbol_column_bytes());
+            void* tab = ap_buf(a, st, 300 + (int)a.coltab.size(), (size_t)ncol * symbol_column_bytes());
             build_symbol_columns(b.sp, tab, a.f64, st);
-            it = a.coltab.emplace(std::make_pair(b.plan.get(), st), tab).first;
+            it = a.coltab.emplace(ckey, tab).first;
         }
         b.sp.coltab = it->second;
         b.sp.ncol = 1;
@@ -142,9 +196,9 @@ Boxed boxed_prepare(Ap& a, const void* src, void* dst, const int64_t* ext, int64
     return b;
 }
 
-// Passes [p0, p1) of a prepared solve.
+// Passes [p0, p1) of a prepared solve (none when the solve is only sized).
 void boxed_run(const Boxed& b, hipStream_t st, size_t p0, size_t p1) {
-    if (p0 < p1) run_plan(*b.plan, b.ws, b.in, b.out, b.keep, b.sp, st, p0, p1);
+    if (b.plan && p0 < p1) run_plan(*b.plan, b.ws, b.in, b.out, b.keep, b.sp, st, p0, p1);
 }
 
 void boxed_periodic(Ap& a, const void* src, void* dst, const int64_t* ext, int64_t B, int64_t boff,
@@ -183,6 +237,7 @@ struct Forked {
 
 // Make `to` wait for all work enqueued so far on `from`.
 void depend(Ap& a, hipStream_t from, hipStream_t to, int ev) {
+    if (a.dry) return;
     hipEvent_t e = device_ctx().side_event(a.st, ev);
     check_hip(hipEventRecord(e, from), "hipEventRecord");
     check_hip(hipStreamWaitEvent(to, e, 0), "hipStreamWaitEvent");
@@ -203,7 +258,6 @@ Forked slab_solve(Ap& a, const void* src, void* dst, int64_t w, int64_t steps, i
                   hipEvent_t fork) {
     Forked f;
     if (lo >= a.maxell || hi <= lo) return f;
-    DevCtx& ctx = device_ctx();
     for (int ax = 0; ax < a.d; ++ax) {
         const bool lo_f = a.act[ax][0], hi_f = a.act[ax][1];
         if (!lo_f && !hi_f) continue;
@@ -235,8 +289,8 @@ Forked slab_solve(Ap& a, const void* src, void* dst, int64_t w, int64_t steps, i
         keep.gorg[ax] += shift;
         const void* s0 = (const char*)interior_origin(a, src) + shift * a.sstride[ax] * (int64_t)a.esz;
         void* d0 = (char*)interior_origin(a, dst) + shift * a.sstride[ax] * (int64_t)a.esz;
-        hipStream_t sa = ctx.side_stream(a.st, 4 * lev + ax);
-        check_hip(hipStreamWaitEvent(sa, fork, 0), "hipStreamWaitEvent");
+        hipStream_t sa = ap_side(a, 4 * lev + ax);
+        ap_wait(a, sa, fork);
         boxed_periodic(a, s0, d0, ext, B, boff, keep, steps, sa);
         f.s[f.n] = sa;
         f.ev[f.n] = 4 * lev + ax;
@@ -384,6 +438,7 @@ void base_case(Ap& a, const void* src, void* dst, int64_t tau, hipStream_t st) {
         first += cnt;
         lds = std::max(lds, (size_t)f * a.esz);
     }
+    if (a.dry) return;
     hipEvent_t ev = nullptr;
     const bool prof = profiling();
     if (prof) profile_launch_begin(st, &ev);
@@ -402,7 +457,7 @@ void recursive_boundary(Ap& a, const void* src, void* dst, int64_t T, int lev, h
     }
     const int64_t T1 = T / 2, T2 = T - T1;
     if ((int)a.level.size() <= lev) {
-        void* p = device_ctx().scratch(a.st, 100 + lev, (size_t)a.total * a.esz);
+        void* p = ap_buf(a, a.st, 100 + lev, (size_t)a.total * a.esz);
         a.level.push_back(p);
     }
     void* mid = a.level[lev];
@@ -410,15 +465,15 @@ void recursive_boundary(Ap& a, const void* src, void* dst, int64_t T, int lev, h
     // is enqueued before the slabs that run beside it: a replayed graph then
     // dispatches the chain of leaves first and fills the device with slab work
     // around it.
-    hipEvent_t fork = device_ctx().side_event(a.st, 4 * lev + 3);
+    hipEvent_t fork = ap_event(a, 4 * lev + 3);
     // (bands in entry-time units, i.e. the distance form with sigma = 1)
     // step 1: band (0, 2T] at t0 -> (0, T + T2] at t0 + T1
-    check_hip(hipEventRecord(fork, st), "hipEventRecord");
+    ap_record(a, fork, st);
     recursive_boundary(a, src, mid, T1, lev + 1, st);
     Forked f = slab_solve(a, src, mid, 2 * T, T1, T1, T + T2, lev, fork);
     join(a, f, st);
     // step 2: band (0, T + T2] at t0 + T1 -> (0, T] at t0 + T
-    check_hip(hipEventRecord(fork, st), "hipEventRecord");
+    ap_record(a, fork, st);
     recursive_boundary(a, mid, dst, T2, lev + 1, st);
     f = slab_solve(a, mid, dst, T + T2, T2, T2, T, lev, fork);
     join(a, f, st);
@@ -492,18 +547,17 @@ Ap make_ap(void* grid, bool f64, int d, const int64_t* dims, const double* coeff
 // T > cutoff and r > 0: StencilFFT-A with RecursiveBoundary, main-line work
 // enqueued on `ls` (the caller's stream, or a capturing stream).
 void recursive_path(Ap& a, int64_t T, hipStream_t ls) {
-    DevCtx& ctx = device_ctx();
-    hipStream_t si = ctx.side_stream(a.st, -1);  // the interior solve's helper stream
+    hipStream_t si = ap_side(a, -1);  // the interior solve's helper stream
     // The interior solve reads the initial interior and stores entry times > T in
     // place.  All but its last pass work in its own workspace and start at once;
     // the last pass stores only after RecursiveBoundary step 1 has read the
     // initial band, and step 2 stores entry times <= T only after the interior's
     // first pass has read the whole initial interior.
     const int64_t T1 = T / 2, T2 = T - T1;
-    void* mid = ctx.scratch(a.st, 100, (size_t)a.total * a.esz);
+    void* mid = ap_buf(a, a.st, 100, (size_t)a.total * a.esz);
     a.level.push_back(mid);
     const bool interior = T < a.maxell;
-    hipEvent_t read_done = ctx.side_event(a.st, -3);
+    hipEvent_t read_done = ap_event(a, -3);
     Boxed in;
     if (interior) {
         depend(a, ls, si, -1);
@@ -511,22 +565,22 @@ void recursive_path(Ap& a, int64_t T, hipStream_t ls) {
                            make_keep(a, T, LLONG_MAX), T, si);
         if (in.npass > 1) {
             boxed_run(in, si, 0, 1);
-            check_hip(hipEventRecord(read_done, si), "hipEventRecord");
+            ap_record(a, read_done, si);
             boxed_run(in, si, 1, in.npass - 1);
         }
     }
-    hipEvent_t fork = ctx.side_event(a.st, 3);
-    check_hip(hipEventRecord(fork, ls), "hipEventRecord");
+    hipEvent_t fork = ap_event(a, 3);
+    ap_record(a, fork, ls);
     recursive_boundary(a, a.grid, mid, T1, 1, ls);
     Forked f = slab_solve(a, a.grid, mid, 2 * T, T1, T1, T + T2, 0, fork);
     join(a, f, ls);
     if (interior) {
         depend(a, ls, si, -4);
-        boxed_run(in, si, in.npass - 1, in.npass);
-        if (in.npass == 1) check_hip(hipEventRecord(read_done, si), "hipEventRecord");
-        check_hip(hipStreamWaitEvent(ls, read_done, 0), "hipStreamWaitEvent");
+        if (in.npass > 0) boxed_run(in, si, in.npass - 1, in.npass);
+        if (in.npass == 1) ap_record(a, read_done, si);
+        ap_wait(a, ls, read_done);
     }
-    check_hip(hipEventRecord(fork, ls), "hipEventRecord");
+    ap_record(a, fork, ls);
     recursive_boundary(a, mid, a.grid, T2, 1, ls);
     f = slab_solve(a, mid, a.grid, T + T2, T2, T2, T, 0, fork);
     join(a, f, ls);
@@ -536,7 +590,6 @@ void recursive_path(Ap& a, int64_t T, hipStream_t ls) {
 // Solves of T <= cutoff or with an inert frame (few launches; always enqueued
 // directly).
 void short_path(Ap& a, int64_t T) {
-    DevCtx& ctx = device_ctx();
     hipStream_t st = a.st;
     void* grid = a.grid;
     if (a.inert) {
@@ -546,11 +599,12 @@ void short_path(Ap& a, int64_t T) {
         boxed_periodic(a, interior_origin(a, grid), interior_origin(a, grid), a.n, 1, 0, keep, T, st);
         return;
     }
-    hipStream_t si = ctx.side_stream(st, -1);
+    hipStream_t si = ap_side(a, -1);
     // The base case reads entry times <= 2T of the initial array while the result
     // is stored in place, so both parts read from a copy and run side by side.
-    void* tmp = ctx.scratch(st, 99, (size_t)a.total * a.esz);
-    check_hip(hipMemcpyAsync(tmp, grid, (size_t)a.total * a.esz, hipMemcpyDeviceToDevice, st), "copy");
+    void* tmp = ap_buf(a, st, 99, (size_t)a.total * a.esz);
+    if (!a.dry)
+        check_hip(hipMemcpyAsync(tmp, grid, (size_t)a.total * a.esz, hipMemcpyDeviceToDevice, st), "copy");
     if (T < a.maxell) {
         depend(a, st, si, -1);
         KeepRule keep = make_keep(a, T, LLONG_MAX);
@@ -601,6 +655,34 @@ void drop_graph(GraphEntry& e) {
 void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
                      hipStream_t st) {
     Ap a = make_ap(grid, f64, d, dims, coeffs, r, st);
+    if (a.inert || T <= a.cutoff)
+        short_path(a, T);
+    else
+        recursive_path(a, T, st);
+}
+
+// Device bytes the solve's buffers take when it runs in a region of its own
+// (solve_aperiodic_pooled), found on the host by the same bookkeeping with
+// nothing enqueued.
+size_t aperiodic_footprint(bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T) {
+    Ap a = make_ap((void*)(uintptr_t)4096, f64, d, dims, coeffs, r, (hipStream_t)(uintptr_t)0x10);
+    a.dry = true;
+    if (T > 0) {
+        if (a.inert || T <= a.cutoff)
+            short_path(a, T);
+        else
+            recursive_path(a, T, a.st);
+    }
+    return (a.pool_used + 255) & ~size_t(255);
+}
+
+// solve_aperiodic with every device buffer taken from [pool, pool + cap)
+// (at least aperiodic_footprint bytes).
+void solve_aperiodic_pooled(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
+                            int64_t T, hipStream_t st, void* pool, size_t cap) {
+    Ap a = make_ap(grid, f64, d, dims, coeffs, r, st);
+    a.pool = (char*)pool;
+    a.pool_cap = cap;
     if (a.inert || T <= a.cutoff)
         short_path(a, T);
     else

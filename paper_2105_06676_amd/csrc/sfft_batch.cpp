@@ -50,13 +50,19 @@ static size_t col_table_bytes(const SymParams& sym) {
     return (size_t)ncol * symbol_column_bytes();
 }
 
-size_t problem_workspace_bytes(const sfft_problem& p) {
+ProblemSize problem_size(const sfft_problem& p) {
     Schedule s;
     std::string why;
     const int rc = build_schedule(p.ndim, p.dims, 1, p.dtype == SFFT_F64, &s, &why);
     if (rc) throw Error(rc == -1 ? SFFT_EINVAL : SFFT_EUNSUPPORTED, why);
-    return align256((size_t)s.spec_elems * (p.dtype == SFFT_F64 ? 16 : 8)) + align256(col_table_bytes(s.sym));
+    ProblemSize ps;
+    ps.ws_bytes = align256((size_t)s.spec_elems * (p.dtype == SFFT_F64 ? 16 : 8)) + align256(col_table_bytes(s.sym));
+    ps.passes = s.passes.size();
+    ps.model_bytes = s.model_bytes;
+    return ps;
 }
+
+size_t problem_workspace_bytes(const sfft_problem& p) { return problem_size(p).ws_bytes; }
 
 ProblemRun prepare_periodic(const sfft_problem& p) {
     ProblemRun r;

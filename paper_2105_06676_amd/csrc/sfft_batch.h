@@ -25,6 +25,14 @@ void validate_problem(const sfft_problem& p);
 ProblemRun prepare_periodic(const sfft_problem& p);
 // Host-only estimate of a problem's device workspace (no GPU needed).
 size_t problem_workspace_bytes(const sfft_problem& p);
+// Host-only sizes of a periodic problem: workspace + column table bytes, number
+// of passes, algorithmic HBM bytes of all passes.
+struct ProblemSize {
+    size_t ws_bytes = 0;
+    size_t passes = 0;
+    int64_t model_bytes = 0;
+};
+ProblemSize problem_size(const sfft_problem& p);
 
 // Device buffers a batch runs in: workspaces and column tables sub-allocated from
 // `ws`, descriptors in `desc`.

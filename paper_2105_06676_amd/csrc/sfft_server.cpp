@@ -8,6 +8,14 @@
 // fired: tickets become done, slots and arena space return.  Requests that
 // arrive while batches run therefore join the next batch, and batches on
 // different streams overlap on the device.
+//
+// Device memory: the whole budget is one arena allocated at creation.  It holds
+// each stream's descriptor buffer (reserved at creation) and, per admitted
+// request, one block with everything the request's solve needs: the spectrum
+// workspace and column table of a periodic request, every buffer of an
+// aperiodic one (its size found on the host at submit by the solver's own
+// bookkeeping with nothing enqueued).  Serving therefore allocates nothing and
+// never synchronises the device after creation.
 #include <algorithm>
 #include <functional>
 #include <chrono>
@@ -22,8 +30,9 @@
 #include "sfft_batch.h"
 
 namespace sfft {
-void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
-                     hipStream_t st);
+size_t aperiodic_footprint(bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T);
+void solve_aperiodic_pooled(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
+                            int64_t T, hipStream_t st, void* pool, size_t cap);
 int guarded_call(const std::function<void()>& f);
 }  // namespace sfft
 
@@ -33,11 +42,17 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 
+// passes per request the descriptor reserve is sized for (the deepest
+// schedules have 9); a request with more is rejected at submit
+constexpr size_t kDescPasses = 12;
+
 struct Req {
     uint64_t ticket;
     sfft_problem p;
     std::vector<double> coeffs;
-    size_t bytes;
+    size_t bytes;          // arena block: the request's device buffers
+    size_t desc_bytes;     // its share of a batch's descriptor buffer
+    int64_t model_bytes;   // algorithmic HBM bytes of its passes (periodic)
 };
 
 // first-fit allocator over [0, cap)
@@ -83,9 +98,18 @@ struct Arena {
 
 struct Flight {
     int stream;
-    hipEvent_t done;
+    hipEvent_t start = nullptr, done = nullptr;  // timing events around the batch's work
     std::vector<uint64_t> tickets;
     std::vector<std::pair<size_t, size_t>> allocs;
+    int64_t model_bytes = 0;
+    bool all_periodic = true;
+};
+
+// Device-time span of one retired batch (ms since the server's base event).
+struct Span {
+    double t0, t1;
+    int64_t bytes;
+    bool periodic;
 };
 
 struct TicketInfo {
@@ -105,8 +129,10 @@ struct sfft_server {
     std::map<uint64_t, TicketInfo> tickets;
     uint64_t next_ticket = 1;
     std::vector<hipStream_t> streams;
-    std::vector<char*> desc;
-    std::vector<size_t> desc_cap;
+    std::vector<char*> desc;   // per stream, inside the arena
+    size_t desc_cap = 0;
+    hipEvent_t base_ev = nullptr;
+    std::vector<Span> spans;
     std::vector<int> stream_busy;
     std::vector<Flight> flights;
     char* arena_base = nullptr;
@@ -119,6 +145,7 @@ struct sfft_server {
     Clock::time_point t0 = Clock::now();
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+    size_t reserved() const { return streams.size() * ((desc_cap + 255) / 256 * 256); }
     void run();
     void launch(int si, std::vector<Req>& reqs, std::vector<size_t>& offs);
 };
@@ -134,29 +161,29 @@ void sfft_server::launch(int si, std::vector<Req>& reqs, std::vector<size_t>& of
         }
     if (!runs.empty()) {
         // every admitted request owns an arena block holding its workspace and
-        // column table
-        const size_t need = batch_desc_bytes(runs);
-        if (desc_cap[si] < need) {
-            if (desc[si]) {
-                check_hip(hipStreamSynchronize(st), "hipStreamSynchronize");
-                check_hip(hipFree(desc[si]), "hipFree");
-            }
-            desc[si] = nullptr;
-            check_hip(hipMalloc(&desc[si], need), "hipMalloc(descriptors)");
-            desc_cap[si] = need;
-        }
+        // column table; admission kept the batch's descriptors within the
+        // stream's reserved buffer
         BatchMem mem;
         mem.desc = desc[si];
-        mem.desc_cap = desc_cap[si];
+        mem.desc_cap = desc_cap;
         std::vector<char*> bases;
         for (int k : which) bases.push_back(arena_base + offs[k]);
         BatchProgram prog = build_batch(runs, mem, &bases);
         enqueue_batch(prog, runs, mem, st, true);
     }
-    for (auto& r : reqs)
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        const Req& r = reqs[i];
         if (r.p.aperiodic && r.p.T > 0)
-            solve_aperiodic(r.p.grid, r.p.dtype == SFFT_F64, r.p.ndim, r.p.dims, r.coeffs.data(), r.p.radius, r.p.T,
-                            st);
+            solve_aperiodic_pooled(r.p.grid, r.p.dtype == SFFT_F64, r.p.ndim, r.p.dims, r.coeffs.data(), r.p.radius,
+                                   r.p.T, st, arena_base + offs[i], r.bytes);
+    }
+}
+
+// Bytes of the descriptor buffer a batch of requests with these shares needs
+// (the layout of batch_desc_bytes: symbol parameters, then the work lists).
+static size_t desc_need(size_t nreq, size_t items) {
+    return (sizeof(SymParams) * std::max<size_t>(1, nreq) + 255) / 256 * 256 +
+           sizeof(BatchItem) * std::max<size_t>(1, items) + 256;
 }
 
 void sfft_server::run() {
@@ -173,6 +200,14 @@ void sfft_server::run() {
             }
             const int status = q == hipSuccess ? 0 : SFFT_EHIP;
             const double t = now();
+            if (status == 0) {
+                float a = 0.f, b = 0.f;
+                if (hipEventElapsedTime(&a, base_ev, f.start) == hipSuccess &&
+                    hipEventElapsedTime(&b, base_ev, f.done) == hipSuccess)
+                    spans.push_back({a, b, f.model_bytes, f.all_periodic});
+                else
+                    (void)hipGetLastError();
+            }
             for (uint64_t tk : f.tickets) {
                 auto& ti = tickets[tk];
                 ti.status = status;
@@ -185,6 +220,7 @@ void sfft_server::run() {
             inflight_reqs -= (int)f.tickets.size();
             n_completed += f.tickets.size();
             stream_busy[f.stream] = 0;
+            (void)hipEventDestroy(f.start);
             (void)hipEventDestroy(f.done);
             flights.erase(flights.begin() + i);
             cv_done.notify_all();
@@ -197,10 +233,17 @@ void sfft_server::run() {
             std::vector<Req> adm;
             std::vector<size_t> offs;
             std::vector<std::pair<size_t, size_t>> allocs;
+            size_t nper = 0, items = 0;
             while (!queue.empty() && inflight_reqs + (int)adm.size() < max_slots) {
                 Req& r = queue.front();
+                const size_t add_items = r.p.aperiodic ? 0 : r.desc_bytes / sizeof(BatchItem);
+                if (!r.p.aperiodic && desc_need(nper + 1, items + add_items) > desc_cap) break;
                 size_t off = 0;
                 if (!arena.alloc(std::max<size_t>(r.bytes, 256), &off)) break;
+                if (!r.p.aperiodic) {
+                    nper += 1;
+                    items += add_items;
+                }
                 in_use += (std::max<size_t>(r.bytes, 256) + 255) / 256 * 256;
                 peak_use = std::max(peak_use, in_use);
                 allocs.push_back({off, std::max<size_t>(r.bytes, 256)});
@@ -216,6 +259,8 @@ void sfft_server::run() {
                     f.tickets.push_back(r.ticket);
                     // requests point at their own coefficient copies
                     r.p.coeffs = r.coeffs.data();
+                    f.model_bytes += r.model_bytes;
+                    f.all_periodic = f.all_periodic && !r.p.aperiodic;
                 }
                 stream_busy[si] = 1;
                 inflight_reqs += (int)adm.size();
@@ -224,6 +269,9 @@ void sfft_server::run() {
                 max_batch = std::max<uint64_t>(max_batch, adm.size());
                 lk.unlock();
                 int status = 0;
+                hipEvent_t ev0 = nullptr;
+                (void)hipEventCreate(&ev0);
+                (void)hipEventRecord(ev0, streams[si]);
                 try {
                     launch(si, adm, offs);
                 } catch (const Error& e) {
@@ -232,9 +280,10 @@ void sfft_server::run() {
                     status = SFFT_EHIP;
                 }
                 hipEvent_t ev;
-                (void)hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                (void)hipEventCreate(&ev);
                 (void)hipEventRecord(ev, streams[si]);
                 lk.lock();
+                f.start = ev0;
                 f.done = ev;
                 if (status) {
                     // failed to enqueue: finish these tickets with the error at once
@@ -249,6 +298,7 @@ void sfft_server::run() {
                     }
                     inflight_reqs -= (int)f.tickets.size();
                     stream_busy[si] = 0;
+                    (void)hipEventDestroy(ev0);
                     (void)hipEventDestroy(ev);
                     cv_done.notify_all();
                 } else {
@@ -261,6 +311,51 @@ void sfft_server::run() {
         cv_work.wait_for(lk, std::chrono::microseconds(flights.empty() ? 2000 : 50));
     }
 }
+
+namespace {
+
+// Device-time statistics of the retired batches: the union of their spans (GPU
+// busy time), their sum (> union when batches on different streams overlapped),
+// the most batches in flight at once on the device, and each periodic batch's
+// algorithmic HBM bytes over its own span against 8 TB/s.
+std::string span_stats(const std::vector<Span>& sp) {
+    std::vector<std::pair<double, int>> ev;
+    double sum = 0.0;
+    int64_t bytes = 0;
+    std::vector<double> frac;
+    for (auto& x : sp) {
+        ev.push_back({x.t0, 1});
+        ev.push_back({x.t1, -1});
+        sum += x.t1 - x.t0;
+        if (x.periodic && x.t1 > x.t0) {
+            frac.push_back((double)x.bytes / ((x.t1 - x.t0) * 1e-3) / 8e12);
+            bytes += x.bytes;
+        }
+    }
+    std::sort(ev.begin(), ev.end(), [](const std::pair<double, int>& a, const std::pair<double, int>& b) {
+        return a.first != b.first ? a.first < b.first : a.second < b.second;
+    });
+    int cur = 0, mx = 0;
+    double uni = 0.0, last = 0.0;
+    for (auto& e : ev) {
+        if (cur > 0) uni += e.first - last;
+        cur += e.second;
+        mx = std::max(mx, cur);
+        last = e.first;
+    }
+    std::sort(frac.begin(), frac.end());
+    auto pct = [&](double q) { return frac.empty() ? 0.0 : frac[(size_t)std::min<double>(frac.size() - 1, q * frac.size())]; };
+    std::ostringstream o;
+    o.precision(6);
+    o << "\"device\": {\"batches_timed\": " << sp.size() << ", \"busy_ms\": " << uni << ", \"sum_batch_ms\": " << sum
+      << ", \"max_concurrent_batches\": " << mx << ", \"periodic_model_bytes\": " << bytes
+      << ", \"hbm_frac_of_busy\": " << (uni > 0 ? (double)bytes / (uni * 1e-3) / 8e12 : 0.0)
+      << ", \"batch_hbm_frac_p10\": " << pct(0.1) << ", \"batch_hbm_frac_p50\": " << pct(0.5)
+      << ", \"batch_hbm_frac_p90\": " << pct(0.9) << "}";
+    return o.str();
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -286,14 +381,29 @@ int sfft_server_create(sfft_server** out, int device, uint64_t hbm_budget_bytes,
         }
         s->arena.init(s->budget);
         const int nst = 4;
+        // descriptor buffers, reserved from the budget: room for a full batch of
+        // requests of up to kDescPasses passes each (admission keeps every batch
+        // within it)
+        s->desc_cap = desc_need((size_t)s->max_slots, (size_t)s->max_slots * kDescPasses);
         for (int i = 0; i < nst; ++i) {
             hipStream_t st;
             check_hip(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
             s->streams.push_back(st);
-            s->desc.push_back(nullptr);
-            s->desc_cap.push_back(0);
+            size_t off = 0;
+            if (!s->arena.alloc(s->desc_cap, &off)) {
+                (void)hipSetDevice(prev);
+                throw Error(SFFT_ENOMEM, "HBM budget of " + std::to_string(s->budget) +
+                                             " bytes is smaller than the descriptor reserve of " +
+                                             std::to_string(nst * s->desc_cap) + " bytes");
+            }
+            s->in_use += (s->desc_cap + 255) / 256 * 256;
+            s->desc.push_back(s->arena_base + off);
             s->stream_busy.push_back(0);
         }
+        s->peak_use = s->in_use;
+        check_hip(hipEventCreate(&s->base_ev), "hipEventCreate");
+        check_hip(hipEventRecord(s->base_ev, s->streams[0]), "hipEventRecord");
+        check_hip(hipEventSynchronize(s->base_ev), "hipEventSynchronize");
         (void)hipSetDevice(prev);
         sfft_server* raw = s.get();
         s->worker = std::thread([raw] { raw->run(); });
@@ -311,15 +421,21 @@ int sfft_server_submit(sfft_server* s, const sfft_problem* p, uint64_t* ticket) 
         for (int a = 0; a < p->ndim; ++a) nc *= 2 * p->radius + 1;
         r.coeffs.assign(p->coeffs, p->coeffs + nc);
         r.p.coeffs = r.coeffs.data();
+        r.model_bytes = 0;
+        r.desc_bytes = 0;
         if (p->aperiodic) {
-            int64_t cells = 1;
-            for (int a = 0; a < p->ndim; ++a) cells *= p->dims[a] + 2 * p->radius;
-            r.bytes = 256;  // the aperiodic path uses per-stream scratch outside the arena
-            (void)cells;
+            // every buffer of the solve, sized by its own bookkeeping on the host
+            r.bytes = aperiodic_footprint(p->dtype == SFFT_F64, p->ndim, p->dims, r.coeffs.data(), p->radius, p->T);
         } else {
-            r.bytes = problem_workspace_bytes(*p);
+            const ProblemSize ps = problem_size(*p);
+            r.bytes = ps.ws_bytes;
+            r.model_bytes = ps.model_bytes;
+            r.desc_bytes = ps.passes * sizeof(BatchItem);
+            if (desc_need(1, ps.passes) > s->desc_cap)
+                throw Error(SFFT_EUNSUPPORTED, "request has more passes than a server batch holds");
         }
-        if (r.bytes > s->budget) throw Error(SFFT_ENOMEM, "request workspace exceeds the server's HBM budget");
+        if (r.bytes > s->budget - s->reserved())
+            throw Error(SFFT_ENOMEM, "request workspace exceeds the server's HBM budget");
         std::lock_guard<std::mutex> g(s->mu);
         r.ticket = s->next_ticket++;
         TicketInfo ti;
@@ -368,8 +484,9 @@ int sfft_server_stats(sfft_server* s, char* buf, int64_t cap) {
         o << "{\"admitted\": " << s->n_admitted << ", \"completed\": " << s->n_completed << ", \"batches\": "
           << s->n_batches << ", \"max_batch\": " << s->max_batch << ", \"queued\": " << s->queue.size()
           << ", \"in_flight\": " << s->inflight_reqs << ", \"budget_bytes\": " << s->budget
+          << ", \"reserved_bytes\": " << s->reserved()
           << ", \"peak_bytes\": " << s->peak_use << ", \"streams\": " << s->streams.size()
-          << ", \"max_slots\": " << s->max_slots << "}";
+          << ", \"max_slots\": " << s->max_slots << ", " << span_stats(s->spans) << "}";
     }
     const std::string str = o.str();
     if ((int64_t)str.size() >= cap) return SFFT_EINVAL;
@@ -392,8 +509,7 @@ void sfft_server_destroy(sfft_server* s) {
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);
     }
-    for (auto d : s->desc)
-        if (d) (void)hipFree(d);
+    if (s->base_ev) (void)hipEventDestroy(s->base_ev);
     if (s->arena_base) (void)hipFree(s->arena_base);
     (void)hipSetDevice(prev);
     delete s;
