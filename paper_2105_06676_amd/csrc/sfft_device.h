@@ -148,6 +148,27 @@ __device__ __forceinline__ void dft(cx<R>* v) {
 }
 
 // ---------------------------------------------------------------------------
+// Division by a divisor n >= 1 that is the same for the whole workgroup, for
+// dividends e < 2^22, through a float reciprocal: (e + 1/2) / n lies at least
+// 1/(2n) away from the nearest integer, while the two float roundings of
+// (e + 1/2) * fl(1/n) move it by at most (e + 1/2) / n * 2^-23 < 1/(2n), so
+// truncation gives floor(e / n).  About 4 instructions instead of the ~20 of an
+// integer division expansion.
+struct UDiv {
+    uint32_t n;
+    float inv;
+};
+__device__ __forceinline__ UDiv udiv(uint32_t n) { return UDiv{n, 1.0f / (float)n}; }
+__device__ __forceinline__ uint32_t udiv_q(uint32_t e, UDiv d) {
+    return (uint32_t)(((float)e + 0.5f) * d.inv);
+}
+// q = e / n, returns e - q n
+__device__ __forceinline__ uint32_t udiv_qr(uint32_t e, UDiv d, uint32_t* q) {
+    *q = udiv_q(e, d);
+    return e - *q * d.n;
+}
+
+// ---------------------------------------------------------------------------
 // One Stockham radix-RAD stage over every transform of an LDS tile.
 // Transform `tr` element `e` lives at lds[tr * ts + e * es].  With Ns the product
 // of the radices already applied, butterfly j reads elements j + t * L/RAD,
@@ -164,17 +185,20 @@ __device__ __forceinline__ void stage(cx<R>* lds, int L, int ntrans, int ts, int
     constexpr int MAXIT = (kTileElems + RAD * gen_threads<R>() - 1) / (RAD * gen_threads<R>());
     cx<R> v[MAXIT][RAD];
     const int step = (L / (Ns * RAD)) * tmul;
+    // (total <= kTileElems / RAD < 2^22)
+    const UDiv dsplit = udiv((uint32_t)(TFAST ? ntrans : nb)), dns = udiv((uint32_t)Ns);
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it) {
         const int e = threadIdx.x + it * gen_threads<R>();
         if (e < total) {
-            int tr, j;
-            if (TFAST) { tr = e % ntrans; j = e / ntrans; }
-            else { j = e % nb; tr = e / nb; }
+            uint32_t tr, j;
+            if (TFAST) tr = udiv_qr((uint32_t)e, dsplit, &j);
+            else j = udiv_qr((uint32_t)e, dsplit, &tr);
             const cx<R>* base = lds + tr * ts;
 #pragma unroll
             for (int t = 0; t < RAD; ++t) v[it][t] = base[(j + t * nb) * es];
-            const int k = j % Ns;
+            uint32_t jq;
+            const int k = (int)udiv_qr(j, dns, &jq);
             if (Ns > 1 && k != 0) {
                 const cx<R> w = tab[k * step];
                 cx<R> wt = w;
@@ -192,12 +216,13 @@ __device__ __forceinline__ void stage(cx<R>* lds, int L, int ntrans, int ts, int
     for (int it = 0; it < MAXIT; ++it) {
         const int e = threadIdx.x + it * gen_threads<R>();
         if (e < total) {
-            int tr, j;
-            if (TFAST) { tr = e % ntrans; j = e / ntrans; }
-            else { j = e % nb; tr = e / nb; }
+            uint32_t tr, j;
+            if (TFAST) tr = udiv_qr((uint32_t)e, dsplit, &j);
+            else j = udiv_qr((uint32_t)e, dsplit, &tr);
             cx<R>* base = lds + tr * ts;
-            const int k = j % Ns;
-            const int dst = (j / Ns) * Ns * RAD + k;
+            uint32_t jq;
+            const int k = (int)udiv_qr(j, dns, &jq);
+            const int dst = (int)jq * Ns * RAD + k;
 #pragma unroll
             for (int t = 0; t < RAD; ++t) base[(dst + t * Ns) * es] = v[it][t];
         }
@@ -335,6 +360,21 @@ __device__ __forceinline__ int64_t pos_to_freq(const SymParams& sp, int a, int64
     const int64_t d0 = p / (s1 * s2);
     const int64_t rem = p - d0 * s1 * s2;
     const int64_t d1 = rem / s2, d2 = rem - d1 * s2;
+    return d0 + s0 * (d1 + s1 * d2);
+}
+
+// Stored position -> frequency along axis a in 32-bit arithmetic (extents below 2^31).
+__device__ __forceinline__ uint32_t pos_to_freq32(const SymParams& sp, int a, uint32_t p) {
+    const int nl = sp.nlev[a];
+    if (nl <= 1) return p;
+    const uint32_t s0 = (uint32_t)sp.sub[a][0], s1 = (uint32_t)sp.sub[a][1];
+    if (nl == 2) {
+        const uint32_t d0 = p / s1, d1 = p - d0 * s1;
+        return d0 + s0 * d1;
+    }
+    const uint32_t s2 = (uint32_t)sp.sub[a][2];
+    const uint32_t d0 = p / (s1 * s2), rem = p - d0 * s1 * s2;
+    const uint32_t d1 = rem / s2, d2 = rem - d1 * s2;
     return d0 + s0 * (d1 + s1 * d2);
 }
 

@@ -315,7 +315,10 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
 
     cx<R> xl = {R(0), R(0)};  // X[L] of a half-spectrum row (held by q == 0)
     if (KIND == ROW_C2R) {
-        if (q == 0 && active) xl = ((const cx<R>*)pd.buf)[row * pd.ostride + L];
+        // X[L] goes straight to its LDS slot, which nothing touches before the
+        // tangle reads it (holding it in registers across the loads made the
+        // FP64 kernel spill it to scratch memory in every thread)
+        if (q == 0) lds[idx(L)] = active ? ((const cx<R>*)pd.buf)[row * pd.ostride + L] : cx<R>{R(0), R(0)};
     } else if (KIND != ROW_CINV) {
         fast_fft<R, false, LOGL>(v, lds, idx, q, tlo, thi);
     }
@@ -367,7 +370,7 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 16; ++i) lds[idx(q + P * i)] = v[i];
-        if (q == 0) lds[idx(L)] = xl;
+        if (KIND != ROW_C2R && q == 0) lds[idx(L)] = xl;
         __syncthreads();
 #pragma unroll
         for (int i = 0; i < 16; ++i) {

@@ -145,20 +145,6 @@ __device__ __forceinline__ void mat_power(E (&D)[M][M], E (&P)[M][M], int64_t T)
         for (int j = 0; j < M; ++j) P[i][j] = V[i][j];
 }
 
-// Stored position -> frequency along axis a in 32-bit arithmetic (extents below 2^31).
-__device__ __forceinline__ uint32_t pos_to_freq32(const SymParams& sp, int a, uint32_t p) {
-    const int nl = sp.nlev[a];
-    if (nl <= 1) return p;
-    const uint32_t s0 = (uint32_t)sp.sub[a][0], s1 = (uint32_t)sp.sub[a][1];
-    if (nl == 2) {
-        const uint32_t d0 = p / s1, d1 = p - d0 * s1;
-        return d0 + s0 * d1;
-    }
-    const uint32_t s2 = (uint32_t)sp.sub[a][2];
-    const uint32_t d0 = p / (s1 * s2), rem = p - d0 * s1 * s2;
-    const uint32_t d1 = rem / s2, d2 = rem - d1 * s2;
-    return d0 + s0 * (d1 + s1 * d2);
-}
 
 // E(o f) of one axis from its E(f), E(2f): zero for o = 0, conjugate for o < 0.
 __device__ __forceinline__ dcx phase(const dcx (&Ea)[kMaxR + 1], int o) {

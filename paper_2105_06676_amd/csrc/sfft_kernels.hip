@@ -22,25 +22,34 @@ namespace sfft {
 __device__ __forceinline__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
 
 // (b, i_0 .. i_{d-2}) of row `row` of a row pass; rows are ordered [B][n_0]..[n_{d-2}].
+// (Unrolled over the at most two leading axes with selects: a run-time index into
+// the small array would place it in scratch memory.)
 __device__ __forceinline__ int64_t row_coords(const PassDesc& pd, int64_t row, int64_t* i) {
     int64_t rem = row;
-    for (int a = pd.d - 2; a >= 0; --a) {
-        const int64_t q = rem / pd.rdims[a];
-        i[a] = rem - q * pd.rdims[a];
-        rem = q;
+#pragma unroll
+    for (int a = 1; a >= 0; --a) {
+        if (a <= pd.d - 2) {
+            const int64_t n = a == 1 ? pd.rdims[1] : pd.rdims[0];
+            const int64_t q = rem / n;
+            i[a] = rem - q * n;
+            rem = q;
+        }
     }
     return rem;
 }
 
 __device__ __forceinline__ bool prefix_inside(const RealView& v, int d, const int64_t* i) {
-    for (int a = 0; a < d - 1; ++a)
-        if (i[a] >= v.ext[a]) return false;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+        if (a < d - 1 && i[a] >= v.ext[a]) return false;
     return true;
 }
 
 __device__ __forceinline__ int64_t prefix_offset(const RealView& v, int d, int64_t b, const int64_t* i) {
     int64_t off = b * v.boff;
-    for (int a = 0; a < d - 1; ++a) off += i[a] * v.stride[a];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+        if (a < d - 1) off += i[a] * v.stride[a];
     return off;
 }
 
@@ -52,10 +61,12 @@ __device__ void r2c_untangle(cx<R>* lds, int nrows, int LS, int L, const cx<R>* 
     // X[k] = (Z[k] + conj Z[L-k]) / 2 - i w^k (Z[k] - conj Z[L-k]) / 2, w = exp(-2 pi i / 2L)
     // tab holds exp(-2 pi i m / 2L).
     const int per = L / 2 + 1;
+    const UDiv dper = udiv((uint32_t)per);
     for (int e = threadIdx.x; e < nrows * per; e += gen_threads<R>()) {
-        const int rr = e / per, k = e - rr * per;
+        uint32_t rr;
+        const int k = (int)udiv_qr((uint32_t)e, dper, &rr);
         cx<R>* row = lds + rr * LS;
-        const int kk = (L - k) % L;
+        const int kk = k == 0 ? 0 : L - k;
         const cx<R> zk = row[k], zm = row[kk];
         if (k == 0) {
             row[0] = cx<R>{zk.x + zk.y, R(0)};
@@ -83,8 +94,10 @@ template <typename R>
 __device__ void c2r_tangle(cx<R>* lds, int nrows, int LS, int L, const cx<R>* tab) {
     // Z'[k] = (X[k] + conj X[L-k]) + i conj(w^k) (X[k] - conj X[L-k]), w as above.
     const int per = L / 2 + 1;
+    const UDiv dper = udiv((uint32_t)per);
     for (int e = threadIdx.x; e < nrows * per; e += gen_threads<R>()) {
-        const int rr = e / per, k = e - rr * per;
+        uint32_t rr;
+        const int k = (int)udiv_qr((uint32_t)e, dper, &rr);
         cx<R>* row = lds + rr * LS;
         const int kk = L - k;
         const cx<R> xk = row[k], xm = row[kk];
@@ -132,8 +145,10 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
     if (pd.in_real) {
         const int64_t sl = pd.rv.stride[pd.d - 1];
         const int64_t el = pd.rv.ext[pd.d - 1];
+        const UDiv dl = udiv((uint32_t)L);
         for (int e = threadIdx.x; e < nrows * L; e += gen_threads<R>()) {
-            const int rr = e / L, m = e - rr * L;
+            uint32_t rr;
+            const int m = (int)udiv_qr((uint32_t)e, dl, &rr);
             int64_t base;
             if (cached) {
                 base = base_in[rr];
@@ -155,8 +170,10 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
         }
     } else {
         const int cnt = pd.rowtrans == RT_HALF ? L + 1 : L;
+        const UDiv dc = udiv((uint32_t)cnt);
         for (int e = threadIdx.x; e < nrows * cnt; e += gen_threads<R>()) {
-            const int rr = e / cnt, m = e - rr * cnt;
+            uint32_t rr;
+            const int m = (int)udiv_qr((uint32_t)e, dc, &rr);
             const cx<R>* src = buf + (row0 + rr) * pd.ostride;
             cx<R> v;
             if (pd.rowtrans == RT_ODD && m >= pd.hcount) v = conj(src[L - m]);
@@ -182,8 +199,10 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
         // 1-D problems: axis 0 is the only axis, G[o] = c[o], K = 1 - sum c.
         const SymCol col = symbol_column_1d(sp);
         const int cnt = half ? L + 1 : L;
+        const UDiv dc = udiv((uint32_t)cnt);
         for (int e = threadIdx.x; e < nrows * cnt; e += gen_threads<R>()) {
-            const int rr = e / cnt, k = e - rr * cnt;
+            uint32_t rr;
+            const int k = (int)udiv_qr((uint32_t)e, dc, &rr);
             const int64_t p0 = ((row0 + rr) % pd.q_mod) * L + k;
             const int64_t f0 = pos_to_freq(sp, 0, p0);
             dcx v;
@@ -205,8 +224,10 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
         const int64_t sl = pd.rvo.stride[pd.d - 1];
         const int64_t el = pd.rvo.ext[pd.d - 1];
         const int per = half ? 2 * L : L;
+        const UDiv dp = udiv((uint32_t)per);
         for (int e = threadIdx.x; e < nrows * per; e += gen_threads<R>()) {
-            const int rr = e / per, m = e - rr * per;
+            uint32_t rr;
+            const int m = (int)udiv_qr((uint32_t)e, dp, &rr);
             if (m >= el) continue;
             int64_t base;
             if (cached && !pd.keep.enabled) {
@@ -216,7 +237,9 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
                 int64_t idx[3];
                 const int64_t b = row_coords(pd, row0 + rr, idx);
                 if (!prefix_inside(pd.rvo, pd.d, idx)) continue;
-                idx[pd.d - 1] = m;
+                if (pd.d == 1) idx[0] = m;
+                else if (pd.d == 2) idx[1] = m;
+                else idx[2] = m;
                 if (!keep_cell(pd.keep, pd.d, b, idx)) continue;
                 base = prefix_offset(pd.rvo, pd.d, b, idx);
             }
@@ -226,8 +249,10 @@ __device__ __forceinline__ void row_tile(const PassDesc& pd, const SymParams& sp
     } else {
         cx<R>* dst = (cx<R>*)pd.buf;
         const int cnt = pd.rowtrans == RT_C2C ? L : pd.hcount;
+        const UDiv dc = udiv((uint32_t)cnt);
         for (int e = threadIdx.x; e < nrows * cnt; e += gen_threads<R>()) {
-            const int rr = e / cnt, m = e - rr * cnt;
+            uint32_t rr;
+            const int m = (int)udiv_qr((uint32_t)e, dc, &rr);
             dst[(row0 + rr) * pd.ostride + m] = lds[rr * LS + m];
         }
     }
@@ -252,7 +277,7 @@ __device__ __forceinline__ void symbol_cols(cx<R>* lds, const SymParams& sp, con
     for (int k = k0; k < L; k += G * tpc) {
         uint32_t f[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) f[g] = (uint32_t)pos_to_freq(sp, 0, qpre + min(k + g * tpc, L - 1));
+        for (int g = 0; g < G; ++g) f[g] = pos_to_freq32(sp, 0, (uint32_t)(qpre + min(k + g * tpc, L - 1)));
         dcx v[G];
         symbol_power_g<G, RR>(sp, col, f, v);
 #pragma unroll
@@ -306,8 +331,10 @@ __device__ __forceinline__ void col_tile(const PassDesc& pd, const SymParams& sp
     };
 
     // ---- load (inverse passes multiply by the conjugate split twiddle first)
+    const UDiv dw = udiv((uint32_t)W);
     for (int e = threadIdx.x; e < L * W; e += gen_threads<R>()) {
-        const int k = e / W, cc = e - k * W;
+        uint32_t k;
+        const int cc = (int)udiv_qr((uint32_t)e, dw, &k);
         const int64_t c = c0 + cc;
         cx<R> v = {R(0), R(0)};
         int64_t twj;
@@ -358,7 +385,8 @@ __device__ __forceinline__ void col_tile(const PassDesc& pd, const SymParams& sp
 
     // ---- store (forward passes multiply by the split twiddle last)
     for (int e = threadIdx.x; e < L * W; e += gen_threads<R>()) {
-        const int k = e / W, cc = e - k * W;
+        uint32_t k;
+        const int cc = (int)udiv_qr((uint32_t)e, dw, &k);
         const int64_t c = c0 + cc;
         int64_t twj;
         if (!column(cc, &twj)) continue;
