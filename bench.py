@@ -103,11 +103,30 @@ def time_path(sfft, torch, w, dtype: str, steps: int, warmup: int):
     return wall, gpu_ms, lat, prof["kernels"], ok
 
 
-def serving_run(sfft, torch, reqs, rate=None, window=None, chunk=128, seed=5):
+def _request_grid(torch, r, gen, seed=5):
+    """The request's initial grid, filled on the device from a torch generator
+    seeded by the request id (the same grid every time it is drawn)."""
+    gen.manual_seed(seed * 1000003 + r.rid)
+    td = torch.float32 if r.dtype == "f32" else torch.float64
+    return torch.rand(r.dims, generator=gen, device="cuda", dtype=td)
+
+
+def _digest(torch, g):
+    """Two wrapping int64 sums over the bit patterns of a result (plain and
+    position-weighted): equal digests mean bit-identical results barring a
+    collision."""
+    v = g.reshape(-1).view(torch.int32 if g.dtype == torch.float32 else torch.int64).to(torch.int64)
+    w = torch.arange(v.numel(), device=v.device, dtype=torch.int64) * 2 + 1
+    return int(v.sum().item()), int((v * w).sum().item())
+
+
+def serving_run(sfft, torch, reqs, rate=None, window=None, chunk=128, seed=5, on_done=None):
     """Drive the continuous-batching server with the request list.  rate=None:
     closed loop (keep `window` requests outstanding); else open-loop Poisson
     arrivals at `rate` requests/s (the list's arrival times rescaled).  Grids are
-    filled on the device from seeded torch generators, a chunk ahead of use."""
+    filled on the device from seeded torch generators, a chunk ahead of use.
+    on_done(request, grid) is called for each finished request (verification
+    runs only: it is not part of a timed run)."""
     import time as _t
     srv = sfft.Server(0, 32 << 30, 64)
     gen = torch.Generator(device="cuda")
@@ -118,9 +137,7 @@ def serving_run(sfft, torch, reqs, rate=None, window=None, chunk=128, seed=5):
         nonlocal nxt
         out = []
         for r in reqs[nxt:nxt + chunk]:
-            gen.manual_seed(seed * 1000003 + r.rid)
-            td = torch.float32 if r.dtype == "f32" else torch.float64
-            out.append((r, torch.rand(r.dims, generator=gen, device="cuda", dtype=td)))
+            out.append((r, _request_grid(torch, r, gen, seed)))
         nxt += len(out)
         torch.cuda.synchronize()
         ready.extend(out)
@@ -160,6 +177,8 @@ def serving_run(sfft, torch, reqs, rate=None, window=None, chunk=128, seed=5):
                 a, b = srv.times(t)
                 lat.append(b - a)
                 cells_T += float(pending[t][0].cells) * pending[t][0].T
+                if on_done is not None:
+                    on_done(*pending[t])
                 del pending[t]
         _t.sleep(20e-6)
     wall = _t.perf_counter() - t0
@@ -170,19 +189,84 @@ def serving_run(sfft, torch, reqs, rate=None, window=None, chunk=128, seed=5):
             "req_per_s": len(lat) / wall,
             "cell_updates_per_s": cells_T / wall, "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "batches": st["batches"], "max_batch": st["max_batch"],
-            "peak_workspace_bytes": st["peak_bytes"]}
+            "peak_workspace_bytes": st["peak_bytes"], "device": st.get("device")}
 
 
-def serving_bench(sfft, torch, count):
+def serving_verify(sfft, torch, reqs, oracle_budget=4e9, per_stratum=9, seed=5):
+    """Correctness of the served mix: (1) every request's served result (closed
+    loop, as in the timed run) against the same request solved alone, bit for bit
+    (by digest); (2) a stratified sample -- up to `per_stratum` requests of each
+    (d, r, dtype) class among those whose loop-oracle cost N*T*(2r+1)^d is at most
+    5e7, spread over T -- against the FP64 loop oracle (rel-L2 and max-abs)."""
+    import oracle
+    strata = {}
+    for r in reqs:
+        if r.cells * r.T * (2 * r.radius + 1) ** r.ndim <= 5e7:
+            strata.setdefault((r.ndim, r.radius, r.dtype), []).append(r)
+    sample = set()
+    for key, lst in strata.items():
+        lst = sorted(lst, key=lambda q: q.T)
+        k = min(per_stratum, len(lst))
+        for j in range(k):
+            sample.add(lst[(j * (len(lst) - 1)) // max(1, k - 1)].rid)
+    mixed, kept = {}, {}
+
+    def on_done(r, g):
+        mixed[r.rid] = _digest(torch, g)
+        if r.rid in sample:
+            kept[r.rid] = g.cpu().numpy().astype(np.float64)
+
+    serving_run(sfft, torch, reqs, rate=None, window=256, seed=seed, on_done=on_done)
+    gen = torch.Generator(device="cuda")
+    mismatched = []
+    for r in reqs:
+        g = _request_grid(torch, r, gen, seed)
+        sfft.periodic(g, r.coeffs, r.T)
+        if _digest(torch, g) != mixed.get(r.rid):
+            mismatched.append(r.rid)
+    nthr = oracle.threads()
+    errs = {"f32": [], "f64": []}
+    spent = 0.0
+    t0 = time.perf_counter()
+    for rid in sorted(sample, key=lambda i: reqs[i].cells * reqs[i].T):
+        r = reqs[rid]
+        cost = r.cells * r.T * (2 * r.radius + 1) ** r.ndim
+        if spent + cost > oracle_budget:
+            continue
+        spent += cost
+        a0 = _request_grid(torch, r, gen, seed).cpu().numpy().astype(np.float64)
+        ref = oracle.periodic(a0, r.coeffs, r.T, nthreads=nthr)
+        e = _errors(kept[rid], ref)
+        e.update(rid=rid, dims=list(r.dims), radius=r.radius, T=r.T)
+        errs[r.dtype].append(e)
+    tol = {"f32": 1e-5, "f64": 1e-12}
+    summary = {}
+    for dt, lst in errs.items():
+        summary[dt] = {"checked": len(lst),
+                       "max_rel_l2": max((e["rel_l2"] for e in lst), default=None),
+                       "max_max_abs_rel": max((e["max_abs_rel"] for e in lst), default=None),
+                       "within_tolerance": all(e["rel_l2"] <= tol[dt] and e["max_abs_rel"] <= tol[dt] for e in lst),
+                       "strata": sorted({(e["dims"].__len__(), e["radius"]) for e in lst})}
+    return {"alone_vs_mix": {"requests": len(reqs), "bit_identical": len(reqs) - len(mismatched),
+                             "mismatched_ids": mismatched[:20]},
+            "oracle_sample": dict(summary, sample_size=sum(len(v) for v in errs.values()),
+                                  selection="up to 9 per (d, r, dtype) class with N*T*(2r+1)^d <= 5e7, spread over T",
+                                  oracle_s=time.perf_counter() - t0)}
+
+
+def serving_bench(sfft, torch, count, verify=True):
     import workloads as wl
     reqs = wl.serving_mix(count)
     # warm the plan cache with a short closed-loop pass over every distinct shape
     closed = serving_run(sfft, torch, reqs, rate=None, window=256)
     mu = closed["req_per_s"]
     openl = serving_run(sfft, torch, reqs, rate=0.7 * mu)
-    return {"workload": f"Poisson stream of {count} periodic requests: d ~ U{{1,2,3}}, cells log-uniform "
-                        "2^10..2^24 (7-smooth extents), r ~ U{1,2}, T log-uniform 1..1e5, FP32/FP64 50/50",
-            "closed_loop": closed, "open_loop_rate_req_s": 0.7 * mu, "open_loop": openl}
+    out = {"workload": f"Poisson stream of {count} periodic requests: d ~ U{{1,2,3}}, cells log-uniform "
+                       "2^10..2^24 (7-smooth extents), r ~ U{1,2}, T log-uniform 1..1e5, FP32/FP64 50/50",
+           "closed_loop": closed, "open_loop_rate_req_s": 0.7 * mu, "open_loop": openl}
+    if verify:
+        out["verification"] = serving_verify(sfft, torch, reqs)
+    return out
 
 
 def time_solve(sfft, torch, w, dtype, reps=5, warmup=1):
@@ -255,21 +339,90 @@ def copy_reference(torch, nbytes: int, reps: int = 10):
 
 
 def cpu_baseline(w, budget_s: float = 12.0):
-    """The FP64 loop oracle on the full-size grid for a bounded number of steps."""
+    """The FP64 loop oracle on the full-size grid for a bounded number of steps.
+    The grid is the FP32-rounded initial grid (exact in both dtypes), so the
+    oracle's output also serves as the expected value of both GPU paths at that
+    step count.  Returns (baseline record, rounded input, steps, oracle output)."""
     import oracle
-    a0 = w.grid()
+    a0 = w.grid().astype(np.float32).astype(np.float64)
     nthr = oracle.threads()
     t0 = time.perf_counter()
     oracle.periodic(a0, w.coeffs, 1, nthreads=nthr)
     t1 = time.perf_counter() - t0
     steps = int(max(1, min(64, budget_s / max(t1, 1e-3))))
     t0 = time.perf_counter()
-    oracle.periodic(a0, w.coeffs, steps, nthreads=nthr)
+    ref = oracle.periodic(a0, w.coeffs, steps, nthreads=nthr)
     dt = time.perf_counter() - t0
     cells = int(np.prod(w.dims))
-    return {"value": cells * steps / dt, "unit": "cell-updates/s", "cores": nthr, "kind": "oracle",
-            "sample": f"full {w.dims[0]}x{w.dims[1]} grid, {steps} of the {w.T} steps "
-                      f"(FP64 nested loop, OpenMP, {dt:.1f} s)"}
+    rec = {"value": cells * steps / dt, "unit": "cell-updates/s", "cores": nthr, "kind": "oracle",
+           "sample": f"full {w.dims[0]}x{w.dims[1]} grid, {steps} of the {w.T} steps "
+                     f"(FP64 nested loop, OpenMP, {dt:.1f} s)"}
+    return rec, a0, steps, ref
+
+
+def _errors(y: np.ndarray, ref: np.ndarray) -> dict:
+    """rel-L2 = |y - y*|_2 / |y*|_2, max-abs = max |y - y*|, and max-abs / max |y*|."""
+    d = np.abs(y - ref)
+    den = float(np.linalg.norm(ref))
+    mref = float(np.max(np.abs(ref)))
+    ma = float(np.max(d))
+    return {"rel_l2": float(np.linalg.norm(y - ref)) / den if den > 0 else float(np.linalg.norm(y - ref)),
+            "max_abs": ma, "max_abs_rel": ma / mref if mref > 0 else ma}
+
+
+def _gpu_solve(sfft, torch, a0, coeffs, T, dtype, aperiodic=False):
+    td = torch.float32 if dtype == "f32" else torch.float64
+    g = torch.from_numpy(np.ascontiguousarray(a0)).to(device="cuda:0", dtype=td)
+    (sfft.aperiodic if aperiodic else sfft.periodic)(g, coeffs, T)
+    torch.cuda.synchronize()
+    out = g.cpu().numpy().astype(np.float64)
+    del g
+    return out
+
+
+def result_errors(sfft, torch, w, full=None):
+    """Errors of GPU results against the FP64 loop oracle (the oracle of an FP32
+    result runs on the FP32-rounded input), per result:
+      * the 2-D Jacobi workload's 256 x 256 periodic instance (same stencil and
+        T = 4096, initial data the top-left crop of the seeded grid), FP32 and FP64;
+      * the full 8192 x 8192 grid at the step count of the CPU baseline's oracle
+        run (`full` = (rounded input, steps, oracle output)), FP32 and FP64;
+      * the full 8192 x 8192 FP32 result at T = 4096 against the FP64 GPU path
+        (the oracle cannot run 2.7e11 cell updates within the bench);
+      * the 1-D heat workload in full (N = 65536, T = 1024, FP64);
+      * a 256 x 256 instance of the aperiodic 9-point box workload (same
+        coefficients, T = 64, frame and interior from its seed), FP64 and FP32."""
+    import oracle
+    import workloads as wl
+    nthr = oracle.threads()
+    out = {"tolerance": {"f32": 1e-5, "f64": 1e-12}}
+    crop = wl.crop_grid(w, 256)
+    for dt in ("f32", "f64"):
+        a0 = crop.astype(np.float32).astype(np.float64) if dt == "f32" else crop
+        ref = oracle.periodic(a0, w.coeffs, w.T, nthreads=nthr)
+        out[f"jacobi2d_256x256_instance_T{w.T}_{dt}"] = _errors(_gpu_solve(sfft, torch, a0, w.coeffs, w.T, dt), ref)
+    if full is not None:
+        a0, steps, ref = full
+        for dt in ("f32", "f64"):
+            out[f"jacobi2d_8192x8192_T{steps}_{dt}"] = _errors(_gpu_solve(sfft, torch, a0, w.coeffs, steps, dt), ref)
+    a0 = w.grid().astype(np.float32).astype(np.float64)
+    y32 = _gpu_solve(sfft, torch, a0, w.coeffs, w.T, "f32")
+    y64 = _gpu_solve(sfft, torch, a0, w.coeffs, w.T, "f64")
+    out[f"jacobi2d_8192x8192_T{w.T}_f32_vs_gpu_f64"] = _errors(y32, y64)
+    del y32, y64, a0
+    w1 = wl.config("heat1d_65536")
+    ref = oracle.periodic(w1.grid(), w1.coeffs, w1.T, nthreads=nthr)
+    out[f"heat1d_65536_T{w1.T}_f64"] = _errors(_gpu_solve(sfft, torch, w1.grid(), w1.coeffs, w1.T, "f64"), ref)
+    w4 = wl.config("box2d_aperiodic_4096")
+    ap = wl.crop_grid(w4, 258)
+    for dt in ("f64", "f32"):
+        a0 = ap.astype(np.float32).astype(np.float64) if dt == "f32" else ap
+        ref = oracle.aperiodic(a0, w4.coeffs, 64, nthreads=nthr)
+        out[f"box2d_aperiodic_256x256_instance_T64_{dt}"] = _errors(
+            _gpu_solve(sfft, torch, a0, w4.coeffs, 64, dt, aperiodic=True), ref)
+    out["max_rel_l2_vs_oracle"] = {dt: max(v["rel_l2"] for k, v in out.items() if k.endswith("_" + dt) and "_vs_" not in k
+                                           and isinstance(v, dict) and "rel_l2" in v) for dt in ("f32", "f64")}
+    return out
 
 
 def main():
@@ -279,6 +432,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 path")
+    ap.add_argument("--no-errors", action="store_true", help="skip the per-result errors against the oracle")
     ap.add_argument("--serving", type=int, default=10000, help="serving-mix requests (0 = skip)")
     ap.add_argument("--no-copy", action="store_true", help="skip the device-copy bandwidth reference")
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads")
@@ -309,6 +463,11 @@ def main():
                  "kernels": {k: {"avg_us": v["ms"] * 1e3 / v["launches"],
                                  "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9}
                              for k, v in k64.items()}}
+
+    cpu_rec, cpu_full = None, None
+    if not args.no_cpu:
+        cpu_rec, a0r, steps_r, ref_r = cpu_baseline(w)
+        cpu_full = (a0r, steps_r, ref_r)
 
     # dominant kernel of the headline path
     dom = max(k32.items(), key=lambda kv: kv[1]["ms"])
@@ -350,8 +509,9 @@ def main():
         "copy_reference": None if args.no_copy else copy_reference(torch, N * 4 * 2),
         "other_workloads": None if args.no_others else other_workloads(
             sfft, torch, None if args.others is None else set(args.others.split(","))),
-        "cpu_baseline": None if args.no_cpu else cpu_baseline(w),
-        "serving": serving_bench(sfft, torch, args.serving) if args.serving > 0 else None,
+        "cpu_baseline": cpu_rec,
+        "errors": None if args.no_errors else result_errors(sfft, torch, w, cpu_full),
+        "serving": serving_bench(sfft, torch, args.serving, verify=not args.no_errors) if args.serving > 0 else None,
     }
     print(json.dumps(out))
 
