@@ -39,8 +39,10 @@
  *
  * Errors: SFFT_EINVAL (null pointer, ndim outside 1..3, an extent < 1,
  * radius < 0, T < 0, a non-finite coefficient, an unknown dtype);
- * SFFT_EUNSUPPORTED (a shape the FFT planner cannot handle, e.g. a prime factor
- * above 7 in an extent of the batched, serving, fields or implicit entry points);
+ * SFFT_EUNSUPPORTED (a shape the FFT planner cannot handle: a prime factor above
+ * 7 in an extent of the fields, implicit or no-allocation entry points, a radius
+ * above 8 (periodic) or above 2 (aperiodic, fields, implicit), a radius above 2
+ * on an extent with a prime factor above 7);
  * SFFT_ENOMEM (device workspace);
  * SFFT_EHIP (a HIP runtime error; the grid is then unspecified).  When
  * validation fails the grid is untouched.
@@ -83,6 +85,10 @@ enum {
  * otherwise each axis with a prime factor above 7 takes its DFT by Bluestein's
  * chirp-z algorithm (a circular convolution of a 7-smooth length >= 2n - 1) and
  * the others complex transforms, several times slower than a 7-smooth extent.
+ * Radius 0..2 runs the fused pass schedule (the symbol power inside the middle
+ * pass); radius 3..8 (7-smooth extents; a 1-D extent must fit one row, n/2 <= 8192)
+ * runs the forward passes, one kernel that forms the symbol of any radius and its
+ * power per mode, and the inverse passes.
  * Accuracy: relative L2 error against the exact result about 1e-6 (F32) and
  * 1e-14 (F64) for stable stencils; the symbol power is always FP64.
  */
@@ -194,10 +200,12 @@ typedef struct {
 
 /*
  * Solve n independent problems of uneven shapes, dtypes and T, enqueued on one
- * stream.  Periodic problems are packed into persistent batched launches: one
- * launch per pass index and kernel variant runs the tiles of every problem's
- * pass of that index that uses that variant.
- * Aperiodic problems are solved one after another on the same stream.
+ * stream.  Periodic problems of 7-smooth extents and radius <= 2 are packed into
+ * batched launches: one launch per pass index and kernel variant runs the tiles
+ * of every problem's pass of that index that uses that variant.  The others
+ * (aperiodic problems, periodic ones with a prime factor above 7 in an extent or
+ * a radius above 2) are solved one after another on the same stream, with the
+ * rules of their single-problem entry points.
  * Validation covers every problem before anything is enqueued: on error nothing
  * runs and the message names the offending problem index.
  */
@@ -222,10 +230,16 @@ void stencil_fft_graph_destroy(sfft_graph* g);
  * HIP streams and an HBM budget for workspace.  submit() never blocks: it
  * copies the request (coefficients included) and returns a ticket, or
  * SFFT_EINVAL / SFFT_EUNSUPPORTED for an invalid request, or SFFT_ENOMEM if the
- * request's own workspace exceeds the whole budget.  The worker admits queued
- * requests in arrival order while a slot is free and their workspace fits the
- * remaining budget, packs the admitted ones into batched launches on a free
- * stream, and releases slot and budget when that stream's work completes, so
+ * request's own workspace exceeds the whole budget.  Every device buffer of the
+ * server lives in one allocation of the budget made at creation: per-stream
+ * descriptor buffers, and per admitted request one block with everything its
+ * solve needs (the spectrum workspace and column table of a batched periodic
+ * request; every buffer of an aperiodic, chirp-z or radius > 2 request, sized at
+ * submit on the host by the solver's own bookkeeping).  The worker admits queued
+ * requests in arrival order while a slot is free and their block fits the
+ * remaining budget, packs the admitted batchable ones into batched launches on a
+ * free stream (the others run one after another on that stream), and releases
+ * slot and budget when that stream's work completes, so
  * requests that arrive while others run join the next launch.  The grid of a
  * request must stay alive until poll() reports it done.
  *  create:  device = HIP device ordinal; hbm_budget_bytes = workspace budget
@@ -263,6 +277,30 @@ void sfft_server_destroy(sfft_server* s);
  * Returns SFFT_EINVAL for an unknown name or an out-of-range value.
  */
 int stencil_fft_set_option(const char* name, int64_t value);
+
+/*
+ * Autotuner (plans for the batched and single periodic solves).  For every
+ * distinct extent of a strided axis (axes 0..ndim-2) of the given 7-smooth shape
+ * it times whole solves (radius 1, T = 4096, `reps` timed solves per candidate,
+ * median) with each candidate factorisation of that axis into sub-transforms --
+ * the planner's balanced default, the single transform when it fits (<= 1024
+ * points), the most balanced two-level splits in both orders, or the orders of a
+ * three-level split -- after checking each candidate's result (T = 3, every mode
+ * visible) against the default schedule's to 1e-5 (F32) / 1e-12 (F64) relative
+ * L2 and largest cell error; only candidates that pass may be chosen.  The
+ * fastest is kept in the process-wide tuning database keyed by (extent, dtype),
+ * which every later plan of that extent uses.  Allocates two grids of the shape
+ * and synchronises the device while it runs.  report (may be NULL) receives JSON
+ * of every candidate's time and error; returns its length or a negative code.
+ * save / load write and read the database as JSON ({"version": 1, "splits":
+ * [{"n": .., "f64": 0|1, "levels": [..]}, ..]}); load merges into the current
+ * database; clear empties it.  (Not a step of the paper's method: plan
+ * selection for the FFT passes.)
+ */
+int stencil_fft_tune(int ndim, const int64_t* dims, sfft_dtype dtype, int reps, char* report, int64_t cap);
+int stencil_fft_tune_save(const char* path);
+int stencil_fft_tune_load(const char* path);
+int stencil_fft_tune_clear(void);
 
 /*
  * Per-kernel timing with HIP events recorded on the launch stream around every

@@ -24,5 +24,9 @@ from ._binding import (  # noqa: F401
     profile_stop,
     set_option,
     symbol_power,
+    tune,
+    tune_clear,
+    tune_load,
+    tune_save,
     version,
 )

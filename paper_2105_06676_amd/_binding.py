@@ -60,6 +60,10 @@ _profile = _sig("stencil_fft_profile", ctypes.c_int, [ctypes.c_int])
 _profile_read = _sig("stencil_fft_profile_read", ctypes.c_int, [ctypes.c_char_p, ctypes.c_int64])
 _plan_describe = _sig("stencil_fft_plan_describe", ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_char_p, ctypes.c_int64])
 _version = _sig("stencil_fft_version", ctypes.c_char_p, [])
+_tune = _sig("stencil_fft_tune", ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_int64])
+_tune_save = _sig("stencil_fft_tune_save", ctypes.c_int, [ctypes.c_char_p])
+_tune_load = _sig("stencil_fft_tune_load", ctypes.c_int, [ctypes.c_char_p])
+_tune_clear = _sig("stencil_fft_tune_clear", ctypes.c_int, [])
 _srv_create = _sig("sfft_server_create", ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_uint64, ctypes.c_int])
 _srv_submit = _sig("sfft_server_submit", ctypes.c_int, [_vp, ctypes.POINTER(_Problem), ctypes.POINTER(ctypes.c_uint64)])
 _srv_poll = _sig("sfft_server_poll", ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)])
@@ -86,6 +90,29 @@ def _check(rc: int) -> int:
 
 def version() -> str:
     return _version().decode()
+
+
+def tune(dims, dtype: str = "f32", reps: int = 5, device: int = 0) -> dict:
+    """Autotune the strided-axis factorisations of a periodic shape (see
+    stencil_fft_tune); returns the tuner's report."""
+    import torch
+    d = (ctypes.c_int64 * len(dims))(*dims)
+    buf = ctypes.create_string_buffer(1 << 20)
+    with torch.cuda.device(device):
+        _check(_tune(len(dims), d, SFFT_F64 if dtype == "f64" else SFFT_F32, int(reps), buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def tune_save(path: str):
+    _check(_tune_save(path.encode()))
+
+
+def tune_load(path: str):
+    _check(_tune_load(path.encode()))
+
+
+def tune_clear():
+    _check(_tune_clear())
 
 
 def _coeffs(coeffs, ndim: int):

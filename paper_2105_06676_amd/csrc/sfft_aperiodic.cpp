@@ -32,6 +32,7 @@
 #include "sfft_base.h"
 #include "sfft_kernels.h"
 #include "sfft_runtime.h"
+#include "sfft_solvers.h"
 
 namespace sfft {
 

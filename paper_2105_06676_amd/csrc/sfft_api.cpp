@@ -7,8 +7,10 @@
 
 #include "../../include/stencil_fft.h"
 #include "sfft_fields.h"
+#include "sfft_general.h"
 #include "sfft_kernels.h"
 #include "sfft_runtime.h"
+#include "sfft_solvers.h"
 
 namespace sfft {
 const char* last_error_cstr();
@@ -16,8 +18,6 @@ void profile_enable(bool on);
 std::string profile_json();
 void solve_aperiodic_cached(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
                      hipStream_t st);
-void solve_periodic_any(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
-                        hipStream_t st);
 void solve_periodic_noalloc(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
                             int64_t T, hipStream_t st);
 }  // namespace sfft
@@ -45,7 +45,7 @@ int guarded(F&& f) {
 }
 
 void validate(const void* ptr, int dtype, int ndim, const int64_t* dims, const double* coeffs, int radius,
-              int64_t T) {
+              int64_t T, int max_radius = kMaxR) {
     if (!ptr) throw Error(SFFT_EINVAL, "grid pointer is null");
     if (dtype != SFFT_F32 && dtype != SFFT_F64) throw Error(SFFT_EINVAL, "unknown dtype");
     if (ndim < 1 || ndim > 3) throw Error(SFFT_EINVAL, "ndim must be 1, 2 or 3");
@@ -53,7 +53,8 @@ void validate(const void* ptr, int dtype, int ndim, const int64_t* dims, const d
     for (int a = 0; a < ndim; ++a)
         if (dims[a] < 1) throw Error(SFFT_EINVAL, "extents must be >= 1");
     if (radius < 0) throw Error(SFFT_EINVAL, "radius must be >= 0");
-    if (radius > kMaxR) throw Error(SFFT_EUNSUPPORTED, "radius above 2 is not supported");
+    if (radius > max_radius)
+        throw Error(SFFT_EUNSUPPORTED, "radius above " + std::to_string(max_radius) + " is not supported here");
     if (T < 0) throw Error(SFFT_EINVAL, "T must be >= 0");
     if (!coeffs) throw Error(SFFT_EINVAL, "coeffs pointer is null");
     int nc = 1;
@@ -82,6 +83,64 @@ void solve_periodic_dense(void* grid, bool f64, int d, const int64_t* dims, int6
     KeepRule keep;
     std::memset(&keep, 0, sizeof(keep));
     run_plan(*plan, ws, v, v, keep, sp, st);
+}
+
+// Periodic solve of a stencil of any radius up to kMaxGeneralR (7-smooth extents;
+// a 1-D extent must fit one row): forward passes, the general symbol kernel on
+// the half spectrum, inverse passes.
+// With `pool`, the workspace and the coefficients live at pool (at least
+// periodic_general_footprint bytes) instead of the context's per-stream buffers.
+size_t periodic_general_footprint(bool f64, int d, const int64_t* dims, int r) {
+    Schedule s;
+    std::string why;
+    const int rc = build_schedule(d, dims, 1, f64, &s, &why, true);
+    if (rc) throw Error(rc == -1 ? SFFT_EINVAL : SFFT_EUNSUPPORTED, why);
+    int nc = 1;
+    for (int a = 0; a < d; ++a) nc *= 2 * r + 1;
+    return ((size_t)s.spec_elems * (f64 ? 16 : 8) + 255) / 256 * 256 + sizeof(double) * (size_t)nc;
+}
+
+void solve_periodic_general(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
+                            int64_t T, hipStream_t st, void* pool) {
+    DevCtx& ctx = device_ctx();
+    auto plan = ctx.plan(d, dims, 1, f64, true);
+    const size_t wsb = (size_t)plan->s.spec_elems * (f64 ? 16 : 8);
+    void* ws = pool ? pool : ctx.workspace(st, wsb);
+    SymParams sp = plan->s.sym;
+    double N = 1.0;
+    int nc = 1;
+    for (int a = 0; a < d; ++a) {
+        N *= (double)dims[a];
+        nc *= 2 * r + 1;
+    }
+    std::vector<double> cn((size_t)nc);
+    fill_symbol(sp, coeffs, r, d, T, 1.0 / N, cn.data());
+    sp.d = d;
+    GeneralParams gp;
+    gp.ws = ws;
+    gp.pitch = plan->s.sym.sdim[d - 1];
+    gp.rows = plan->s.spec_elems / gp.pitch;
+    if (pool) {
+        void* cdev = (char*)pool + (wsb + 255) / 256 * 256;
+        ctx.upload_to(st, cdev, cn.data(), sizeof(double) * cn.size());
+        gp.c = (const double*)cdev;
+    } else {
+        gp.c = (const double*)ctx.upload(st, 61, cn.data(), sizeof(double) * cn.size());
+    }
+    gp.r = r;
+    RealView v = dense_view(grid, d, dims);
+    KeepRule keep;
+    std::memset(&keep, 0, sizeof(keep));
+    const int at = plan->s.sym_at;
+    run_plan(*plan, ws, v, v, keep, sp, st, 0, (size_t)at);
+    hipEvent_t ev = nullptr;
+    const bool prof = profiling();
+    if (prof) profile_launch_begin(st, &ev);
+    check_hip(launch_symbol_general(gp, sp, f64, st), "general symbol launch");
+    if (prof)
+        profile_launch_end(st, ev, f64 ? "general_symbol_f64" : "general_symbol_f32",
+                           2 * gp.rows * sp.hcount * (f64 ? 16 : 8));
+    run_plan(*plan, ws, v, v, keep, sp, st, (size_t)at);
 }
 
 // m coupled periodic fields (field-major grid): forward transforms of all fields
@@ -173,14 +232,19 @@ const char* stencil_fft_last_error(void) { return last_error_cstr(); }
 int stencil_fft_periodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims, const double* coeffs,
                          int radius, int64_t T, void* stream) {
     return guarded([&] {
-        validate(grid, dtype, ndim, dims, coeffs, radius, T);
+        validate(grid, dtype, ndim, dims, coeffs, radius, T, kMaxGeneralR);
         bool smooth = true;
         for (int a = 0; a < ndim; ++a) {
             if (dims[a] > ((int64_t)1 << 30)) throw Error(SFFT_EUNSUPPORTED, "extents above 2^30 are not supported");
             smooth = smooth && is_7smooth(dims[a]);
         }
+        if (radius > kMaxR && !smooth)
+            throw Error(SFFT_EUNSUPPORTED, "radius above 2 needs 7-smooth extents");
         if (T == 0) return;
-        if (smooth)
+        if (radius > kMaxR)
+            solve_periodic_general(grid, dtype == SFFT_F64, ndim, dims, coeffs, radius, T, (hipStream_t)stream,
+                                   nullptr);
+        else if (smooth)
             solve_periodic_dense(grid, dtype == SFFT_F64, ndim, dims, 1, coeffs, radius, T, (hipStream_t)stream);
         else
             solve_periodic_any(grid, dtype == SFFT_F64, ndim, dims, coeffs, radius, T, (hipStream_t)stream);

@@ -15,7 +15,9 @@
 #include <mutex>
 #include <tuple>
 
+#include "sfft_general.h"
 #include "sfft_kernels.h"
+#include "sfft_solvers.h"
 
 namespace sfft {
 
@@ -30,7 +32,8 @@ void validate_problem(const sfft_problem& p) {
     for (int a = 0; a < p.ndim; ++a)
         if (p.dims[a] < 1) throw Error(SFFT_EINVAL, "extents must be >= 1");
     if (p.radius < 0) throw Error(SFFT_EINVAL, "radius must be >= 0");
-    if (p.radius > kMaxR) throw Error(SFFT_EUNSUPPORTED, "radius above 2 is not supported");
+    if (p.radius > (p.aperiodic ? kMaxR : kMaxGeneralR))
+        throw Error(SFFT_EUNSUPPORTED, "radius " + std::to_string(p.radius) + " is not supported for this problem kind");
     if (p.T < 0) throw Error(SFFT_EINVAL, "T must be >= 0");
     if (!p.coeffs) throw Error(SFFT_EINVAL, "coeffs pointer is null");
     int nc = 1;
@@ -38,9 +41,18 @@ void validate_problem(const sfft_problem& p) {
     for (int i = 0; i < nc; ++i)
         if (!std::isfinite(p.coeffs[i])) throw Error(SFFT_EINVAL, "coefficient " + std::to_string(i) + " is not finite");
     if (!p.aperiodic)
-        for (int a = 0; a < p.ndim; ++a)
-            if (!is_7smooth(p.dims[a]))
-                throw Error(SFFT_EUNSUPPORTED, "extent " + std::to_string(p.dims[a]) + " has a prime factor above 7");
+        for (int a = 0; a < p.ndim; ++a) {
+            if (p.dims[a] > ((int64_t)1 << 30)) throw Error(SFFT_EUNSUPPORTED, "extents above 2^30 are not supported");
+            if (p.radius > kMaxR && !is_7smooth(p.dims[a]))
+                throw Error(SFFT_EUNSUPPORTED, "radius above 2 needs 7-smooth extents");
+        }
+}
+
+bool batchable(const sfft_problem& p) {
+    if (p.aperiodic || p.radius > kMaxR) return false;
+    for (int a = 0; a < p.ndim; ++a)
+        if (!is_7smooth(p.dims[a])) return false;
+    return true;
 }
 
 static size_t col_table_bytes(const SymParams& sym) {
@@ -212,8 +224,7 @@ void enqueue_batch(BatchProgram& prog, std::vector<ProblemRun>& runs, const Batc
 using namespace sfft;
 
 namespace sfft {
-void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
-                     hipStream_t st);
+
 int guarded_call(const std::function<void()>& f);
 }  // namespace sfft
 
@@ -240,7 +251,7 @@ int stencil_fft_batch(const sfft_problem* probs, int n, void* stream) {
         hipStream_t st = (hipStream_t)stream;
         std::vector<ProblemRun> runs;
         for (int i = 0; i < n; ++i)
-            if (!probs[i].aperiodic && probs[i].T > 0) runs.push_back(prepare_periodic(probs[i]));
+            if (batchable(probs[i]) && probs[i].T > 0) runs.push_back(prepare_periodic(probs[i]));
         if (!runs.empty()) {
             DevCtx& ctx = device_ctx();
             BatchMem mem;
@@ -251,10 +262,17 @@ int stencil_fft_batch(const sfft_problem* probs, int n, void* stream) {
             BatchProgram prog = build_batch(runs, mem);
             enqueue_batch(prog, runs, mem, st, true);
         }
-        for (int i = 0; i < n; ++i)
-            if (probs[i].aperiodic && probs[i].T > 0)
-                solve_aperiodic(probs[i].grid, probs[i].dtype == SFFT_F64, probs[i].ndim, probs[i].dims, probs[i].coeffs,
-                                probs[i].radius, probs[i].T, st);
+        for (int i = 0; i < n; ++i) {
+            const sfft_problem& p = probs[i];
+            if (batchable(p) || p.T == 0) continue;
+            const bool f64 = p.dtype == SFFT_F64;
+            if (p.aperiodic)
+                solve_aperiodic(p.grid, f64, p.ndim, p.dims, p.coeffs, p.radius, p.T, st);
+            else if (p.radius > kMaxR)
+                solve_periodic_general(p.grid, f64, p.ndim, p.dims, p.coeffs, p.radius, p.T, st);
+            else
+                solve_periodic_any(p.grid, f64, p.ndim, p.dims, p.coeffs, p.radius, p.T, st);
+        }
     });
 }
 
@@ -268,7 +286,9 @@ int stencil_fft_graph_create(const sfft_problem* probs, int n, sfft_graph** out)
             } catch (const Error& e) {
                 throw Error(e.code, "problem " + std::to_string(i) + ": " + e.what());
             }
-            if (probs[i].aperiodic) throw Error(SFFT_EUNSUPPORTED, "graphs hold periodic problems only");
+            if (!batchable(probs[i]))
+                throw Error(SFFT_EUNSUPPORTED, "problem " + std::to_string(i) +
+                                                   ": graphs hold periodic problems of 7-smooth extents and radius <= 2");
         }
         std::unique_ptr<sfft_graph> g(new sfft_graph());
         check_hip(hipGetDevice(&g->device), "hipGetDevice");

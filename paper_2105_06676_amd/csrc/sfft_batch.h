@@ -18,8 +18,12 @@ struct ProblemRun {
     size_t col_bytes = 0;   // per-column symbol table
 };
 
-// Validation shared by every entry point; throws Error.
+// Validation shared by every entry point; throws Error.  Periodic problems may
+// have any extent and radius up to kMaxGeneralR; aperiodic ones radius <= 2.
 void validate_problem(const sfft_problem& p);
+// Periodic problems that run in batched launches (7-smooth extents, radius <= 2);
+// the others are solved one after another on the batch's stream.
+bool batchable(const sfft_problem& p);
 
 // Plan a periodic problem (creates plans and tables on the current device).
 ProblemRun prepare_periodic(const sfft_problem& p);

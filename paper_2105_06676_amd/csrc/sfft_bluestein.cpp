@@ -18,6 +18,7 @@
 #include "sfft_bluestein.h"
 #include "sfft_kernels.h"
 #include "sfft_runtime.h"
+#include "sfft_solvers.h"
 
 namespace sfft {
 
@@ -159,9 +160,13 @@ void axis_transform(void* ws, void* tmp, int64_t outer, int64_t n, int64_t inner
 
 }  // namespace
 
-void solve_periodic_any(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
-                        hipStream_t st) {
-    DevCtx& ctx = device_ctx();
+namespace {
+// Byte offsets of the solve's buffers inside one region: workspace, convolution
+// scratch, column table.
+struct AnyLayout {
+    size_t ws, tmp, col, total;
+};
+AnyLayout any_layout(bool f64, int d, const int64_t* dims) {
     const size_t csz = f64 ? 16 : 8;
     int64_t N = 1;
     for (int a = 0; a < d; ++a) N *= dims[a];
@@ -170,8 +175,29 @@ void solve_periodic_any(void* grid, bool f64, int d, const int64_t* dims, const 
         if (is_7smooth(dims[a])) continue;
         tmp_elems = std::max(tmp_elems, N / dims[a] * conv_len(dims[a]));
     }
-    void* ws = ctx.workspace(st, (size_t)N * csz);
-    void* tmp = ctx.scratch(st, 70, (size_t)tmp_elems * csz);
+    int64_t ncol = 1;
+    for (int a = 1; a < d; ++a) ncol *= dims[a];
+    auto up = [](size_t x) { return (x + 255) / 256 * 256; };
+    AnyLayout l;
+    l.ws = 0;
+    l.tmp = up((size_t)N * csz);
+    l.col = l.tmp + up((size_t)tmp_elems * csz);
+    l.total = l.col + (d >= 2 ? up((size_t)ncol * symbol_column_bytes()) : 0);
+    return l;
+}
+}  // namespace
+
+size_t periodic_any_footprint(bool f64, int d, const int64_t* dims) { return any_layout(f64, d, dims).total; }
+
+void solve_periodic_any(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
+                        hipStream_t st, void* pool) {
+    DevCtx& ctx = device_ctx();
+    const size_t csz = f64 ? 16 : 8;
+    int64_t N = 1;
+    for (int a = 0; a < d; ++a) N *= dims[a];
+    const AnyLayout lay = any_layout(f64, d, dims);
+    void* ws = pool ? pool : ctx.workspace(st, lay.tmp);
+    void* tmp = pool ? (char*)pool + lay.tmp : ctx.scratch(st, 70, lay.col - lay.tmp);
     SymParams sp;
     std::memset(&sp, 0, sizeof(sp));
     sp.d = d;
@@ -192,7 +218,8 @@ void solve_periodic_any(void* grid, bool f64, int d, const int64_t* dims, const 
         for (int a = 0; a < d; ++a) sp.sdim[a] = dims[a];
         int64_t ncol = 1;
         for (int a = 1; a < d; ++a) ncol *= dims[a];
-        build_symbol_columns(sp, ctx.scratch(st, 71, (size_t)ncol * symbol_column_bytes()), f64, st);
+        build_symbol_columns(sp, pool ? (char*)pool + lay.col : ctx.scratch(st, 71, (size_t)ncol * symbol_column_bytes()),
+                             f64, st);
     }
     timed(st, "symbol_full", f64, 2 * N * (int64_t)csz, [&] { return launch_symbol_full(ws, sp, N, f64, st); });
     for (int a = d - 1; a >= 0; --a) {

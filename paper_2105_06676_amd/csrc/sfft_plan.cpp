@@ -46,9 +46,35 @@ static bool radix_list(int64_t L, int* out, int* nst) {
     return true;
 }
 
-// Split n (7-smooth) into 1..3 factors, each <= cap, as balanced as possible.
-static bool split_axis(int64_t n, int64_t cap, std::vector<int64_t>* out) {
+TuneDB& tune_db() {
+    static TuneDB db;
+    return db;
+}
+
+bool valid_split(int64_t n, const std::vector<int64_t>& lev) {
+    if (lev.empty() || lev.size() > 3) return false;
+    int64_t p = 1;
+    for (int64_t s : lev) {
+        if (s < 1 || s > kMaxTunedLevel) return false;
+        if (lev.size() > 1 && s < 2) return false;
+        p *= s;
+    }
+    return p == n;
+}
+
+// Split n (7-smooth) into 1..3 factors, each <= cap, as balanced as possible,
+// unless the tuning database holds a factorisation for (n, f64).
+static bool split_axis(int64_t n, int64_t cap, std::vector<int64_t>* out, bool f64) {
     out->clear();
+    {
+        TuneDB& db = tune_db();
+        std::lock_guard<std::mutex> g(db.mu);
+        auto it = db.split.find({n, f64 ? 1 : 0});
+        if (it != db.split.end() && valid_split(n, it->second)) {
+            *out = it->second;
+            return true;
+        }
+    }
     if (n <= cap) { out->push_back(n); return true; }
     int64_t best = 0, b0 = 0;
     for (int64_t s0 = 2; s0 <= cap && s0 < n; ++s0) {
@@ -298,7 +324,7 @@ int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* S,
         } else {
             const int64_t nr = split_row(n, row_max);
             std::vector<int64_t> lev;
-            if (!nr || !split_axis(n / nr, col_max, &lev) || lev.size() > 2) {
+            if (!nr || !split_axis(n / nr, col_max, &lev, f64) || lev.size() > 2) {
                 *why = "1-D extent " + std::to_string(n) + " cannot be split into supported factors";
                 return -2;
             }
@@ -356,7 +382,7 @@ int build_schedule(int d, const int64_t* dims, int64_t B, bool f64, Schedule* S,
 
         std::vector<std::vector<int64_t>> lev(d);
         for (int a = 0; a < d - 1; ++a) {
-            if (!split_axis(dims[a], col_max, &lev[a])) {
+            if (!split_axis(dims[a], col_max, &lev[a], f64)) {
                 *why = "extent " + std::to_string(dims[a]) + " cannot be split into supported factors";
                 return -2;
             }
@@ -451,13 +477,13 @@ int axis_schedule(int64_t outer, int64_t n, int64_t inner, bool f64, bool invers
         // (a power of two above the register row kernels' limit splits off
         // strided levels so that its row level stays on them)
         const int64_t nr = split_row(n, row_max);
-        if (!nr || !split_axis(n / nr, col_max, &lev) || lev.size() > 2) {
+        if (!nr || !split_axis(n / nr, col_max, &lev, f64) || lev.size() > 2) {
             *why = "length " + std::to_string(n) + " cannot be split into supported factors";
             return -2;
         }
         lev.push_back(nr);
         last_row = true;
-    } else if (!split_axis(n, col_max, &lev)) {
+    } else if (!split_axis(n, col_max, &lev, f64)) {
         *why = "length " + std::to_string(n) + " cannot be split into supported factors";
         return -2;
     }

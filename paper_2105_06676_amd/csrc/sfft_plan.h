@@ -3,6 +3,9 @@
 
 #include <stdint.h>
 
+#include <atomic>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -55,6 +58,18 @@ struct Schedule {
 // levels receives the factorisation (position -> frequency as in the solver).
 int axis_schedule(int64_t outer, int64_t n, int64_t inner, bool f64, bool inverse, std::vector<PassPlan>* out,
                   std::vector<int64_t>* levels, std::string* why);
+
+// Autotuned factorisations of strided axes: (extent, f64) -> factor levels in
+// pass order (the last level of axis 0 is the fused middle pass).  `gen` counts
+// changes, so cached plans built before a change are not reused.
+constexpr int64_t kMaxTunedLevel = 1024;
+struct TuneDB {
+    std::mutex mu;
+    std::map<std::pair<int64_t, int>, std::vector<int64_t>> split;
+    std::atomic<uint64_t> gen{0};
+};
+TuneDB& tune_db();
+bool valid_split(int64_t n, const std::vector<int64_t>& levels);
 
 struct Tunables {
     int col_max = 0;          // 0: default

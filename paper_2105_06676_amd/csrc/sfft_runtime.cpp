@@ -74,7 +74,8 @@ const double2* DevCtx::phase_table(int64_t n) {
 
 std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f64, bool unfused) {
     std::ostringstream key;
-    key << d << ":" << B << ":" << f64 << ":" << tunables().col_max << ":" << tunables().no_fast << ":" << unfused;
+    key << d << ":" << B << ":" << f64 << ":" << tunables().col_max << ":" << tunables().no_fast << ":" << unfused
+        << ":" << tune_db().gen.load();
     for (int a = 0; a < d; ++a) key << ":" << dims[a];
     {
         std::lock_guard<std::mutex> g(mu);
@@ -101,7 +102,7 @@ std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f
 std::shared_ptr<Plan> DevCtx::axis_plan(int64_t outer, int64_t n, int64_t inner, bool f64, bool inverse) {
     std::ostringstream key;
     key << "axis:" << outer << ":" << n << ":" << inner << ":" << f64 << ":" << inverse << ":"
-        << tunables().col_max << ":" << tunables().no_fast;
+        << tunables().col_max << ":" << tunables().no_fast << ":" << tune_db().gen.load();
     {
         std::lock_guard<std::mutex> g(mu);
         auto it = plans.find(key.str());
@@ -186,6 +187,11 @@ void* DevCtx::workspace(hipStream_t st, size_t bytes) {
 
 void* DevCtx::upload(hipStream_t st, int slot, const void* host, size_t bytes) {
     void* dev = scratch(st, slot, bytes);
+    upload_to(st, dev, host, bytes);
+    return dev;
+}
+
+void DevCtx::upload_to(hipStream_t st, void* dev, const void* host, size_t bytes) {
     std::lock_guard<std::mutex> g(mu);
     auto& sg = staging[st];
     if (!sg.second) check_hip(hipEventCreateWithFlags(&sg.second, hipEventDisableTiming), "hipEventCreate(staging)");
@@ -201,7 +207,6 @@ void* DevCtx::upload(hipStream_t st, int slot, const void* host, size_t bytes) {
     std::memcpy(sg.first.first, host, bytes);
     check_hip(hipMemcpyAsync(dev, sg.first.first, bytes, hipMemcpyHostToDevice, st), "upload");
     check_hip(hipEventRecord(sg.second, st), "hipEventRecord(staging)");
-    return dev;
 }
 
 hipStream_t DevCtx::side_stream(hipStream_t st, int i) {
@@ -242,9 +247,13 @@ void* DevCtx::scratch(hipStream_t st, int slot, size_t bytes) {
 
 // ---------------------------------------------------------------- symbol -----
 
-void fill_symbol(SymParams& sp, const double* coeffs, int r, int d, int64_t T, double scale) {
+void fill_symbol(SymParams& sp, const double* coeffs, int r, int d, int64_t T, double scale, double* cout) {
     int nc = 1;
     for (int a = 0; a < d; ++a) nc *= 2 * r + 1;
+    if (!cout) {
+        if (nc > kMaxCoef) throw Error(-2, "stencil has more coefficients than the fused passes hold");
+        cout = sp.c;
+    }
     sp.r = r;
     sp.ncoef = nc;
     sp.T = T;
@@ -271,7 +280,7 @@ void fill_symbol(SymParams& sp, const double* coeffs, int r, int d, int64_t T, d
         // multiply the result by lambda(0)^T, formed here in extended precision as
         // exp(T log|lambda(0)|) with log(s + comp) = log s + log1p(comp / s).
         const long double rho = (long double)s + (long double)comp;
-        for (int i = 0; i < nc; ++i) sp.c[i] = (double)((long double)coeffs[i] / rho);
+        for (int i = 0; i < nc; ++i) cout[i] = (double)((long double)coeffs[i] / rho);
         sp.one_minus_sum = 0.0;
         const long double as = std::fabs((long double)s);
         const long double lg = std::log(as) + std::log1p((long double)comp / (long double)s);
@@ -283,7 +292,7 @@ void fill_symbol(SymParams& sp, const double* coeffs, int r, int d, int64_t T, d
         // Mixed signs (or sum 0): no bound on |lambda| from lambda(0); every mode
         // takes the switching power.  1 - sum(c): when the sum is close to 1,
         // 1 - s is exact and only the final subtraction rounds.
-        for (int i = 0; i < nc; ++i) sp.c[i] = coeffs[i];
+        for (int i = 0; i < nc; ++i) cout[i] = coeffs[i];
         sp.one_minus_sum = (1.0 - s) - comp;
         sp.scale = scale;
         sp.switching = 1;

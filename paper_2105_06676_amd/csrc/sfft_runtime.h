@@ -60,6 +60,8 @@ struct DevCtx {
     // order, through a pinned staging buffer of that stream (the host data may be
     // released on return); returns the device pointer.
     void* upload(hipStream_t st, int slot, const void* host, size_t bytes);
+    // The same into a device buffer the caller owns.
+    void upload_to(hipStream_t st, void* dev, const void* host, size_t bytes);
     std::map<hipStream_t, std::pair<std::pair<void*, size_t>, hipEvent_t>> staging;
     hipStream_t side_stream(hipStream_t st, int i);
     hipEvent_t side_event(hipStream_t st, int i);
@@ -76,7 +78,10 @@ struct DevCtx {
 DevCtx& device_ctx();  // context of the current HIP device (created on first use)
 
 // Coefficient-dependent part of the symbol parameters (Sec. 3 Steps 1(i), 2).
-void fill_symbol(SymParams& sp, const double* coeffs, int radius, int d, int64_t T, double scale);
+// The (possibly normalised) coefficients go to sp.c, or to `cout` when given
+// (stencils with more than kMaxCoef coefficients).
+void fill_symbol(SymParams& sp, const double* coeffs, int radius, int d, int64_t T, double scale,
+                 double* cout = nullptr);
 
 // Fill `tab` with the per-column symbol parts of `sym` (d >= 2) and point
 // sym.coltab / sym.ncol at it.

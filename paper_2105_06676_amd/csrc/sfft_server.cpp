@@ -28,11 +28,9 @@
 #include <thread>
 
 #include "sfft_batch.h"
+#include "sfft_solvers.h"
 
 namespace sfft {
-size_t aperiodic_footprint(bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T);
-void solve_aperiodic_pooled(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
-                            int64_t T, hipStream_t st, void* pool, size_t cap);
 int guarded_call(const std::function<void()>& f);
 }  // namespace sfft
 
@@ -52,7 +50,8 @@ struct Req {
     std::vector<double> coeffs;
     size_t bytes;          // arena block: the request's device buffers
     size_t desc_bytes;     // its share of a batch's descriptor buffer
-    int64_t model_bytes;   // algorithmic HBM bytes of its passes (periodic)
+    int64_t model_bytes;   // algorithmic HBM bytes of its passes (batched requests)
+    bool batched;          // runs in the batched launches (else solved on its own)
 };
 
 // first-fit allocator over [0, cap)
@@ -155,7 +154,7 @@ void sfft_server::launch(int si, std::vector<Req>& reqs, std::vector<size_t>& of
     std::vector<ProblemRun> runs;
     std::vector<int> which;
     for (size_t i = 0; i < reqs.size(); ++i)
-        if (!reqs[i].p.aperiodic && reqs[i].p.T > 0) {
+        if (reqs[i].batched && reqs[i].p.T > 0) {
             runs.push_back(prepare_periodic(reqs[i].p));
             which.push_back((int)i);
         }
@@ -171,11 +170,19 @@ void sfft_server::launch(int si, std::vector<Req>& reqs, std::vector<size_t>& of
         BatchProgram prog = build_batch(runs, mem, &bases);
         enqueue_batch(prog, runs, mem, st, true);
     }
+    // the others, each in its own arena block
     for (size_t i = 0; i < reqs.size(); ++i) {
         const Req& r = reqs[i];
-        if (r.p.aperiodic && r.p.T > 0)
-            solve_aperiodic_pooled(r.p.grid, r.p.dtype == SFFT_F64, r.p.ndim, r.p.dims, r.coeffs.data(), r.p.radius,
-                                   r.p.T, st, arena_base + offs[i], r.bytes);
+        if (r.batched || r.p.T == 0) continue;
+        const bool f64 = r.p.dtype == SFFT_F64;
+        void* pool = arena_base + offs[i];
+        if (r.p.aperiodic)
+            solve_aperiodic_pooled(r.p.grid, f64, r.p.ndim, r.p.dims, r.coeffs.data(), r.p.radius, r.p.T, st, pool,
+                                   r.bytes);
+        else if (r.p.radius > kMaxR)
+            solve_periodic_general(r.p.grid, f64, r.p.ndim, r.p.dims, r.coeffs.data(), r.p.radius, r.p.T, st, pool);
+        else
+            solve_periodic_any(r.p.grid, f64, r.p.ndim, r.p.dims, r.coeffs.data(), r.p.radius, r.p.T, st, pool);
     }
 }
 
@@ -236,11 +243,11 @@ void sfft_server::run() {
             size_t nper = 0, items = 0;
             while (!queue.empty() && inflight_reqs + (int)adm.size() < max_slots) {
                 Req& r = queue.front();
-                const size_t add_items = r.p.aperiodic ? 0 : r.desc_bytes / sizeof(BatchItem);
-                if (!r.p.aperiodic && desc_need(nper + 1, items + add_items) > desc_cap) break;
+                const size_t add_items = r.batched ? r.desc_bytes / sizeof(BatchItem) : 0;
+                if (r.batched && desc_need(nper + 1, items + add_items) > desc_cap) break;
                 size_t off = 0;
                 if (!arena.alloc(std::max<size_t>(r.bytes, 256), &off)) break;
-                if (!r.p.aperiodic) {
+                if (r.batched) {
                     nper += 1;
                     items += add_items;
                 }
@@ -260,7 +267,7 @@ void sfft_server::run() {
                     // requests point at their own coefficient copies
                     r.p.coeffs = r.coeffs.data();
                     f.model_bytes += r.model_bytes;
-                    f.all_periodic = f.all_periodic && !r.p.aperiodic;
+                    f.all_periodic = f.all_periodic && r.batched;
                 }
                 stream_busy[si] = 1;
                 inflight_reqs += (int)adm.size();
@@ -423,9 +430,14 @@ int sfft_server_submit(sfft_server* s, const sfft_problem* p, uint64_t* ticket) 
         r.p.coeffs = r.coeffs.data();
         r.model_bytes = 0;
         r.desc_bytes = 0;
+        r.batched = batchable(*p);
+        const bool f64 = p->dtype == SFFT_F64;
         if (p->aperiodic) {
             // every buffer of the solve, sized by its own bookkeeping on the host
-            r.bytes = aperiodic_footprint(p->dtype == SFFT_F64, p->ndim, p->dims, r.coeffs.data(), p->radius, p->T);
+            r.bytes = aperiodic_footprint(f64, p->ndim, p->dims, r.coeffs.data(), p->radius, p->T);
+        } else if (!r.batched) {
+            r.bytes = p->radius > kMaxR ? periodic_general_footprint(f64, p->ndim, p->dims, p->radius)
+                                        : periodic_any_footprint(f64, p->ndim, p->dims);
         } else {
             const ProblemSize ps = problem_size(*p);
             r.bytes = ps.ws_bytes;

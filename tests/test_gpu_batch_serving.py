@@ -74,9 +74,10 @@ def test_batch_rejects_invalid_member_without_running():
     import paper_2105_06676_amd as sfft
     c = wl.box_random_coeffs(3, 2, 1)
     good = to_dev(np.ones((16, 16)), "f64")
-    bad = to_dev(np.ones((11, 16)), "f64")  # 11 is not 7-smooth
+    bad = to_dev(np.ones((11, 16)), "f64")
+    wide = np.ones((7, 7)) / 49  # radius 3 needs 7-smooth extents; 11 is not
     with pytest.raises(sfft.SfftError) as e:
-        sfft.batch([(good, c, 5), (bad, c, 5)])
+        sfft.batch([(good, c, 5), (bad, wide, 5)])
     assert "problem 1" in str(e.value)
     torch.cuda.synchronize()
     assert torch.equal(good, torch.ones_like(good))
@@ -154,7 +155,9 @@ def test_server_rejects_bad_requests():
     srv = sfft.Server(0, 1 << 20, 4)
     c = wl.jacobi5_coeffs()
     with pytest.raises(sfft.SfftError):
-        srv.submit(to_dev(np.ones((13, 16)), "f32"), c, 5)  # not 7-smooth
+        srv.submit(to_dev(np.ones((13, 16)), "f32"), np.ones((7, 7)) / 49, 5)  # radius 3 on a non-7-smooth extent
+    with pytest.raises(sfft.SfftError):
+        srv.submit(to_dev(np.ones((16, 16)), "f32"), c, -1)  # negative T
     with pytest.raises(sfft.SfftError) as e:
         srv.submit(to_dev(np.ones((1024, 1024)), "f64"), c, 5)  # workspace above the budget
     assert e.value.code == -3

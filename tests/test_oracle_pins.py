@@ -126,6 +126,27 @@ def test_exact_matrix_power_periodic(dims, T):
     assert np.array_equal(got, expect)
 
 
+@pytest.mark.parametrize("dims,r,T", [((9,), 3, 6), ((13,), 4, 5), ((5,), 4, 4), ((8, 9), 3, 3), ((4, 3, 5), 3, 2),
+                                     ((11,), 8, 3)])
+def test_exact_matrix_power_periodic_wide_radius(dims, r, T):
+    """The loop for radii above 2 (extents shorter than 2r + 1 alias offsets
+    modulo the extent) against the exact integer matrix power."""
+    d = len(dims)
+    rng = np.random.default_rng(40 + r + T)
+    den = 16
+    c_int = rng.integers(-4, 5, size=(2 * r + 1,) * d)
+    c_int.flat[0] = 3
+    c = c_int.astype(float) / den
+    x = rng.integers(-8, 9, size=dims)
+    A = _dense_periodic(c_int, dims)
+    v = [int(t) for t in x.ravel()]
+    for _ in range(T):
+        v = _matvec(A, v)
+    expect = np.array([float(Fraction(t, den ** T)) for t in v]).reshape(dims)
+    got = oracle.periodic(x.astype(float), c, T)
+    assert np.array_equal(got, expect)
+
+
 @pytest.mark.parametrize("dims,T", [((6,), 7), ((4, 5), 5), ((3, 3, 2), 4), ((2, 2), 9)])
 def test_exact_affine_power_aperiodic(dims, T):
     """Fixed frame as an affine map: state (interior, 1) evolves by [[S_int, b], [0, 1]]
