@@ -10,9 +10,11 @@ Contents
     T sweeps of the periodic nested loop in FP64 (C, ``loops.c``): the plain
     definition ``a_T = S^T a_0`` of the paper's periodic problem (Sec. 3, the
     periodic looping algorithm; d-D form in the appendix on d-D grids).
-``aperiodic(a, coeffs, T)``
+``aperiodic(a, coeffs, T, bc="fixed")``
     The aperiodic nested loop with a fixed r-wide frame (Sec. 2 aperiodic looping
-    algorithm; Sec. 4 for what StencilFFT-A must reproduce).
+    algorithm; Sec. 4 for what StencilFFT-A must reproduce).  ``bc="reflect"``:
+    the zero-flux (Neumann) boundary Sec. 4 names among the base case's options,
+    the frame refilled before every step with the mirror image of the interior.
 ``periodic_fields(a, coeffs, T)``
     T sweeps of the periodic loop for m coupled scalar fields (the vector-valued
     extension of Sec. 3 and its appendix): field i at t+1 is the sum over j of
@@ -78,6 +80,10 @@ def _load():
         lib.oracle_periodic_fields.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                                ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p, ctypes.c_int,
                                                ctypes.c_int64, ctypes.c_int]
+        lib.oracle_aperiodic_bc.restype = ctypes.c_int
+        lib.oracle_aperiodic_bc.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                                            ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                            ctypes.c_int]
         lib.oracle_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -174,18 +180,31 @@ def implicit_periodic(a: np.ndarray, q: np.ndarray, s: np.ndarray, T: int, rcond
     return x
 
 
-def aperiodic(a: np.ndarray, coeffs: np.ndarray, T: int, nthreads: int = 0) -> np.ndarray:
-    """``a`` has extents n_i + 2r; the r-wide frame is fixed; the interior evolves T steps."""
+BCS = {"fixed": 0, "reflect": 1}
+
+
+def aperiodic(a: np.ndarray, coeffs: np.ndarray, T: int, nthreads: int = 0, bc: str = "fixed") -> np.ndarray:
+    """``a`` has extents n_i + 2r; the interior evolves T steps.
+
+    ``bc="fixed"``: the r-wide frame holds fixed boundary values.  ``bc="reflect"``:
+    before every step the frame is the mirror image of the interior about the
+    cell faces (zero-flux boundary); the frame's input values are ignored and the
+    returned frame is the mirror image of the final interior."""
+    if bc not in BCS:
+        raise ValueError(f"bc must be one of {sorted(BCS)}")
     x = np.ascontiguousarray(a, dtype=np.float64).copy()
     c = np.ascontiguousarray(coeffs, dtype=np.float64)
     r = _check_coeffs(c, x.ndim)
     interior = [s - 2 * r for s in x.shape]
     if min(interior) < 1:
         raise ValueError("interior extents must be >= 1")
+    if bc == "reflect" and min(interior) < r:
+        raise ValueError("a reflecting boundary needs interior extents >= r")
     dims = (ctypes.c_int64 * x.ndim)(*interior)
-    rc = _load().oracle_aperiodic(x.ctypes.data, x.ndim, dims, c.ctypes.data, r, int(T), int(nthreads))
+    rc = _load().oracle_aperiodic_bc(x.ctypes.data, x.ndim, dims, c.ctypes.data, r, int(T), BCS[bc],
+                                     int(nthreads))
     if rc != 0:
-        raise RuntimeError(f"oracle_aperiodic failed ({rc})")
+        raise RuntimeError(f"oracle_aperiodic_bc failed ({rc})")
     return x
 
 

@@ -18,6 +18,12 @@
  *    frame holds fixed (Dirichlet) boundary values and is copied unchanged each step;
  *    interior cells use the same sum without the modulo (the aperiodic looping
  *    algorithm of the same figure, with r boundary cells on each side).
+ *    With the reflecting (zero-flux, Neumann) boundary instead, the frame is
+ *    refilled before every step as the mirror image of the interior: along each
+ *    axis, frame cell r-1-k takes the value of interior cell r+k and frame cell
+ *    n+r+k that of n+r-1-k (the even extension of the grid about the cell faces),
+ *    corners mirrored along every axis they lie outside of; Sec. 4 lists such
+ *    boundaries among those the base case may apply.
  *
  *  - periodic fields: m scalar fields a^(0..m-1) on the same periodic grid, each
  *    step computing b^(i)[x] = sum over j (field order), then over offsets o (row-major),
@@ -99,14 +105,29 @@ int oracle_periodic(double* a, int ndim, const int64_t* dims, const double* coef
     return 0;
 }
 
+/* Mirror image of storage coordinate g along an axis with interior extent n and
+ * frame width r: frame cells reflect about the nearer cell face, interior cells
+ * map to themselves. */
+static int64_t mirror(int64_t g, int64_t n, int r) {
+    if (g < r) return 2 * (int64_t)r - 1 - g;
+    if (g >= n + r) return 2 * (n + r) - 1 - g;
+    return g;
+}
+
 /* a: prod(dims[k] + 2r) doubles (interior plus an r-wide frame on every side);
- * the frame is left unchanged and the interior evolves T steps. */
-int oracle_aperiodic(double* a, int ndim, const int64_t* dims, const double* coeffs,
-                     int r, int64_t T, int nthreads) {
+ * the interior evolves T steps.  bc 0: the frame holds fixed values and is left
+ * unchanged.  bc 1: reflecting boundary; the frame's input values are ignored and
+ * on return it holds the mirror image of the final interior (every interior
+ * extent must be at least r, so that each mirror image lies inside). */
+int oracle_aperiodic_bc(double* a, int ndim, const int64_t* dims, const double* coeffs,
+                        int r, int64_t T, int bc, int nthreads) {
     if (ndim < 1 || ndim > 3 || r < 0 || T < 0 || !a || !dims || !coeffs) return -1;
+    if (bc != 0 && bc != 1) return -1;
     int64_t n[3]; int rr[3];
     expand3(ndim, dims, r, n, rr);
     for (int k = 0; k < 3; ++k) if (n[k] < 1) return -1;
+    if (bc == 1)
+        for (int k = 0; k < ndim; ++k) if (dims[k] < r) return -1;
     int64_t s[3]; /* storage extents */
     for (int k = 0; k < 3; ++k) s[k] = n[k] + 2 * rr[k];
     const int64_t S = s[0] * s[1] * s[2];
@@ -117,7 +138,19 @@ int oracle_aperiodic(double* a, int ndim, const int64_t* dims, const double* coe
     double* src = a;
     double* dst = b;
     if (nthreads <= 0) nthreads = oracle_threads();
-    for (int64_t t = 0; t < T; ++t) {
+    for (int64_t t = 0; t <= T; ++t) {
+        if (bc == 1) {
+            /* frame of the current state := mirror image of its interior */
+            for (int64_t i0 = 0; i0 < s[0]; ++i0)
+                for (int64_t i1 = 0; i1 < s[1]; ++i1)
+                    for (int64_t i2 = 0; i2 < s[2]; ++i2) {
+                        const int64_t m0 = mirror(i0, n[0], rr[0]), m1 = mirror(i1, n[1], rr[1]),
+                                      m2 = mirror(i2, n[2], rr[2]);
+                        if (m0 != i0 || m1 != i1 || m2 != i2)
+                            src[(i0 * s[1] + i1) * s[2] + i2] = src[(m0 * s[1] + m1) * s[2] + m2];
+                    }
+        }
+        if (t == T) break;
 #pragma omp parallel for schedule(static) num_threads(nthreads)
         for (int64_t i0 = rr[0]; i0 < rr[0] + n[0]; ++i0) {
             for (int64_t i1 = rr[1]; i1 < rr[1] + n[1]; ++i1) {
@@ -141,6 +174,11 @@ int oracle_aperiodic(double* a, int ndim, const int64_t* dims, const double* coe
     if (src != a) memcpy(a, src, sizeof(double) * (size_t)S);
     free(b);
     return 0;
+}
+
+int oracle_aperiodic(double* a, int ndim, const int64_t* dims, const double* coeffs,
+                     int r, int64_t T, int nthreads) {
+    return oracle_aperiodic_bc(a, ndim, dims, coeffs, r, T, 0, nthreads);
 }
 
 /* a: m * prod(dims) doubles, field-major ([m][dims...]), overwritten with the state
