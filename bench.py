@@ -266,6 +266,13 @@ def serving_bench(sfft, torch, count, verify=True):
            "closed_loop": closed, "open_loop_rate_req_s": 0.7 * mu, "open_loop": openl}
     if verify:
         out["verification"] = serving_verify(sfft, torch, reqs)
+    # the same distribution at exact extents (rounded to the nearest integer, not
+    # to a 7-smooth one): requests with a prime factor above 7 in an extent take
+    # the chirp-z path, each solved on its own inside its arena block
+    exact = wl.serving_mix(count // 5, smooth=False)
+    out["exact_extents"] = dict(serving_run(sfft, torch, exact, rate=None, window=256),
+                                workload=f"{count // 5} requests of the same distribution with extents rounded to "
+                                         "the nearest integer")
     return out
 
 
@@ -297,7 +304,7 @@ def time_solve(sfft, torch, w, dtype, reps=5, warmup=1):
     return {"ms": ms, "cell_updates_per_s": cells * w.T / (ms * 1e-3)}
 
 
-def other_workloads(sfft, torch, only=None):
+def other_workloads(sfft, torch, only=None, reps=5, warmup=1):
     """The other workloads of the method, timed the same way (context for the headline);
     `only`: a set of "<workload>_<dtype>" keys to restrict the list to."""
     import workloads as wl
@@ -306,12 +313,13 @@ def other_workloads(sfft, torch, only=None):
                       ("box2d_aperiodic_4096", ("f64", "f32")), ("upwind2d_aperiodic_4096", ("f64", "f32")),
                       ("wave2d_leapfrog_4096", ("f32", "f64")),
                       ("heat2d_backward_euler_4096", ("f32", "f64")), ("jacobi2d_6300x6720_smooth", ("f32",)),
+                      ("jacobi2d_8000_smooth", ("f32", "f64")), ("heat3d_800_smooth", ("f32",)),
                       ("jacobi2d_8191_prime", ("f32",))):
         w = wl.config(name)
         for dt in dts:
             if only is not None and f"{name}_{dt}" not in only:
                 continue
-            out[f"{name}_{dt}"] = dict(time_solve(sfft, torch, w, dt), dims=list(w.dims), T=w.T,
+            out[f"{name}_{dt}"] = dict(time_solve(sfft, torch, w, dt, reps=reps, warmup=warmup), dims=list(w.dims), T=w.T,
                                        aperiodic=w.aperiodic, fields=w.fields, implicit=w.implicit_q is not None)
     return out
 
@@ -433,11 +441,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 path")
     ap.add_argument("--no-errors", action="store_true", help="skip the per-result errors against the oracle")
+    ap.add_argument("--no-tune", action="store_true", help="plan with the default heuristics (no autotuning)")
     ap.add_argument("--serving", type=int, default=10000, help="serving-mix requests (0 = skip)")
     ap.add_argument("--no-copy", action="store_true", help="skip the device-copy bandwidth reference")
     ap.add_argument("--no-others", action="store_true", help="skip the other workloads")
     ap.add_argument("--others", default=None,
                     help="comma-separated <workload>_<dtype> keys: time only these other workloads")
+    ap.add_argument("--only-others", action="store_true",
+                    help="profiling runs: time only the other workloads (prints their JSON, no headline line)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -449,8 +460,24 @@ def main():
     import paper_2105_06676_amd as sfft
     import workloads as wl
 
+    if args.only_others:
+        print(json.dumps({"other_workloads": other_workloads(
+            sfft, torch, None if args.others is None else set(args.others.split(",")), reps=args.steps,
+            warmup=args.warmup)}))
+        return
+
     w = wl.config("jacobi2d_8192")
     N = int(np.prod(w.dims))
+    # plan selection by the library's autotuner, outside the timed regions
+    tuning = {}
+    if not args.no_tune:
+        for dt in ("f32",) + (() if args.no_f64 else ("f64",)):
+            t0 = time.perf_counter()
+            rep = sfft.tune(w.dims, dt, reps=5)
+            tuning[dt] = {"seconds": time.perf_counter() - t0,
+                          "axes": [{"n": a["n"], "chosen": a["chosen"], "chosen_us": a["chosen_us"],
+                                    "default_us": a["default_us"]} for a in rep["axes"]],
+                          "plan": sfft.plan_describe(w.dims, dt)["levels"]}
     wall32, gms32, lat32, k32, ok32 = time_path(sfft, torch, w, "f32", args.steps, args.warmup)
     ms32 = wall32 * 1e3 / args.steps
     res64 = None
@@ -506,6 +533,7 @@ def main():
         "kernels_f32": {k: {"avg_us": v["ms"] * 1e3 / v["launches"], "launches": v["launches"],
                             "GBps": v["bytes"] / (v["ms"] * 1e-3) / 1e9} for k, v in k32.items()},
         "f64": res64,
+        "autotune": tuning or None,
         "copy_reference": None if args.no_copy else copy_reference(torch, N * 4 * 2),
         "other_workloads": None if args.no_others else other_workloads(
             sfft, torch, None if args.others is None else set(args.others.split(","))),

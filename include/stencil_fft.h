@@ -75,6 +75,16 @@ enum {
     SFFT_ENOTFOUND = -6
 };
 
+/* Boundary conditions of the aperiodic solve (Sec. 4 leaves the choice to the
+ * base case of RecursiveBoundary). */
+enum {
+    SFFT_BC_FIXED = 0,   /* Dirichlet: the frame holds fixed boundary values        */
+    SFFT_BC_REFLECT = 1  /* zero-flux (Neumann): before every step each frame cell
+                            takes the value of its mirror image about the cell faces
+                            (interior cell r + k for frame cell r - 1 - k along each
+                            axis it lies outside of)                                 */
+};
+
 /*
  * Periodic stencil solve (Sec. 3, StencilFFT-P; d-D form in the appendix on
  * d-D grids).  grid holds prod(dims) cells; on return (once the stream has run)
@@ -110,6 +120,20 @@ int stencil_fft_periodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* 
  */
 int stencil_fft_aperiodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims,
                           const double* coeffs, int radius, int64_t T, void* stream);
+
+/*
+ * stencil_fft_aperiodic with a choice of boundary condition (Sec. 4: the FFT
+ * parts of RecursiveBoundary only keep cells whose dependency cone stays inside
+ * the interior, so the boundary enters through the base case alone).
+ *   bc  SFFT_BC_FIXED: exactly stencil_fft_aperiodic.
+ *       SFFT_BC_REFLECT: the frame's values are never read and are left
+ *       unchanged; the interior evolves as if, before every step, the frame held
+ *       the mirror image of the interior.  Every interior extent must be at least
+ *       radius (SFFT_EINVAL otherwise).
+ * Other bc values: SFFT_EINVAL.  Everything else as stencil_fft_aperiodic.
+ */
+int stencil_fft_aperiodic_bc(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims,
+                             const double* coeffs, int radius, int64_t T, int bc, void* stream);
 
 /*
  * Vector-valued fields (the appendix on vector-valued fields): nfields scalar
@@ -195,7 +219,9 @@ typedef struct {
     const double* coeffs;  /* HOST pointer, (2*radius+1)^ndim doubles, copied       */
     int radius;
     int64_t T;
-    int aperiodic;         /* 0: periodic (dims = grid extents); 1: aperiodic       */
+    int aperiodic;         /* 0: periodic (dims = grid extents); 1: aperiodic with
+                              a fixed frame; 2: aperiodic with a reflecting frame
+                              (SFFT_BC_REFLECT)                                     */
 } sfft_problem;
 
 /*
@@ -281,8 +307,8 @@ int stencil_fft_set_option(const char* name, int64_t value);
 /*
  * Autotuner (plans for the batched and single periodic solves).  For every
  * distinct extent of a strided axis (axes 0..ndim-2) of the given 7-smooth shape
- * it times whole solves (radius 1, T = 4096, `reps` timed solves per candidate,
- * median) with each candidate factorisation of that axis into sub-transforms --
+ * it times whole solves (radius 1, T = 4096; three runs of `reps` back-to-back
+ * solves per candidate, median) with each candidate factorisation of that axis into sub-transforms --
  * the planner's balanced default, the single transform when it fits (<= 1024
  * points), the most balanced two-level splits in both orders, or the orders of a
  * three-level split -- after checking each candidate's result (T = 3, every mode

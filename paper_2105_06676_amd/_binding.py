@@ -52,6 +52,10 @@ _periodic_fields = _sig("stencil_fft_periodic_fields", ctypes.c_int,
 _periodic_implicit = _sig("stencil_fft_periodic_implicit", ctypes.c_int,
                          [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, _dp, ctypes.c_int, ctypes.c_int64, _vp])
 _aperiodic = _sig("stencil_fft_aperiodic", ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
+_aperiodic_bc = _sig("stencil_fft_aperiodic_bc", ctypes.c_int,
+                     [_vp, ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, ctypes.c_int, _vp])
+SFFT_BC_FIXED, SFFT_BC_REFLECT = 0, 1
+_BCS = {"fixed": SFFT_BC_FIXED, "reflect": SFFT_BC_REFLECT}
 _last_error = _sig("stencil_fft_last_error", ctypes.c_char_p, [])
 _symbol_power = _sig("stencil_fft_symbol_power", ctypes.c_int, [_vp, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64, _vp])
 _batch = _sig("stencil_fft_batch", ctypes.c_int, [ctypes.POINTER(_Problem), ctypes.c_int, _vp])
@@ -205,17 +209,25 @@ def periodic_implicit(grid, q_coeffs, s_coeffs, T: int, stream=None):
     return grid
 
 
-def aperiodic(grid, coeffs, T: int, stream=None):
-    """Evolve the interior of ``grid`` T steps in place; the outer r-wide frame holds
-    fixed boundary values (grid extents are interior extents + 2r)."""
+def aperiodic(grid, coeffs, T: int, stream=None, bc: str = "fixed"):
+    """Evolve the interior of ``grid`` T steps in place (grid extents are interior
+    extents + 2r).  ``bc="fixed"``: the outer r-wide frame holds fixed boundary
+    values; ``bc="reflect"``: zero-flux boundary, the frame is not read (before
+    every step it stands for the mirror image of the interior)."""
     import torch
     _check_grid(grid)
+    if bc not in _BCS:
+        raise ValueError(f"bc must be one of {sorted(_BCS)}")
     c, r = _coeffs(coeffs, grid.dim())
     interior = [s - 2 * r for s in grid.shape]
     dims = (ctypes.c_int64 * grid.dim())(*interior)
     with torch.cuda.device(grid.device):
-        _check(_aperiodic(grid.data_ptr(), _dtype_code(grid), grid.dim(), dims,
-                          c.ctypes.data_as(_dp), r, int(T), _stream(grid, stream)))
+        if bc == "fixed":
+            _check(_aperiodic(grid.data_ptr(), _dtype_code(grid), grid.dim(), dims,
+                              c.ctypes.data_as(_dp), r, int(T), _stream(grid, stream)))
+        else:
+            _check(_aperiodic_bc(grid.data_ptr(), _dtype_code(grid), grid.dim(), dims,
+                                 c.ctypes.data_as(_dp), r, int(T), _BCS[bc], _stream(grid, stream)))
     return grid
 
 
@@ -232,7 +244,16 @@ def symbol_power(out, dims: Sequence[int], coeffs, T: int, stream=None):
     return out
 
 
-def _problem(grid, coeffs, T, aperiodic_: bool, keep):
+def _kind(aperiodic_) -> int:
+    """sfft_problem.aperiodic from False/True or a boundary name."""
+    if isinstance(aperiodic_, str):
+        if aperiodic_ not in _BCS:
+            raise ValueError(f"boundary must be one of {sorted(_BCS)}")
+        return 1 + _BCS[aperiodic_]
+    return 1 if aperiodic_ else 0
+
+
+def _problem(grid, coeffs, T, aperiodic_, keep):
     _check_grid(grid)
     c, r = _coeffs(coeffs, grid.dim())
     keep.append(c)
@@ -246,20 +267,21 @@ def _problem(grid, coeffs, T, aperiodic_: bool, keep):
     p.coeffs = c.ctypes.data_as(_dp)
     p.radius = r
     p.T = int(T)
-    p.aperiodic = 1 if aperiodic_ else 0
+    p.aperiodic = _kind(aperiodic_)
     return p
 
 
 def batch(problems, stream=None):
     """Solve a list of ``(grid, coeffs, T)`` or ``(grid, coeffs, T, aperiodic)`` in
-    batched launches on one stream."""
+    batched launches on one stream (``aperiodic``: False, True = fixed frame,
+    or a boundary name, "fixed" or "reflect")."""
     import torch
     keep = []
     arr = (_Problem * len(problems))()
     dev = None
     for i, pr in enumerate(problems):
         grid, coeffs, T = pr[0], pr[1], pr[2]
-        ap = bool(pr[3]) if len(pr) > 3 else False
+        ap = pr[3] if len(pr) > 3 else False
         arr[i] = _problem(grid, coeffs, T, ap, keep)
         dev = grid.device
     if not problems:
@@ -306,7 +328,7 @@ class Server:
         _check(_srv_create(ctypes.byref(self._h), int(device), int(hbm_budget_bytes), int(max_slots)))
         self._keep = {}
 
-    def submit(self, grid, coeffs, T: int, aperiodic_: bool = False) -> int:
+    def submit(self, grid, coeffs, T: int, aperiodic_=False) -> int:
         keep = []
         p = _problem(grid, coeffs, T, aperiodic_, keep)
         t = ctypes.c_uint64()

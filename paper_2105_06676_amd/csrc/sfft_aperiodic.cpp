@@ -88,6 +88,11 @@ struct Ap {
     int64_t su;
     int64_t maxell;      // largest entry time of any interior cell (LLONG_MAX: none)
     bool inert;          // no active face: the frame never influences the interior
+    // boundary condition, applied by the base case only (Sec. 4): 0 fixed frame
+    // values, 1 reflecting (frame = mirror image of the interior every step).  The
+    // FFT parts never depend on it: a cell they keep has a dependency cone that
+    // stays inside the interior, whatever the frame does.
+    int bc = 0;
 };
 
 constexpr int kWsSlot = -1;  // the spectrum workspace of a stream
@@ -320,6 +325,7 @@ void base_case(Ap& a, const void* src, void* dst, int64_t tau, hipStream_t st) {
         bp.sstride[k + sh] = a.sstride[k];
     }
     bp.steps = (int)tau;
+    bp.bc = a.bc;
     bp.src = src;
     bp.frame = a.grid;
     bp.dst = dst;
@@ -486,8 +492,10 @@ namespace {
 
 // Set up the solve state; resources (helper streams, events, scratch) are owned
 // by the caller's stream `st`.
-Ap make_ap(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, hipStream_t st) {
+Ap make_ap(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int bc,
+           hipStream_t st) {
     Ap a;
+    a.bc = bc;
     a.f64 = f64;
     a.d = d;
     a.r = r;
@@ -623,14 +631,14 @@ struct GraphKey {
     int dev;
     hipStream_t st;
     void* grid;
-    int f64, d, r;
+    int f64, d, r, bc;
     int64_t dims[3];
     int64_t T, cutoff;
     int col_max, no_fast;
     std::vector<double> c;
     bool operator<(const GraphKey& o) const {
-        return std::tie(dev, st, grid, f64, d, r, dims[0], dims[1], dims[2], T, cutoff, col_max, no_fast, c) <
-               std::tie(o.dev, o.st, o.grid, o.f64, o.d, o.r, o.dims[0], o.dims[1], o.dims[2], o.T, o.cutoff,
+        return std::tie(dev, st, grid, f64, d, r, bc, dims[0], dims[1], dims[2], T, cutoff, col_max, no_fast, c) <
+               std::tie(o.dev, o.st, o.grid, o.f64, o.d, o.r, o.bc, o.dims[0], o.dims[1], o.dims[2], o.T, o.cutoff,
                         o.col_max, o.no_fast, o.c);
     }
 };
@@ -654,8 +662,8 @@ void drop_graph(GraphEntry& e) {
 }  // namespace
 
 void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
-                     hipStream_t st) {
-    Ap a = make_ap(grid, f64, d, dims, coeffs, r, st);
+                     int bc, hipStream_t st) {
+    Ap a = make_ap(grid, f64, d, dims, coeffs, r, bc, st);
     if (a.inert || T <= a.cutoff)
         short_path(a, T);
     else
@@ -665,8 +673,8 @@ void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const dou
 // Device bytes the solve's buffers take when it runs in a region of its own
 // (solve_aperiodic_pooled), found on the host by the same bookkeeping with
 // nothing enqueued.
-size_t aperiodic_footprint(bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T) {
-    Ap a = make_ap((void*)(uintptr_t)4096, f64, d, dims, coeffs, r, (hipStream_t)(uintptr_t)0x10);
+size_t aperiodic_footprint(bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T, int bc) {
+    Ap a = make_ap((void*)(uintptr_t)4096, f64, d, dims, coeffs, r, bc, (hipStream_t)(uintptr_t)0x10);
     a.dry = true;
     if (T > 0) {
         if (a.inert || T <= a.cutoff)
@@ -680,8 +688,8 @@ size_t aperiodic_footprint(bool f64, int d, const int64_t* dims, const double* c
 // solve_aperiodic with every device buffer taken from [pool, pool + cap)
 // (at least aperiodic_footprint bytes).
 void solve_aperiodic_pooled(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
-                            int64_t T, hipStream_t st, void* pool, size_t cap) {
-    Ap a = make_ap(grid, f64, d, dims, coeffs, r, st);
+                            int64_t T, int bc, hipStream_t st, void* pool, size_t cap) {
+    Ap a = make_ap(grid, f64, d, dims, coeffs, r, bc, st);
     a.pool = (char*)pool;
     a.pool_cap = cap;
     if (a.inert || T <= a.cutoff)
@@ -695,8 +703,8 @@ void solve_aperiodic_pooled(void* grid, bool f64, int d, const int64_t* dims, co
 // graph and later identical calls replay it, which removes the per-launch and
 // per-event host cost of the several hundred launches of a deep recursion.
 void solve_aperiodic_cached(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
-                            int64_t T, hipStream_t st) {
-    Ap a = make_ap(grid, f64, d, dims, coeffs, r, st);
+                            int64_t T, int bc, hipStream_t st) {
+    Ap a = make_ap(grid, f64, d, dims, coeffs, r, bc, st);
     if (a.inert || T <= a.cutoff) {
         short_path(a, T);
         return;
@@ -713,6 +721,7 @@ void solve_aperiodic_cached(void* grid, bool f64, int d, const int64_t* dims, co
     key.f64 = f64;
     key.d = d;
     key.r = r;
+    key.bc = bc;
     for (int k = 0; k < 3; ++k) key.dims[k] = k < d ? dims[k] : 0;
     key.T = T;
     key.cutoff = a.cutoff;

@@ -17,7 +17,7 @@ const char* last_error_cstr();
 void profile_enable(bool on);
 std::string profile_json();
 void solve_aperiodic_cached(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
-                     hipStream_t st);
+                            int bc, hipStream_t st);
 void solve_periodic_noalloc(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
                             int64_t T, hipStream_t st);
 }  // namespace sfft
@@ -66,6 +66,14 @@ void validate(const void* ptr, int dtype, int ndim, const int64_t* dims, const d
 }  // namespace
 
 namespace sfft {
+
+void validate_bc(int bc, int ndim, const int64_t* dims, int radius) {
+    if (bc != SFFT_BC_FIXED && bc != SFFT_BC_REFLECT) throw Error(SFFT_EINVAL, "unknown boundary condition");
+    if (bc == SFFT_BC_REFLECT)
+        for (int a = 0; a < ndim; ++a)
+            if (dims[a] < radius)
+                throw Error(SFFT_EINVAL, "a reflecting boundary needs interior extents >= radius");
+}
 
 int guarded_call(const std::function<void()>& f) { return guarded(f); }
 
@@ -300,10 +308,16 @@ int stencil_fft_periodic_implicit(void* grid, sfft_dtype dtype, int ndim, const 
 
 int stencil_fft_aperiodic(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims, const double* coeffs,
                           int radius, int64_t T, void* stream) {
+    return stencil_fft_aperiodic_bc(grid, dtype, ndim, dims, coeffs, radius, T, SFFT_BC_FIXED, stream);
+}
+
+int stencil_fft_aperiodic_bc(void* grid, sfft_dtype dtype, int ndim, const int64_t* dims, const double* coeffs,
+                             int radius, int64_t T, int bc, void* stream) {
     return guarded([&] {
         validate(grid, dtype, ndim, dims, coeffs, radius, T);
+        validate_bc(bc, ndim, dims, radius);
         if (T == 0) return;
-        solve_aperiodic_cached(grid, dtype == SFFT_F64, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
+        solve_aperiodic_cached(grid, dtype == SFFT_F64, ndim, dims, coeffs, radius, T, bc, (hipStream_t)stream);
     });
 }
 

@@ -20,7 +20,8 @@ struct BaseStrip {
 };
 
 struct BaseParams {
-    int nstrip, steps, ncoef, pad_;
+    int nstrip, steps, ncoef;
+    int bc;                    // 0: fixed frame values; 1: reflecting (frame = mirror image of the interior)
     int64_t n[3];              // interior extents (padded to 3 axes)
     int64_t r3[3];             // frame width per axis (0 on unused axes)
     int64_t reach3[3];         // the stencil's largest offset along each axis

@@ -10,6 +10,14 @@
 // stale values; the stale margin grows by at most the reach per step and never
 // reaches the tile), and stores the tile.  Reads stay inside entry times
 // <= 2 * steps, where the recursion guarantees valid input.
+//
+// Boundary condition (Sec. 4 leaves it to the base case): with a fixed frame the
+// frame cells keep the values of the stored array; with a reflecting (zero-flux)
+// boundary every frame cell in LDS is, at the start and after every step, a copy
+// of its mirror image about the cell faces (interior cell r + k for frame cell
+// r - 1 - k along each axis it lies outside of).  The copy of a frame cell is
+// exactly as current as its mirror, which is nearer the tile than the frame cell
+// itself, so every value a kept cell reads is still current.
 #include <hip/hip_runtime.h>
 
 #include "sfft_base.h"
@@ -64,9 +72,10 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
         const bool fr = g0 < bp.r3[0] || g0 >= bp.n[0] + bp.r3[0] || g1 < bp.r3[1] || g1 >= bp.n[1] + bp.r3[1] ||
                         g2 < bp.r3[2] || g2 >= bp.n[2] + bp.r3[2];
         const int64_t gi = g0 * bp.sstride[0] + g1 * bp.sstride[1] + g2 * bp.sstride[2];
-        A[i] = fr ? frame[gi] : src[gi];
+        A[i] = fr ? (bp.bc ? R(0) : frame[gi]) : src[gi];
     }
-    // per-thread cells and the last step at which each is updated (-1: never).
+    // per-thread cells and the last step at which each is updated (-1: never;
+    // <= -2: a reflected frame cell copying LDS cell -2 - lim).
     // An interior cell whose whole neighbourhood is loaded is updated while it
     // can still reach the tile: a cell delta_a cells outside the tile along axis
     // a influences the tile's values after the last step only through steps
@@ -84,19 +93,34 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
             const int x0 = i / le0, rem = i - x0 * le0, x1 = rem / le1, x2 = rem - x1 * le1;
             const int64_t xs[3] = {x0, x1, x2};
             bool ok = true;
-            int64_t need = 0;
+            bool frame_cell = false, mirror_in = true;
+            int64_t need = 0, mli = 0;
             for (int a = 0; a < 3; ++a) {
                 const int64_t g = rlo[a] + xs[a];
-                if (g < bp.r3[a] || g >= bp.n[a] + bp.r3[a]) ok = false;             // frame cell: fixed
+                const int64_t lo = bp.r3[a], hi = bp.n[a] + bp.r3[a];
+                const int64_t gm = g < lo ? 2 * lo - 1 - g : (g >= hi ? 2 * hi - 1 - g : g);
+                mirror_in = mirror_in && gm >= rlo[a] && gm < rlo[a] + rext[a];
+                mli = mli * rext[a] + (gm - rlo[a]);
+                if (g < lo || g >= hi) { ok = false; frame_cell = true; }           // frame cell
                 if (xs[a] < bp.reach3[a] || xs[a] + bp.reach3[a] >= rext[a]) ok = false;  // neighbourhood not loaded
                 const int64_t t0 = org[a] + bp.r3[a], t1 = t0 + ext[a] - 1;
                 const int64_t delta = g < t0 ? t0 - g : (g > t1 ? g - t1 : 0);
                 if (delta > 0 && bp.reach3[a] > 0) need = max(need, (delta + bp.reach3[a] - 1) / bp.reach3[a]);
             }
             if (ok) lim[k] = bp.steps - 1 - (int)need;
+            if (bp.bc && frame_cell && mirror_in) lim[k] = -2 - (int)mli;
         }
     }
     __syncthreads();
+    // reflecting boundary: frame cells := their mirror images (interior cells,
+    // never written in this phase)
+    auto reflect = [&]() {
+#pragma unroll
+        for (int k = 0; k < MAXC; ++k)
+            if (lim[k] <= -2) A[idx[k]] = A[-2 - lim[k]];
+        __syncthreads();
+    };
+    if (bp.bc) reflect();
 
     for (int step = 0; step < bp.steps; ++step) {
         R nv[MAXC];
@@ -113,6 +137,7 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
         for (int k = 0; k < MAXC; ++k)
             if (step <= lim[k]) A[idx[k]] = nv[k];
         __syncthreads();
+        if (bp.bc) reflect();
     }
 
     // store the tile (every tile cell lies in the band dist <= wout)

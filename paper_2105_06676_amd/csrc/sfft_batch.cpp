@@ -17,6 +17,7 @@
 
 #include "sfft_general.h"
 #include "sfft_kernels.h"
+#include "sfft_mixed.h"
 #include "sfft_solvers.h"
 
 namespace sfft {
@@ -35,6 +36,8 @@ void validate_problem(const sfft_problem& p) {
     if (p.radius > (p.aperiodic ? kMaxR : kMaxGeneralR))
         throw Error(SFFT_EUNSUPPORTED, "radius " + std::to_string(p.radius) + " is not supported for this problem kind");
     if (p.T < 0) throw Error(SFFT_EINVAL, "T must be >= 0");
+    if (p.aperiodic < 0 || p.aperiodic > 2) throw Error(SFFT_EINVAL, "aperiodic must be 0, 1 or 2");
+    if (p.aperiodic) validate_bc(p.aperiodic - 1, p.ndim, p.dims, p.radius);
     if (!p.coeffs) throw Error(SFFT_EINVAL, "coeffs pointer is null");
     int nc = 1;
     for (int a = 0; a < p.ndim; ++a) nc *= 2 * p.radius + 1;
@@ -133,13 +136,18 @@ BatchProgram build_batch(std::vector<ProblemRun>& runs, const BatchMem& mem, con
     size_t item_off = sym_bytes;
     for (size_t k = 0; k < maxp; ++k) {
         // group pass k of every problem by kernel variant
-        std::map<std::tuple<int, int, int, int, int, int>, std::vector<int>> groups;
+        std::map<std::tuple<int, int, int, int, int, int, int, int>, std::vector<int>> groups;
         for (size_t i = 0; i < runs.size(); ++i) {
             if (k >= runs[i].plan->pd.size()) continue;
             const PassDesc& pd = runs[i].plan->pd[k];
             const bool f64 = runs[i].plan->s.f64;
-            auto key = pd.fast ? std::make_tuple(1, pd.kind, pd.mode, pd.fast_kind, pd.logL, (int)f64)
-                               : std::make_tuple(0, pd.kind, 0, 0, 0, (int)f64);
+            // one launch per kernel variant (for the mixed-radix kernels: points per
+            // thread and last-stage radix, and the workgroup size, since the tile
+            // code assumes W * P threads)
+            auto key = pd.mq ? std::make_tuple(2, pd.kind, pd.mode, pd.fast_kind, pd.mq,
+                                               mixed_radix_at(pd.mrad, pd.nst - 1), (int)f64, pd.mthreads)
+                       : pd.fast ? std::make_tuple(1, pd.kind, pd.mode, pd.fast_kind, pd.logL, 0, (int)f64, 0)
+                                 : std::make_tuple(0, pd.kind, 0, 0, 0, 0, (int)f64, 0);
             groups[key].push_back((int)i);
         }
         for (auto& g : groups) {
@@ -267,7 +275,7 @@ int stencil_fft_batch(const sfft_problem* probs, int n, void* stream) {
             if (batchable(p) || p.T == 0) continue;
             const bool f64 = p.dtype == SFFT_F64;
             if (p.aperiodic)
-                solve_aperiodic(p.grid, f64, p.ndim, p.dims, p.coeffs, p.radius, p.T, st);
+                solve_aperiodic(p.grid, f64, p.ndim, p.dims, p.coeffs, p.radius, p.T, p.aperiodic - 1, st);
             else if (p.radius > kMaxR)
                 solve_periodic_general(p.grid, f64, p.ndim, p.dims, p.coeffs, p.radius, p.T, st);
             else

@@ -21,6 +21,8 @@ struct ProblemRun {
 // Validation shared by every entry point; throws Error.  Periodic problems may
 // have any extent and radius up to kMaxGeneralR; aperiodic ones radius <= 2.
 void validate_problem(const sfft_problem& p);
+// Boundary condition of an aperiodic problem (SFFT_BC_*), checked against its extents.
+void validate_bc(int bc, int ndim, const int64_t* dims, int radius);
 // Periodic problems that run in batched launches (7-smooth extents, radius <= 2);
 // the others are solved one after another on the batch's stream.
 bool batchable(const sfft_problem& p);

@@ -16,6 +16,7 @@
 #include "sfft_device.h"
 #include "sfft_fast.h"
 #include "sfft_kernels.h"
+#include "sfft_mixed.h"
 
 namespace sfft {
 
@@ -519,12 +520,14 @@ static hipError_t launch_pass_t(const PassDesc& pd, const SymParams& sp, size_t 
 }
 
 hipError_t launch_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t lds, hipStream_t st) {
+    if (pd.mq) return launch_mixed_pass(pd, sp, f64, lds, st);
     if (pd.fast) return launch_fast_pass(pd, sp, f64, lds, st);
     return f64 ? launch_pass_t<double>(pd, sp, lds, st) : launch_pass_t<float>(pd, sp, lds, st);
 }
 
 hipError_t launch_pass_batch(const PassDesc& proto, const BatchItem* items, int n, const SymParams* syms,
                              int64_t tiles, bool f64, size_t lds, hipStream_t st) {
+    if (proto.mq) return launch_mixed_batch(proto, items, n, syms, tiles, f64, lds, st);
     if (proto.fast) return launch_fast_batch(proto, items, n, syms, tiles, f64, lds, st);
     const dim3 g((unsigned)tiles), b(f64 ? gen_threads<double>() : gen_threads<float>());
     if (proto.kind == PASS_ROW) {

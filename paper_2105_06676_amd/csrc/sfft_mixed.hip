@@ -1,0 +1,508 @@
+// Register mixed-radix pass kernels (gfx950) for lengths of the form
+// 2^a 5^b, 2^a 3^b and 5^b (5, 10, 12, 20 or 25 points per thread).
+//
+// A transform of L points is done by P = L/Q threads that each hold Q points
+// (Q a compile-time constant of the length's family, every stage radix dividing
+// it): thread q holds x[q + P i], i < Q, on entry and on exit (natural order).
+// The first Stockham stage takes its butterfly inputs straight from those
+// registers (butterfly q + P b of radix R reads x[q + P (b + t Q/R)]) and the last
+// one leaves its outputs there; every stage in between exchanges the points
+// through LDS once, with the stage twiddles read from the pass's table
+// exp(-2 pi i m / (L st_mul)).  The stage list is packed in PassDesc::mrad
+// (4 bits per stage), so the kernels index no array at run time; divisions by
+// the run-time, workgroup-uniform P, W and Ns go through the float reciprocal
+// of sfft_device.h.  The same tile code (loads, the real-data untangling, the
+// fused symbol step, keep rules, stores) as the power-of-two register kernels;
+// lengths outside these families run on the generic kernels.
+//
+// Kernels:
+//  k_mrow<R, KIND, Q>  rows: R2C first pass, C2R last pass, whole 1-D real solve
+//  k_mcol<R, MODE, Q>  strided axis: forward / inverse / fused middle pass
+#include <hip/hip_runtime.h>
+
+#include "sfft_device.h"
+#include "sfft_fast.h"
+#include "sfft_mixed.h"
+#include "sfft_symapply.h"
+
+namespace sfft {
+
+namespace {
+
+constexpr int kMRowThreads = 512;  // most threads of a mixed-radix row workgroup
+constexpr int kMColThreads = 256;  // ... and of a column workgroup
+
+struct MRowIdx {
+    int base;
+    __device__ __forceinline__ int operator()(int e) const { return base + e + (e >> 4); }
+};
+struct MColIdx {
+    int c, ws;
+    __device__ __forceinline__ int operator()(int e) const { return e * ws + c; }
+};
+
+// One Stockham stage of radix RAD on the Q points of each of the P threads of a
+// transform (NS = product of the radices already applied).  FIRST: the inputs
+// are the registers (NS = 1, no twiddles); otherwise they are read from LDS.
+// LAST: the outputs go to the registers in natural order; otherwise to LDS at
+// their self-sorting positions.  The flags are compile-time so that the point
+// registers are dead between the first and the last stage.
+template <typename R, int Q, int RAD, bool INV, bool FIRST, bool LAST, typename IDX>
+__device__ __forceinline__ void mstage(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, int P, int L, int NS,
+                                       const cx<R>* tab, int tmul) {
+    constexpr int NB = Q / RAD;
+    const int span = L / RAD;
+    cx<R> w[NB][RAD];
+    const UDiv dns = udiv((uint32_t)NS);
+    if (FIRST) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) w[b][t] = v[b + t * NB];
+    } else {
+        const int step = (L / (NS * RAD)) * tmul;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = q + P * b;
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) w[b][t] = lds[idx(j + t * span)];
+            uint32_t jq;
+            const int k = (int)udiv_qr((uint32_t)j, dns, &jq);
+            const cx<R> w1 = tab[k * step];
+            cx<R> wt = w1;
+#pragma unroll
+            for (int t = 1; t < RAD; ++t) {
+                w[b][t] = INV ? cmulc(w[b][t], wt) : cmul(w[b][t], wt);
+                if (t + 1 < RAD) wt = cmul(wt, w1);
+            }
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) dft<R, RAD, INV>(w[b]);
+    if (!LAST) {
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = q + P * b;
+            uint32_t jq;
+            const int k = (int)udiv_qr((uint32_t)j, dns, &jq);
+            const int d = (int)jq * NS * RAD + k;
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) lds[idx(d + t * NS)] = w[b][t];
+        }
+        __syncthreads();
+    } else {
+        // outputs y[q + P (b + t NB)] -> natural register order
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int t = 0; t < RAD; ++t) v[b + t * NB] = w[b][t];
+    }
+}
+
+template <typename R, int Q, bool INV, bool FIRST, bool LAST, typename IDX>
+__device__ __forceinline__ void mstage_rad(int rad, cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, int P, int L, int NS,
+                                           const cx<R>* tab, int tmul) {
+#define SFFT_MST(RAD)                                                                                      if constexpr (Q % RAD == 0) mstage<R, Q, RAD, INV, FIRST, LAST>(v, lds, idx, q, P, L, NS, tab, tmul);
+    switch (rad) {
+        case 2: SFFT_MST(2) break;
+        case 3: SFFT_MST(3) break;
+        case 4: SFFT_MST(4) break;
+        case 5: SFFT_MST(5) break;
+        default: SFFT_MST(7) break;
+    }
+#undef SFFT_MST
+}
+
+// The radix a family's first stage uses (its odd prime) and, for every family,
+// stage lists in the order odd primes, 4s, then one 2 (the planner's canonical
+// order): the first stage's radix is R0<Q>() and the last one's is a kernel
+// template parameter, so no stage that touches the point registers sits behind
+// a run-time switch (which would move the registers to scratch memory).
+template <int Q>
+constexpr int R0() { return Q % 5 == 0 ? 5 : (Q % 3 == 0 ? 3 : 7); }
+
+// Length-L transform of the Q points held by each of the P threads (stage
+// radices in pd.mrad, pd.nst >= 2 stages, the last of radix RL).
+template <typename R, int Q, int RL, bool INV, typename IDX>
+__device__ __forceinline__ void mfft(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, int P, const PassDesc& pd) {
+    const cx<R>* tab = (const cx<R>*)pd.st_tab;
+    const int L = pd.L, tmul = pd.st_mul, nst = pd.nst;
+    const uint64_t rads = (uint64_t)pd.mrad;
+    constexpr int RF = R0<Q>();
+    mstage<R, Q, RF, INV, true, false>(v, lds, idx, q, P, L, 1, tab, tmul);
+    int NS = RF;
+    for (int s = 1; s < nst - 1; ++s) {
+        const int rad = mixed_radix_at((int64_t)rads, s);
+        mstage_rad<R, Q, INV, false, false>(rad, v, lds, idx, q, P, L, NS, tab, tmul);
+        NS *= rad;
+    }
+    mstage<R, Q, RL, INV, false, true>(v, lds, idx, q, P, L, NS, tab, tmul);
+}
+
+// ---------------------------------------------------------------------------
+// Row passes
+// ---------------------------------------------------------------------------
+template <typename R, int KIND, int Q, int RL>
+__device__ __forceinline__ void mrow_tile(const PassDesc& pd, const SymParams& sp, uint32_t bid) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
+    const int L = pd.L;
+    const int P = L / Q;
+    const int NTR = pd.W;
+    const int LS = L + L / 16 + 2;
+    // the workgroup has exactly NTR * P threads
+    uint32_t rr_u;
+    const int q = (int)udiv_qr((uint32_t)threadIdx.x, udiv((uint32_t)P), &rr_u);
+    const int rr = (int)rr_u;
+    const int64_t row = (int64_t)bid * NTR + rr;
+    bool active = row < pd.outer;
+    const MRowIdx idx{rr * LS};
+    // exp(-2 pi i m / 2L) for the real-data untangling (the pass table has 2L entries)
+    const cx<R>* htab = (const cx<R>*)pd.st_tab;
+    cx<R> v[Q];
+
+    int64_t ii[3] = {0, 0, 0};
+    int64_t b = 0;
+    {
+        int64_t rem = active ? row : 0;
+#pragma unroll
+        for (int a = 1; a >= 0; --a) {
+            if (a <= pd.d - 2) {
+                const int64_t n = a == 1 ? pd.rdims[1] : pd.rdims[0];
+                const int64_t qq = rem / n;
+                ii[a] = rem - qq * n;
+                rem = qq;
+            }
+        }
+        b = rem;
+    }
+    if (KIND == ROW_C2R && active && pd.keep.enabled && !row_may_keep(pd.keep, keep_row(pd.keep, pd.d, b, ii), pd.d, b))
+        active = false;
+    auto row_base = [&](const RealView& rv) -> int64_t {
+        int64_t off = b * rv.boff;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if (a < pd.d - 1) {
+                if (ii[a] >= rv.ext[a]) return -1;
+                off += ii[a] * rv.stride[a];
+            }
+        }
+        return off;
+    };
+
+    // ---------------- load
+    if (KIND == ROW_R2C || KIND == ROW_MIDR) {
+        const R* src = (const R*)pd.rv.ptr;
+        const int64_t base = active ? row_base(pd.rv) : -1;
+        const int64_t sl = pick3(pd.rv.stride, pd.d - 1), el = pick3(pd.rv.ext, pd.d - 1);
+        const bool vec = base >= 0 && sl == 1 && el >= 2 * L && ((((uintptr_t)(src + base)) % (2 * sizeof(R))) == 0);
+        if (vec) {
+            const cx<R>* s2 = (const cx<R>*)(src + base) + q;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) v[i] = s2[P * i];
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int m = q + P * i;
+                cx<R> z = {R(0), R(0)};
+                if (base >= 0) {
+                    if (2 * m < el) z.x = src[base + (int64_t)(2 * m) * sl];
+                    if (2 * m + 1 < el) z.y = src[base + (int64_t)(2 * m + 1) * sl];
+                }
+                v[i] = z;
+            }
+        }
+    } else {
+        const cx<R>* src = (const cx<R>*)pd.buf + (active ? row : 0) * pd.ostride + q;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = active ? src[P * i] : cx<R>{R(0), R(0)};
+    }
+
+    cx<R> xl = {R(0), R(0)};  // X[L] of a half-spectrum row (held by q == 0)
+    if (KIND == ROW_C2R) {
+        if (q == 0) lds[idx(L)] = active ? ((const cx<R>*)pd.buf)[row * pd.ostride + L] : cx<R>{R(0), R(0)};
+    } else {
+        mfft<R, Q, RL, false>(v, lds, idx, q, P, pd);
+    }
+
+    if (KIND == ROW_R2C || KIND == ROW_MIDR) {
+        // untangle the half-length transform: X[k] from Z[k] and Z[L-k]
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < Q; ++i) lds[idx(q + P * i)] = v[i];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int k = q + P * i;
+            const cx<R> zk = v[i];
+            if (k == 0) {
+                v[i] = cx<R>{zk.x + zk.y, R(0)};
+                xl = cx<R>{zk.x - zk.y, R(0)};
+            } else {
+                const cx<R> zm = lds[idx(L - k)];
+                const cx<R> e = scale(zk + conj(zm), R(0.5));
+                const cx<R> o = scale(zk - conj(zm), R(0.5));
+                const cx<R> t = cmul(htab[k], o);
+                v[i] = cx<R>{e.x + t.y, e.y - t.x};
+            }
+        }
+        if (KIND == ROW_R2C) {
+            if (active) {
+                cx<R>* dst = (cx<R>*)pd.buf + row * pd.ostride + q;
+#pragma unroll
+                for (int i = 0; i < Q; ++i) dst[P * i] = v[i];
+                if (q == 0) dst[L] = xl;
+            }
+            return;
+        }
+        // 1-D middle: multiply X[k], k = 0..L, by lambda^T / n
+        const SymCol col = symbol_column_1d(sp);
+        apply_symbol<R, kMRowThreads, Q, kMGroup<Q>()>(v, lds, sp, col, (uint32_t)q, (uint32_t)P);
+        if (q == 0) {
+            const int64_t fl = L;
+            dcx s;
+            symbol_power_n<1>(sp, col, &fl, &s);
+            xl = cmul(xl, cx<R>{R(s.x), R(s.y)});
+        }
+    }
+
+    // tangle for the half-length inverse:
+    // Z'[k] = (X[k] + conj X[L-k]) + i conj(w^k) (X[k] - conj X[L-k]), w = exp(-2 pi i / 2L)
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) lds[idx(q + P * i)] = v[i];
+    if (KIND != ROW_C2R && q == 0) lds[idx(L)] = xl;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int k = q + P * i;
+        const cx<R> xk = v[i], xm = lds[idx(L - k)];
+        const cx<R> e = xk + conj(xm);
+        const cx<R> o = cmulc(xk - conj(xm), htab[k]);
+        v[i] = cx<R>{e.x - o.y, e.y + o.x};
+    }
+    __syncthreads();
+
+    mfft<R, Q, RL, true>(v, lds, idx, q, P, pd);
+
+    // ---------------- store: x[2m] = Re z[m], x[2m+1] = Im z[m]
+    if (!active) return;
+    R* out = (R*)pd.rvo.ptr;
+    const int64_t base = row_base(pd.rvo);
+    if (base < 0) return;
+    const int64_t sl = pick3(pd.rvo.stride, pd.d - 1), el = pick3(pd.rvo.ext, pd.d - 1);
+    const bool vec = !pd.keep.enabled && sl == 1 && el >= 2 * L &&
+                     ((((uintptr_t)(out + base)) % (2 * sizeof(R))) == 0);
+    if (vec) {
+        cx<R>* d2 = (cx<R>*)(out + base) + q;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d2[P * i] = v[i];
+        return;
+    }
+    const RowKeep rk = keep_row(pd.keep, pd.d, b, ii);
+    const bool interval = KIND == ROW_C2R && pd.keep.enabled && pd.keep.face_axis >= 0 && pd.keep.face_axis != pd.d - 1;
+    int64_t mlo = 0, mhi = -1;
+    if (interval) {
+        const int la = pd.d - 1;
+        const int64_t goff = pick3(pd.keep.gorg, la) + b * pick3(pd.keep.gbstep, la);
+        mlo = rk.dpre - 1 - goff;
+        mhi = pick3(pd.keep.gdim, la) - rk.dpre - goff;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int m = q + P * i;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int64_t mm = 2 * m + h;
+            if (mm >= el) continue;
+            if (interval) {
+                if (mm < mlo || mm > mhi) continue;
+            } else if (pd.keep.enabled && !keep_last(pd.keep, rk, pd.d, b, mm)) {
+                continue;
+            }
+            out[base + mm * sl] = h ? v[i].y : v[i].x;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column passes
+// ---------------------------------------------------------------------------
+template <typename R, int MODE, int Q, int RL>
+__device__ __forceinline__ void mcol_tile(const PassDesc& pd, const SymParams& sp, uint32_t bid) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
+    const int L = pd.L;
+    const int P = L / Q;
+    const int W = pd.W;
+    // the workgroup has exactly W * P threads
+    uint32_t q_u;
+    const int cl = (int)udiv_qr((uint32_t)threadIdx.x, udiv((uint32_t)W), &q_u);
+    const int q = (int)q_u;
+    uint32_t tile = bid;
+    if (pd.xcd_remap) {
+        const uint32_t per = (uint32_t)(pd.ntiles / 8);
+        if (tile < 8 * per) tile = (tile % 8) * per + tile / 8;
+    }
+    const uint32_t ti = (uint32_t)pd.tiles_inner;
+    const uint32_t o32 = tile / ti;
+    const int64_t o = o32;
+    const int64_t c = (int64_t)(tile - o32 * ti) * W + cl;
+    const bool valid = c < pd.inner &&
+                       (pd.cpitch == 0 || ((uint32_t)c % (uint32_t)pd.cpitch) < (uint32_t)pd.hcount);
+    const MColIdx idx{cl, W + 1};
+    const int64_t step = (int64_t)P * pd.kstride;
+    // (columns past the last valid one take no twiddle: their index would run past the table)
+    const uint32_t twj = (pd.tw && valid) ? (uint32_t)c / (uint32_t)pd.tw_div : 0;
+    const int qq = q;
+    cx<R> v[Q];
+
+    // ---------------- load
+    if (pd.in_real) {
+        const R* src = (const R*)pd.rv.ptr;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int64_t m = (int64_t)(qq + P * i) * pd.kstride + c;
+            v[i] = cx<R>{(valid && m < pd.rv.ext[0]) ? src[o * pd.rv.boff + m * pd.rv.stride[0]] : R(0), R(0)};
+        }
+    } else {
+        const cx<R>* src = (const cx<R>*)pd.buf + o * pd.ostride + (int64_t)qq * pd.kstride + (valid ? c : 0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = valid ? src[i * step] : cx<R>{R(0), R(0)};
+    }
+    if (MODE == MODE_INV && pd.tw) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = cmulc(v[i], step_twiddle<R>(pd, (int64_t)(qq + P * i) * twj));
+    }
+
+    if (MODE != MODE_INV) mfft<R, Q, RL, false>(v, lds, idx, qq, P, pd);
+
+    if (MODE == MODE_MID) {
+        const SymCol col = valid ? ((const SymCol*)sp.coltab)[c] : SymCol{};
+        const int64_t fp = pos_to_freq(sp, 0, (o % pd.q_mod) * L);
+        const int64_t M = sp.n[0] / L;
+        apply_symbol<R, kMColThreads, Q, kMGroup<Q>()>(v, lds, sp, col, (uint32_t)(fp + M * qq), (uint32_t)(M * P));
+        mfft<R, Q, RL, true>(v, lds, idx, qq, P, pd);
+    }
+    if (MODE == MODE_INV) mfft<R, Q, RL, true>(v, lds, idx, qq, P, pd);
+    if (MODE == MODE_FWD && pd.tw) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = cmul(v[i], step_twiddle<R>(pd, (int64_t)(qq + P * i) * twj));
+    }
+
+    // ---------------- store
+    if (!valid) return;
+    if (pd.out_real) {
+        R* dst = (R*)pd.rvo.ptr;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int64_t m = (int64_t)(qq + P * i) * pd.kstride + c;
+            if (m >= pd.rvo.ext[0]) continue;
+            if (pd.keep.enabled && !keep_last(pd.keep, RowKeep{INT64_MAX, -1}, 1, o, m)) continue;
+            dst[o * pd.rvo.boff + m * pd.rvo.stride[0]] = v[i].x;
+        }
+    } else {
+        cx<R>* dst = (cx<R>*)pd.buf + o * pd.ostride + (int64_t)qq * pd.kstride + c;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) dst[i * step] = v[i];
+    }
+}
+
+__device__ __forceinline__ int batch_find_m(const BatchItem* it, int n, uint32_t bid) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (it[mid].first <= (int64_t)bid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename R, int KIND, int Q, int RL>
+__global__ __launch_bounds__(kMRowThreads) void k_mrow(PassDesc pd, SymParams sp) {
+    mrow_tile<R, KIND, Q, RL>(pd, sp, blockIdx.x);
+}
+template <typename R, int KIND, int Q, int RL>
+__global__ __launch_bounds__(kMRowThreads) void k_mrow_b(const BatchItem* it, int n, const SymParams* sy) {
+    const int i = batch_find_m(it, n, blockIdx.x);
+    mrow_tile<R, KIND, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
+}
+template <typename R, int MODE, int Q, int RL>
+__global__ __launch_bounds__(kMColThreads) void k_mcol(PassDesc pd, SymParams sp) {
+    mcol_tile<R, MODE, Q, RL>(pd, sp, blockIdx.x);
+}
+template <typename R, int MODE, int Q, int RL>
+__global__ __launch_bounds__(kMColThreads) void k_mcol_b(const BatchItem* it, int n, const SymParams* sy) {
+    const int i = batch_find_m(it, n, blockIdx.x);
+    mcol_tile<R, MODE, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
+}
+
+struct MBatch {
+    const BatchItem* items;
+    int n;
+    const SymParams* syms;
+    int64_t tiles;
+};
+
+template <typename R, int Q, int RL>
+void launch_q(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st, const MBatch* ba) {
+    const dim3 g((unsigned)(ba ? ba->tiles : pd.ntiles)), b((unsigned)pd.mthreads);
+    if (pd.kind == PASS_ROW) {
+#define SFFT_MROW(K)                                                                               \
+    if (ba) hipLaunchKernelGGL((k_mrow_b<R, K, Q, RL>), g, b, lds, st, ba->items, ba->n, ba->syms);     \
+    else hipLaunchKernelGGL((k_mrow<R, K, Q, RL>), g, b, lds, st, pd, sp);
+        switch (pd.fast_kind) {
+            case ROW_R2C: SFFT_MROW(ROW_R2C) break;
+            case ROW_C2R: SFFT_MROW(ROW_C2R) break;
+            default: SFFT_MROW(ROW_MIDR) break;
+        }
+#undef SFFT_MROW
+    } else {
+#define SFFT_MCOL(M)                                                                               \
+    if (ba) hipLaunchKernelGGL((k_mcol_b<R, M, Q, RL>), g, b, lds, st, ba->items, ba->n, ba->syms);     \
+    else hipLaunchKernelGGL((k_mcol<R, M, Q, RL>), g, b, lds, st, pd, sp);
+        switch (pd.mode) {
+            case MODE_FWD: SFFT_MCOL(MODE_FWD) break;
+            case MODE_INV: SFFT_MCOL(MODE_INV) break;
+            default: SFFT_MCOL(MODE_MID) break;
+        }
+#undef SFFT_MCOL
+    }
+}
+
+template <typename R>
+hipError_t launch_m(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st, const MBatch* ba) {
+    if (pd.nst < 2) return hipErrorInvalidValue;
+    const int rl = mixed_radix_at(pd.mrad, pd.nst - 1);
+    // (Q, last radix) pairs the planner's canonical order produces
+    // (FP32 only for 20 and 25 points per thread: FP64 would hold one wave per SIMD)
+    if (pd.mq == 5 && rl == 5) launch_q<R, 5, 5>(pd, sp, lds, st, ba);
+    else if (pd.mq == 10 && rl == 2) launch_q<R, 10, 2>(pd, sp, lds, st, ba);
+    else if (pd.mq == 12 && rl == 4) launch_q<R, 12, 4>(pd, sp, lds, st, ba);
+    else if (pd.mq == 12 && rl == 2) launch_q<R, 12, 2>(pd, sp, lds, st, ba);
+    else if constexpr (sizeof(R) == 4) {
+        if (pd.mq == 20 && rl == 4) launch_q<R, 20, 4>(pd, sp, lds, st, ba);
+        else if (pd.mq == 20 && rl == 2) launch_q<R, 20, 2>(pd, sp, lds, st, ba);
+        else if (pd.mq == 25 && rl == 5) launch_q<R, 25, 5>(pd, sp, lds, st, ba);
+        else return hipErrorInvalidValue;
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_mixed_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t lds, hipStream_t st) {
+    return f64 ? launch_m<double>(pd, sp, lds, st, nullptr) : launch_m<float>(pd, sp, lds, st, nullptr);
+}
+
+hipError_t launch_mixed_batch(const PassDesc& proto, const BatchItem* items, int n, const SymParams* syms,
+                              int64_t tiles, bool f64, size_t lds, hipStream_t st) {
+    const MBatch ba{items, n, syms, tiles};
+    SymParams dummy;
+    return f64 ? launch_m<double>(proto, dummy, lds, st, &ba) : launch_m<float>(proto, dummy, lds, st, &ba);
+}
+
+}  // namespace sfft

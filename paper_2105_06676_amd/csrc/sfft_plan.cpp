@@ -13,6 +13,7 @@
 #include "sfft_plan.h"
 
 #include "sfft_fast.h"
+#include "sfft_mixed.h"
 
 #include <algorithm>
 #include <cstring>
@@ -46,6 +47,54 @@ static bool radix_list(int64_t L, int* out, int* nst) {
     return true;
 }
 
+static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+bool mixed_family(int64_t L, bool column, bool f64, int* Q, int64_t* packed, int* nst) {
+    if (tunables().no_fast || L < 2) return false;
+    int64_t n = L;
+    int e2 = 0, e3 = 0, e5 = 0, e7 = 0;
+    while (n % 2 == 0) { n /= 2; ++e2; }
+    while (n % 3 == 0) { n /= 3; ++e3; }
+    while (n % 5 == 0) { n /= 5; ++e5; }
+    while (n % 7 == 0) { n /= 7; ++e7; }
+    if (n != 1) return false;
+    std::vector<int> r;
+    int q = 0;
+    // Points per thread: rows (contiguous, any thread count coalesces) take the
+    // fewest (more waves per SIMD); columns take more so that a workgroup spans
+    // enough adjacent columns for full-width loads, within the register budget
+    // (FP64 points take twice the registers: 20 and 25 points would run one wave
+    // per SIMD).
+    if (e3 == 0 && e7 == 0 && e5 >= 1) {
+        if (!column || f64) q = e2 >= 1 ? 10 : 5;
+        else q = e2 >= 2 ? 20 : (e2 == 1 ? 10 : 25);
+        if (e2 == 0 && e5 < 2) return false;
+        for (int i = 0; i < e5; ++i) r.push_back(5);
+    } else if (e5 == 0 && e7 == 0 && e3 >= 1 && e2 >= 2) {
+        q = 12;
+        for (int i = 0; i < e3; ++i) r.push_back(3);
+    } else {
+        return false;
+    }
+    if (q % 4 == 0) {
+        for (int i = 0; i < e2 / 2; ++i) r.push_back(4);
+        if (e2 % 2) r.push_back(2);
+    } else {
+        for (int i = 0; i < e2; ++i) r.push_back(2);
+    }
+    const int64_t P = L / q;
+    if (P < 1 || P > (column ? 64 : 512) || r.size() < 2 || (int)r.size() * kMRadBits > 64) return false;
+    int64_t pk = 0;
+    for (size_t i = 0; i < r.size(); ++i) {
+        if (q % r[i]) return false;
+        pk |= (int64_t)r[i] << (kMRadBits * i);
+    }
+    *Q = q;
+    *packed = pk;
+    *nst = (int)r.size();
+    return true;
+}
+
 TuneDB& tune_db() {
     static TuneDB db;
     return db;
@@ -76,6 +125,19 @@ static bool split_axis(int64_t n, int64_t cap, std::vector<int64_t>* out, bool f
         }
     }
     if (n <= cap) { out->push_back(n); return true; }
+    // A power-of-two factor of at least kFastMinL points runs on the register
+    // kernels, several times faster than the mixed-radix ones: when n has one, the
+    // largest such factor up to cap leads (its level runs first, the rest of n in
+    // the next level) provided the rest also fits (8000 -> 64 x 125).
+    if (!is_pow2(n)) {
+        int64_t p2 = 1;
+        while (n % (p2 * 2) == 0 && p2 * 2 <= cap) p2 *= 2;
+        if (p2 >= kFastMinL && n / p2 <= cap) {
+            out->push_back(p2);
+            out->push_back(n / p2);
+            return true;
+        }
+    }
     int64_t best = 0, b0 = 0;
     for (int64_t s0 = 2; s0 <= cap && s0 < n; ++s0) {
         if (n % s0) continue;
@@ -104,7 +166,6 @@ static bool split_axis(int64_t n, int64_t cap, std::vector<int64_t>* out, bool f
     return true;
 }
 
-static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 static int ilog2(int64_t x) {
     int l = 0;
@@ -198,6 +259,31 @@ static PassPlan make_row(const Ctx& c, int64_t rows, int L, int rowtrans, int mo
         else
             pd.fast_kind = mode == MODE_FWD ? ROW_R2C : mode == MODE_INV ? ROW_C2R : ROW_MIDR;
     }
+    int mq = 0, mst = 0;
+    int64_t mrad = 0;
+    if (!fast_ok && allow_fast && rowtrans == RT_HALF && mixed_family(L, false, c.f64, &mq, &mrad, &mst)) {
+        // register mixed-radix rows: P = L / Q threads per row, NTR rows per workgroup
+        const int64_t P = L / mq;
+        const int64_t LS = L + L / 16 + 2;
+        int64_t ntr = std::max<int64_t>(1, 512 / P);
+        ntr = std::min<int64_t>(ntr, rows);
+        auto bytes = [&](int64_t w) {
+            return (size_t)std::max<int64_t>(w * LS, mode == MODE_MID ? 512 * (int64_t)mq : 0) * c.csz;
+        };
+        // at most ~48 KB of LDS per workgroup, so that three fit a compute unit
+        while (ntr > 1 && bytes(ntr) > 48 * 1024) --ntr;
+        if (bytes(ntr) <= 128 * 1024) {
+            pd.mq = mq;
+            pd.mrad = mrad;
+            pd.nst = mst;
+            for (int i = 0; i < mst; ++i) pd.radix[i] = mixed_radix_at(mrad, i);
+            pd.W = (int)ntr;
+            pd.mthreads = (int)(ntr * P);
+            pd.ntiles = (rows + ntr - 1) / ntr;
+            pd.fast_kind = mode == MODE_FWD ? ROW_R2C : mode == MODE_INV ? ROW_C2R : ROW_MIDR;
+            p.lds_bytes = bytes(ntr);
+        }
+    }
     return p;
 }
 
@@ -244,6 +330,27 @@ static PassPlan make_col(const Ctx& c, int64_t outer, int L, int64_t inner, int 
         p.lds_bytes = (size_t)L * (Wf + 1) * c.csz;
         p.has_fast = true;
         two_level(L, &p.f_lo, &p.f_hi);
+    } else {
+        int mq = 0, mst = 0;
+        int64_t mrad = 0;
+        if (mixed_family(L, true, c.f64, &mq, &mrad, &mst)) {
+            // register mixed-radix columns: P = L / Q threads per column, W columns
+            const int64_t P = L / mq;
+            const int64_t Wm = std::min<int64_t>(64, 256 / P);
+            const size_t bytes = (size_t)std::max<int64_t>((int64_t)L * (Wm + 1), 256 * (int64_t)mq) * c.csz;
+            if (Wm >= 4 && bytes <= 128 * 1024) {
+                pd.mq = mq;
+                pd.mrad = mrad;
+                pd.nst = mst;
+                for (int i = 0; i < mst; ++i) pd.radix[i] = mixed_radix_at(mrad, i);
+                pd.W = (int)Wm;
+                pd.mthreads = (int)(Wm * P);
+                pd.tiles_inner = (inner + Wm - 1) / Wm;
+                pd.ntiles = outer * pd.tiles_inner;
+                pd.xcd_remap = 1;
+                p.lds_bytes = bytes;
+            }
+        }
     }
     return p;
 }
@@ -531,7 +638,7 @@ std::string describe_schedule(const Schedule& s) {
         o << (i ? ", " : "") << "{\"name\": \"" << p.name << "\", \"kind\": \""
           << (pd.kind == PASS_ROW ? "row" : "col") << "\", \"mode\": \""
           << (pd.mode == MODE_FWD ? "fwd" : pd.mode == MODE_INV ? "inv" : "mid") << "\", \"L\": " << pd.L
-          << ", \"fast\": " << pd.fast << ", \"W\": " << pd.W << ", \"outer\": " << pd.outer << ", \"inner\": " << pd.inner
+          << ", \"fast\": " << pd.fast << ", \"mixed_q\": " << pd.mq << ", \"W\": " << pd.W << ", \"outer\": " << pd.outer << ", \"inner\": " << pd.inner
           << ", \"tiles\": " << pd.ntiles << ", \"twiddle\": " << pd.tw << ", \"lds_bytes\": " << p.lds_bytes
           << ", \"model_bytes\": " << p.model_bytes << ", \"radices\": [";
         for (int k = 0; k < pd.nst; ++k) o << (k ? ", " : "") << pd.radix[k];

@@ -177,8 +177,8 @@ void sfft_server::launch(int si, std::vector<Req>& reqs, std::vector<size_t>& of
         const bool f64 = r.p.dtype == SFFT_F64;
         void* pool = arena_base + offs[i];
         if (r.p.aperiodic)
-            solve_aperiodic_pooled(r.p.grid, f64, r.p.ndim, r.p.dims, r.coeffs.data(), r.p.radius, r.p.T, st, pool,
-                                   r.bytes);
+            solve_aperiodic_pooled(r.p.grid, f64, r.p.ndim, r.p.dims, r.coeffs.data(), r.p.radius, r.p.T,
+                                   r.p.aperiodic - 1, st, pool, r.bytes);
         else if (r.p.radius > kMaxR)
             solve_periodic_general(r.p.grid, f64, r.p.ndim, r.p.dims, r.coeffs.data(), r.p.radius, r.p.T, st, pool);
         else
@@ -434,7 +434,7 @@ int sfft_server_submit(sfft_server* s, const sfft_problem* p, uint64_t* ticket) 
         const bool f64 = p->dtype == SFFT_F64;
         if (p->aperiodic) {
             // every buffer of the solve, sized by its own bookkeeping on the host
-            r.bytes = aperiodic_footprint(f64, p->ndim, p->dims, r.coeffs.data(), p->radius, p->T);
+            r.bytes = aperiodic_footprint(f64, p->ndim, p->dims, r.coeffs.data(), p->radius, p->T, p->aperiodic - 1);
         } else if (!r.batched) {
             r.bytes = p->radius > kMaxR ? periodic_general_footprint(f64, p->ndim, p->dims, p->radius)
                                         : periodic_any_footprint(f64, p->ndim, p->dims);

@@ -22,11 +22,11 @@ size_t periodic_any_footprint(bool f64, int d, const int64_t* dims);
 void solve_periodic_general(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
                             int64_t T, hipStream_t st, void* pool = nullptr);
 size_t periodic_general_footprint(bool f64, int d, const int64_t* dims, int r);
-// StencilFFT-A with RecursiveBoundary.
+// StencilFFT-A with RecursiveBoundary; bc 0: fixed frame, 1: reflecting frame.
 void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T,
-                     hipStream_t st);
+                     int bc, hipStream_t st);
 void solve_aperiodic_pooled(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
-                            int64_t T, hipStream_t st, void* pool, size_t cap);
-size_t aperiodic_footprint(bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T);
+                            int64_t T, int bc, hipStream_t st, void* pool, size_t cap);
+size_t aperiodic_footprint(bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T, int bc);
 
 }  // namespace sfft

@@ -131,6 +131,11 @@ struct PassDesc {
     const void* f_hi;         // ... and 64 * (m div 64)
     const void* h_lo;         // exp(-2 pi i m / 2L) for the real-data untangling
     const void* h_hi;
+    // register mixed-radix kernels: points per thread (0: not used), threads per
+    // workgroup, stage radices packed 4 bits each (first stage lowest)
+    int mq;
+    int mthreads;
+    int64_t mrad;
 };
 
 // One problem's pass inside a batched launch: workgroups [first, first + pd.ntiles)
@@ -141,5 +146,22 @@ struct BatchItem {
     int sym;
     int pad_;
 };
+
+// The host fills these structs and the kernels read them (by value in kernel
+// arguments, or from device memory in batched launches), so both compilation
+// passes must agree on their layout; a change here is checked in both.
+static_assert(sizeof(void*) == 8 && sizeof(int64_t) == 8, "LP64 layout assumed");
+static_assert(sizeof(RealView) == 64 && alignof(RealView) == 8, "RealView layout");
+static_assert(sizeof(KeepRule) == 104 && alignof(KeepRule) == 8, "KeepRule layout");
+static_assert(sizeof(SymParams) == 1232 && alignof(SymParams) == 8, "SymParams layout");
+static_assert(sizeof(PassDesc) == 568 && alignof(PassDesc) == 8, "PassDesc layout");
+static_assert(sizeof(BatchItem) == 584 && alignof(BatchItem) == 8, "BatchItem layout");
+static_assert(__builtin_offsetof(PassDesc, rvo) == 280 && __builtin_offsetof(PassDesc, keep) == 344 &&
+              __builtin_offsetof(PassDesc, mq) == 552, "PassDesc field offsets");
+static_assert(__builtin_offsetof(SymParams, eph) == 192 && __builtin_offsetof(SymParams, c) == 232,
+              "SymParams field offsets");
+// one direct launch passes a PassDesc and a SymParams by value: well inside the
+// 4 KiB of kernel arguments
+static_assert(sizeof(PassDesc) + sizeof(SymParams) + 64 <= 4096, "kernel argument budget");
 
 }  // namespace sfft

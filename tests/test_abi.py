@@ -61,6 +61,16 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
     p = (ctypes.c_int64 * 2)(11, 8)
     assert ff(fake, 0, 1, 2, p, cp, 1, 5, None) == -2
     assert "prime factor" in s._binding._last_error().decode()
+    # boundary conditions of the aperiodic entry point
+    fb = lib.stencil_fft_aperiodic_bc
+    fb.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),
+                   ctypes.POINTER(ctypes.c_double), ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
+    assert fb(fake, 0, 2, dims, cp, 1, 5, 7, None) == -1
+    assert "boundary" in s._binding._last_error().decode()
+    c5 = np.ones((5, 5)) / 25
+    small = (ctypes.c_int64 * 2)(8, 1)
+    assert fb(fake, 0, 2, small, c5.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), 2, 5, 1, None) == -1
+    assert "reflecting" in s._binding._last_error().decode()
 
 
 def test_unknown_option_rejected():

@@ -1,0 +1,106 @@
+"""The register mixed-radix kernels (transform lengths 2^a 5^b, 2^a 3^b, 5^b held
+10, 12, 20 or 25 points per thread) against the FP64 loop oracle: every family,
+rows (real-to-complex, complex-to-real, the whole 1-D solve) and strided axes
+(forward, inverse, fused middle pass, split twiddles), every mode visible (T = 1
+with an asymmetric stencil) and long damped runs; batched launches that mix these
+kernels with the other families; the pass schedule uses them where expected."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+from gpu_util import TOL, assert_close, gpu_periodic, rounded_input, to_dev
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [
+    (2000, 1000),     # rows 500 = 4 * 125; columns 2000 = 16 x 125
+    (250, 160),       # rows 80 = 16 * 5 (FP64: 10 points); columns 250 = 2 * 125
+    (96, 768),        # rows 384 = 2^7 * 3 (12 points); columns 96 = 2^5 * 3
+    (75, 50),         # columns 75 = 3 * 25 (generic), rows 25 = 5^2
+    (20, 40, 100),    # 3-D: rows 50, columns 40 and 20
+    (640,),           # 1-D whole solve, L = 320 = 2^6 * 5
+    (1536,),          # 1-D whole solve, L = 768 = 2^8 * 3
+    (8000, 64),       # the paper's 8000: columns 8000 = 64 x 125
+]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_mixed_radix_full_spectrum(shape, dtype):
+    c = wl.box_random_coeffs(900 + len(shape), len(shape), 1)
+    a0 = wl.uniform(900 + shape[0], "grid", int(np.prod(shape))).reshape(shape)
+    print(f"mixed radix T=1: {shape} {dtype}", flush=True)
+    ref = oracle.periodic(rounded_input(a0, dtype), c, 1)
+    assert_close(gpu_periodic(a0, c, 1, dtype), ref, TOL[dtype], (shape, dtype))
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape", [(2000, 1000), (96, 768), (20, 40, 100), (640,)])
+def test_mixed_radix_long_damped(shape, dtype):
+    rng = np.random.default_rng(31)
+    c = np.abs(rng.uniform(size=(3,) * len(shape)))
+    c = 0.97 * c / c.sum()
+    a0 = wl.uniform(31, "grid", int(np.prod(shape))).reshape(shape)
+    T = 120
+    ref = oracle.periodic(rounded_input(a0, dtype), c, T)
+    assert_close(gpu_periodic(a0, c, T, dtype), ref, TOL[dtype], (shape, dtype))
+
+
+def test_mixed_radix_kernels_are_planned():
+    import paper_2105_06676_amd as sfft
+    d = sfft.plan_describe((2000, 1000), "f32")
+    mixed = [p for p in d["passes"] if p.get("mixed_q")]
+    assert len(mixed) >= 3, d["passes"]
+    d = sfft.plan_describe((2000, 1000), "f64")
+    assert any(p.get("mixed_q") == 10 for p in d["passes"]), d["passes"]
+
+
+def test_batch_with_mixed_radix_members_equals_alone():
+    import torch
+    import paper_2105_06676_amd as sfft
+    probs = []
+    for k, (shape, dt) in enumerate([((2000, 1000), "f32"), ((250, 160), "f64"), ((96, 768), "f32"),
+                                     ((250, 160), "f32"), ((1000, 640), "f32"), ((640,), "f64")]):
+        c = wl.box_random_coeffs(950 + k, len(shape), 1 + (k % 2))
+        a = wl.uniform(950 + k, "grid", int(np.prod(shape))).reshape(shape)
+        probs.append((a, c, 37 + k, dt))
+    alone = []
+    for a, c, T, dt in probs:
+        g = to_dev(a, dt)
+        sfft.periodic(g, c, T)
+        alone.append(g)
+    grids = [to_dev(a, dt) for a, c, T, dt in probs]
+    sfft.batch([(g, c, T) for g, (a, c, T, dt) in zip(grids, probs)])
+    torch.cuda.synchronize()
+    for g, al in zip(grids, alone):
+        assert torch.equal(g, al)
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_batch_groups_mixed_members_by_last_radix(dt):
+    """Members with the same points per thread but different last-stage radices
+    (e.g. 96- and 48-point axes of the 12-point family) run in separate launches
+    and each equals its solve alone."""
+    import torch
+    import paper_2105_06676_amd as sfft
+    shapes = [(192, 96), (96, 192), (96, 48), (48, 96), (384,), (192,), (1536, 40)]
+    probs = []
+    for k, shape in enumerate(shapes):
+        c = wl.box_random_coeffs(970 + k, len(shape), 1)
+        a = wl.uniform(970 + k, "grid", int(np.prod(shape))).reshape(shape)
+        probs.append((a, c, 11 + k))
+    alone = []
+    for a, c, T in probs:
+        g = to_dev(a, dt)
+        sfft.periodic(g, c, T)
+        alone.append(g)
+    grids = [to_dev(a, dt) for a, c, T in probs]
+    sfft.batch([(g, c, T) for g, (a, c, T) in zip(grids, probs)])
+    torch.cuda.synchronize()
+    for g, al, (a, c, T) in zip(grids, alone, probs):
+        assert torch.equal(g, al), a.shape
+    # and against the oracle
+    for g, (a, c, T) in zip(grids, probs):
+        ref = oracle.periodic(rounded_input(a, dt), c, T)
+        assert_close(g.cpu().numpy().astype(np.float64), ref, TOL[dt], a.shape)

@@ -225,6 +225,19 @@ def config(name: str) -> Workload:
                         dtypes=("f32", "f64"),
                         notes="2-D periodic 5-point Jacobi on a 7-smooth, non-power-of-two torus "
                               "(6300 = 2^2 3^2 5^2 7, 6720 = 2^6 3 5 7; mixed-radix transforms)")
+    if name == "jacobi2d_8000_smooth":
+        return Workload("jacobi2d_8000_smooth", 2, (8000, 8000), 1, 100000, jacobi5_coeffs(), 10, "uniform",
+                        dtypes=("f32", "f64"),
+                        notes="2-D periodic 5-point Jacobi at the paper's 2-D size and step count "
+                              "(8000 = 2^6 5^3: mixed-radix transforms)")
+    if name == "heat3d_800_smooth":
+        c = np.zeros((3, 3, 3), dtype=np.float64)
+        c[1, 1, 1] = 0.4
+        c[0, 1, 1] = c[2, 1, 1] = c[1, 0, 1] = c[1, 2, 1] = c[1, 1, 0] = c[1, 1, 2] = 0.1
+        return Workload("heat3d_800_smooth", 3, (800, 800, 800), 1, 10000, c, 11, "uniform",
+                        dtypes=("f32",),
+                        notes="3-D periodic 7-point heat at the paper's 3-D size and step count "
+                              "(800 = 2^5 5^2: mixed-radix transforms)")
     if name == "jacobi2d_8191_prime":
         return Workload("jacobi2d_8191_prime", 2, (8191, 8191), 1, 4096, jacobi5_coeffs(), 8, "uniform",
                         dtypes=("f32", "f64"),
@@ -333,12 +346,12 @@ class Request:
 
 
 def serving_mix(count: int = 10000, seed: int = 5, rate_per_s: float = 1000.0,
-                log2_cells=(10.0, 24.0), max_T: float = 1e5) -> list:
+                log2_cells=(10.0, 24.0), max_T: float = 1e5, smooth: bool = True) -> list:
     """Requests of the serving mix: d ~ U{1,2,3}; log2(N) ~ U[10, 24]; extents
     N^(1/d) * 2^delta_i with sum(delta) = 0, delta ~ U[-1/2, 1/2], each rounded to the
-    nearest 7-smooth integer; r ~ U{1,2}; full box weights normalised and snapped;
-    T = round(10^u), u ~ U[0, log10(max_T)]; dtype f32/f64 with probability 1/2;
-    Poisson arrivals at ``rate_per_s``."""
+    nearest 7-smooth integer (smooth=True) or to the nearest integer; r ~ U{1,2};
+    full box weights normalised and snapped; T = round(10^u), u ~ U[0, log10(max_T)];
+    dtype f32/f64 with probability 1/2; Poisson arrivals at ``rate_per_s``."""
     per = 16
     u = uniform(seed, "mix", per * count).reshape(count, per)
     reqs = []
@@ -351,7 +364,8 @@ def serving_mix(count: int = 10000, seed: int = 5, rate_per_s: float = 1000.0,
         delta = row[3:3 + d] - 0.5
         delta = delta - delta.mean() if d > 1 else np.zeros(1)
         base = 2.0 ** (lg / d)
-        dims = tuple(nearest_7smooth(base * 2.0 ** float(dl)) for dl in delta)
+        dims = tuple(nearest_7smooth(base * 2.0 ** float(dl)) if smooth else max(1, int(round(base * 2.0 ** float(dl))))
+                     for dl in delta)
         r = 1 + int(row[6] * 2)
         T = max(1, int(round(10.0 ** (row[7] * math.log10(max_T)))))
         dtype = "f32" if row[8] < 0.5 else "f64"
