@@ -300,6 +300,10 @@ void sfft_server_destroy(sfft_server* s);
  *                       identical call (same grid address, shape, coefficients,
  *                       T, stream and tunables) into a graph and replays it on
  *                       later identical calls; 0: always enqueue directly.
+ *   "mixed_row_q"       most points per thread of the register mixed-radix
+ *   "mixed_col_q"       kernels on row / strided-axis passes (5, 10, 12, 20
+ *                       or 25; 0 = default: the most the register budget
+ *                       allows for the length's family and dtype).
  * Returns SFFT_EINVAL for an unknown name or an out-of-range value.
  */
 int stencil_fft_set_option(const char* name, int64_t value);

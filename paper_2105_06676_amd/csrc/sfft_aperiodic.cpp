@@ -634,12 +634,13 @@ struct GraphKey {
     int f64, d, r, bc;
     int64_t dims[3];
     int64_t T, cutoff;
-    int col_max, no_fast;
+    int col_max, no_fast, mrq, mcq;
     std::vector<double> c;
     bool operator<(const GraphKey& o) const {
-        return std::tie(dev, st, grid, f64, d, r, bc, dims[0], dims[1], dims[2], T, cutoff, col_max, no_fast, c) <
+        return std::tie(dev, st, grid, f64, d, r, bc, dims[0], dims[1], dims[2], T, cutoff, col_max, no_fast, mrq,
+                        mcq, c) <
                std::tie(o.dev, o.st, o.grid, o.f64, o.d, o.r, o.bc, o.dims[0], o.dims[1], o.dims[2], o.T, o.cutoff,
-                        o.col_max, o.no_fast, o.c);
+                        o.col_max, o.no_fast, o.mrq, o.mcq, o.c);
     }
 };
 struct GraphEntry {
@@ -727,6 +728,8 @@ void solve_aperiodic_cached(void* grid, bool f64, int d, const int64_t* dims, co
     key.cutoff = a.cutoff;
     key.col_max = tunables().col_max;
     key.no_fast = tunables().no_fast;
+    key.mrq = tunables().mixed_row_q;
+    key.mcq = tunables().mixed_col_q;
     int nc = 1;
     for (int k = 0; k < d; ++k) nc *= 2 * r + 1;
     key.c.assign(coeffs, coeffs + nc);

@@ -359,6 +359,10 @@ int stencil_fft_set_option(const char* name, int64_t value) {
         } else if (n == "aperiodic_graphs") {
             if (value != 0 && value != 1) throw Error(SFFT_EINVAL, "aperiodic_graphs must be 0 or 1");
             tunables().aperiodic_graphs = (int)value;
+        } else if (n == "mixed_row_q" || n == "mixed_col_q") {
+            if (value != 0 && value != 5 && value != 10 && value != 12 && value != 20 && value != 25)
+                throw Error(SFFT_EINVAL, n + " must be 0, 5, 10, 12, 20 or 25");
+            (n == "mixed_row_q" ? tunables().mixed_row_q : tunables().mixed_col_q) = (int)value;
         } else if (n == "aperiodic_cutoff") {
             if (value < 0 || value > (1 << 20)) throw Error(SFFT_EINVAL, "aperiodic_cutoff out of range");
             tunables().aperiodic_cutoff = (int)value;

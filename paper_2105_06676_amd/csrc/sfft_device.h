@@ -67,6 +67,63 @@ struct RootTab<7> {
                                     -0.4338837391175581, -0.9749279121818236, -0.7818314824680298};
 };
 
+template <>
+struct RootTab<6> {
+    static constexpr double c[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
+    static constexpr double s[6] = {0.0, 0.8660254037844386, 0.8660254037844386, 0.0, -0.8660254037844386,
+                                    -0.8660254037844386};
+};
+template <>
+struct RootTab<10> {
+    static constexpr double c[10] = {1.0, 0.8090169943749475, 0.30901699437494745, -0.30901699437494745,
+                                     -0.8090169943749475, -1.0, -0.8090169943749475, -0.30901699437494745,
+                                     0.30901699437494745, 0.8090169943749475};
+    static constexpr double s[10] = {0.0, 0.5877852522924731, 0.9510565162951535, 0.9510565162951535,
+                                     0.5877852522924731, 0.0, -0.5877852522924731, -0.9510565162951535,
+                                     -0.9510565162951535, -0.5877852522924731};
+};
+template <>
+struct RootTab<12> {
+    static constexpr double c[12] = {1.0, 0.8660254037844386, 0.5, 0.0, -0.5, -0.8660254037844386,
+                                     -1.0, -0.8660254037844386, -0.5, 0.0, 0.5, 0.8660254037844386};
+    static constexpr double s[12] = {0.0, 0.5, 0.8660254037844386, 1.0, 0.8660254037844386, 0.5,
+                                     0.0, -0.5, -0.8660254037844386, -1.0, -0.8660254037844386, -0.5};
+};
+template <>
+struct RootTab<20> {
+    static constexpr double c[20] = {1.0, 0.9510565162951535, 0.8090169943749475, 0.5877852522924731,
+                                     0.30901699437494745, 0.0, -0.30901699437494745, -0.5877852522924731,
+                                     -0.8090169943749475, -0.9510565162951535, -1.0, -0.9510565162951535,
+                                     -0.8090169943749475, -0.5877852522924731, -0.30901699437494745, 0.0,
+                                     0.30901699437494745, 0.5877852522924731, 0.8090169943749475,
+                                     0.9510565162951535};
+    static constexpr double s[20] = {0.0, 0.30901699437494745, 0.5877852522924731, 0.8090169943749475,
+                                     0.9510565162951535, 1.0, 0.9510565162951535, 0.8090169943749475,
+                                     0.5877852522924731, 0.30901699437494745, 0.0, -0.30901699437494745,
+                                     -0.5877852522924731, -0.8090169943749475, -0.9510565162951535, -1.0,
+                                     -0.9510565162951535, -0.8090169943749475, -0.5877852522924731,
+                                     -0.30901699437494745};
+};
+template <>
+struct RootTab<25> {
+    static constexpr double c[25] = {1.0, 0.9685831611286311, 0.8763066800438636, 0.7289686274214116,
+                                     0.5358267949789967, 0.30901699437494745, 0.06279051952931337,
+                                     -0.18738131458572463, -0.42577929156507266, -0.6374239897486897,
+                                     -0.8090169943749475, -0.9297764858882515, -0.9921147013144779,
+                                     -0.9921147013144779, -0.9297764858882515, -0.8090169943749475,
+                                     -0.6374239897486897, -0.42577929156507266, -0.18738131458572463,
+                                     0.06279051952931337, 0.30901699437494745, 0.5358267949789967,
+                                     0.7289686274214116, 0.8763066800438636, 0.9685831611286311};
+    static constexpr double s[25] = {0.0, 0.2486898871648548, 0.48175367410171527, 0.6845471059286887,
+                                     0.8443279255020151, 0.9510565162951535, 0.9980267284282716,
+                                     0.9822872507286887, 0.9048270524660196, 0.7705132427757893,
+                                     0.5877852522924731, 0.368124552684678, 0.12533323356430426,
+                                     -0.12533323356430426, -0.368124552684678, -0.5877852522924731,
+                                     -0.7705132427757893, -0.9048270524660196, -0.9822872507286887,
+                                     -0.9980267284282716, -0.9510565162951535, -0.8443279255020151,
+                                     -0.6845471059286887, -0.48175367410171527, -0.2486898871648548};
+};
+
 template <typename R, bool INV>
 __device__ __forceinline__ void dft2(cx<R>* v) {
     cx<R> a = v[0], b = v[1];
@@ -139,11 +196,64 @@ __device__ __forceinline__ void dft_odd(cx<R>* v) {
     for (int k = 0; k < RAD; ++k) v[k] = out[k];
 }
 
+// a * exp(-+2 pi i m / N) for an m that is a constant once the caller's loops
+// are unrolled (quarter turns exactly, the rest from the root table).
+template <typename R, int N, bool INV>
+__device__ __forceinline__ cx<R> twiddle_n(cx<R> a, int m) {
+    m %= N;
+    if (m == 0) return a;
+    if ((4 * m) % N == 0) {
+        const int qt = 4 * m / N;
+        if (qt == 1) return rot90<R, INV>(a);
+        if (qt == 2) return cx<R>{-a.x, -a.y};
+        return rot90<R, !INV>(a);
+    }
+    const R c = R(RootTab<N>::c[m]), sn = R(RootTab<N>::s[m]);
+    // forward: a (c - i s); inverse: a (c + i s)
+    return INV ? cx<R>{fma(-a.y, sn, a.x * c), fma(a.x, sn, a.y * c)}
+               : cx<R>{fma(a.y, sn, a.x * c), fma(-a.x, sn, a.y * c)};
+}
+
+template <typename R, int RAD, bool INV>
+__device__ __forceinline__ void dft(cx<R>* v);
+
+// Composite radix N = A B (Cooley-Tukey inside the registers): with n = B n1 + n2
+// and k = k1 + A k2, X[k] = sum_n2 W_B^(n2 k2) W_N^(n2 k1) sum_n1 x[B n1 + n2] W_A^(n1 k1):
+// B transforms of length A, the twiddles W_N^(n2 k1), then A transforms of length B.
+template <typename R, int A, int B, bool INV>
+__device__ __forceinline__ void dft_ab(cx<R>* v) {
+    constexpr int N = A * B;
+    cx<R> y[B][A];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) y[n2][n1] = v[B * n1 + n2];
+        dft<R, A, INV>(y[n2]);
+#pragma unroll
+        for (int k1 = 1; k1 < A; ++k1)
+            if (n2 > 0) y[n2][k1] = twiddle_n<R, N, INV>(y[n2][k1], n2 * k1);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+        cx<R> z[B];
+#pragma unroll
+        for (int n2 = 0; n2 < B; ++n2) z[n2] = y[n2][k1];
+        dft<R, B, INV>(z);
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = z[k2];
+    }
+}
+
 template <typename R, int RAD, bool INV>
 __device__ __forceinline__ void dft(cx<R>* v) {
     if constexpr (RAD == 2) dft2<R, INV>(v);
     else if constexpr (RAD == 4) dft4<R, INV>(v[0], v[1], v[2], v[3]);
     else if constexpr (RAD == 8) dft8<R, INV>(v);
+    else if constexpr (RAD == 6) dft_ab<R, 3, 2, INV>(v);
+    else if constexpr (RAD == 10) dft_ab<R, 5, 2, INV>(v);
+    else if constexpr (RAD == 12) dft_ab<R, 4, 3, INV>(v);
+    else if constexpr (RAD == 20) dft_ab<R, 4, 5, INV>(v);
+    else if constexpr (RAD == 25) dft_ab<R, 5, 5, INV>(v);
     else dft_odd<R, RAD, INV>(v);
 }
 

@@ -1,5 +1,6 @@
 // Register mixed-radix pass kernels (sfft_mixed.hip): lengths 2^a 5^b, 2^a 3^b
-// and 5^b held Q points per thread (Q of the length's family).
+// and 5^b held Q points per thread (Q of the length's family), radix-Q stages
+// first and last.
 #pragma once
 
 #include <hip/hip_runtime.h>

@@ -4,20 +4,23 @@
 // A transform of L points is done by P = L/Q threads that each hold Q points
 // (Q a compile-time constant of the length's family, every stage radix dividing
 // it): thread q holds x[q + P i], i < Q, on entry and on exit (natural order).
-// The first Stockham stage takes its butterfly inputs straight from those
-// registers (butterfly q + P b of radix R reads x[q + P (b + t Q/R)]) and the last
-// one leaves its outputs there; every stage in between exchanges the points
-// through LDS once, with the stage twiddles read from the pass's table
-// exp(-2 pi i m / (L st_mul)).  The stage list is packed in PassDesc::mrad
-// (4 bits per stage), so the kernels index no array at run time; divisions by
-// the run-time, workgroup-uniform P, W and Ns go through the float reciprocal
-// of sfft_device.h.  The same tile code (loads, the real-data untangling, the
-// fused symbol step, keep rules, stores) as the power-of-two register kernels;
-// lengths outside these families run on the generic kernels.
+// The first Stockham stage has radix Q: a thread's Q registers are one butterfly,
+// computed as a composite in-register DFT (Q = A B: B transforms of length A, the
+// constant twiddles, A transforms of length B).  The last stage leaves its
+// outputs in the registers; every stage in between exchanges the points through
+// LDS once, with the stage twiddles read from the pass's table
+// exp(-2 pi i m / (L st_mul)).  Most of a length is covered by radix-Q stages, so
+// a transform takes few LDS exchanges and barriers.  The stage list is packed in
+// PassDesc::mrad (5 bits per stage), so the kernels index no array at run time;
+// divisions by the run-time, workgroup-uniform P, W and Ns go through the float
+// reciprocal of sfft_device.h.  The same tile code (loads, the real-data
+// untangling, the fused symbol step, keep rules, stores) as the power-of-two
+// register kernels; lengths outside these families run on the generic kernels.
 //
 // Kernels:
-//  k_mrow<R, KIND, Q>  rows: R2C first pass, C2R last pass, whole 1-D real solve
-//  k_mcol<R, MODE, Q>  strided axis: forward / inverse / fused middle pass
+//  k_mrow<R, KIND, Q, RL>  rows: R2C first pass, C2R last pass, whole 1-D real solve
+//  k_mcol<R, MODE, Q, RL>  strided axis: forward / inverse / fused middle pass
+// (RL: radix of the last stage)
 #include <hip/hip_runtime.h>
 
 #include "sfft_device.h"
@@ -69,11 +72,34 @@ __device__ __forceinline__ void mstage(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q
             uint32_t jq;
             const int k = (int)udiv_qr((uint32_t)j, dns, &jq);
             const cx<R> w1 = tab[k * step];
-            cx<R> wt = w1;
+            if constexpr (RAD <= 5) {
+                cx<R> wt = w1;
 #pragma unroll
-            for (int t = 1; t < RAD; ++t) {
-                w[b][t] = INV ? cmulc(w[b][t], wt) : cmul(w[b][t], wt);
-                if (t + 1 < RAD) wt = cmul(wt, w1);
+                for (int t = 1; t < RAD; ++t) {
+                    w[b][t] = INV ? cmulc(w[b][t], wt) : cmul(w[b][t], wt);
+                    if (t + 1 < RAD) wt = cmul(wt, w1);
+                }
+            } else {
+                // w1^t for t = a BS + c as (w1^BS)^a w1^c, both factors by short
+                // product chains from two table entries (a few roundings, not RAD)
+                constexpr int BS = RAD % 5 == 0 ? 5 : (RAD % 4 == 0 ? 4 : 3);
+                const cx<R> wb = tab[k * BS * step];
+                cx<R> lo[BS];
+                lo[0] = cx<R>{R(1), R(0)};
+                lo[1] = w1;
+#pragma unroll
+                for (int c = 2; c < BS; ++c) lo[c] = cmul(lo[c - 1], w1);
+                cx<R> hi = wb;
+#pragma unroll
+                for (int a = 0; a < RAD / BS; ++a) {
+#pragma unroll
+                    for (int c = 0; c < BS; ++c) {
+                        if (a == 0 && c == 0) continue;
+                        const cx<R> wt = a == 0 ? lo[c] : (c == 0 ? hi : cmul(hi, lo[c]));
+                        w[b][a * BS + c] = INV ? cmulc(w[b][a * BS + c], wt) : cmul(w[b][a * BS + c], wt);
+                    }
+                    if (a > 0 && a + 1 < RAD / BS) hi = cmul(hi, wb);
+                }
             }
         }
     }
@@ -109,29 +135,32 @@ __device__ __forceinline__ void mstage_rad(int rad, cx<R> (&v)[Q], cx<R>* lds, I
         case 3: SFFT_MST(3) break;
         case 4: SFFT_MST(4) break;
         case 5: SFFT_MST(5) break;
-        default: SFFT_MST(7) break;
+        case 6: SFFT_MST(6) break;
+        case 10: SFFT_MST(10) break;
+        case 12: SFFT_MST(12) break;
+        case 20: SFFT_MST(20) break;
+        default: SFFT_MST(25) break;
     }
 #undef SFFT_MST
 }
 
-// The radix a family's first stage uses (its odd prime) and, for every family,
-// stage lists in the order odd primes, 4s, then one 2 (the planner's canonical
-// order): the first stage's radix is R0<Q>() and the last one's is a kernel
-// template parameter, so no stage that touches the point registers sits behind
-// a run-time switch (which would move the registers to scratch memory).
-template <int Q>
-constexpr int R0() { return Q % 5 == 0 ? 5 : (Q % 3 == 0 ? 3 : 7); }
+// Stage lists (the planner's canonical order): the first stage has radix Q (a
+// thread's Q registers form one butterfly, computed as a composite in-register
+// DFT), then the middle stages, then a last stage of radix RL (Q again when the
+// length holds two factors Q).  The first and last radices are compile-time, so
+// no stage that touches the point registers sits behind a run-time switch
+// (which would move the registers to scratch memory); radix-Q stages keep the
+// number of LDS exchanges (and workgroup barriers) per transform small.
 
 // Length-L transform of the Q points held by each of the P threads (stage
-// radices in pd.mrad, pd.nst >= 2 stages, the last of radix RL).
+// radices in pd.mrad, pd.nst >= 2 stages, the first of radix Q, the last RL).
 template <typename R, int Q, int RL, bool INV, typename IDX>
 __device__ __forceinline__ void mfft(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, int P, const PassDesc& pd) {
     const cx<R>* tab = (const cx<R>*)pd.st_tab;
     const int L = pd.L, tmul = pd.st_mul, nst = pd.nst;
     const uint64_t rads = (uint64_t)pd.mrad;
-    constexpr int RF = R0<Q>();
-    mstage<R, Q, RF, INV, true, false>(v, lds, idx, q, P, L, 1, tab, tmul);
-    int NS = RF;
+    mstage<R, Q, Q, INV, true, false>(v, lds, idx, q, P, L, 1, tab, tmul);
+    int NS = Q;
     for (int s = 1; s < nst - 1; ++s) {
         const int rad = mixed_radix_at((int64_t)rads, s);
         mstage_rad<R, Q, INV, false, false>(rad, v, lds, idx, q, P, L, NS, tab, tmul);
@@ -446,18 +475,24 @@ struct MBatch {
 };
 
 template <typename R, int Q, int RL>
-void launch_q(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st, const MBatch* ba) {
+hipError_t launch_q(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st, const MBatch* ba) {
     const dim3 g((unsigned)(ba ? ba->tiles : pd.ntiles)), b((unsigned)pd.mthreads);
     if (pd.kind == PASS_ROW) {
+        // rows take at most 10 points per thread when the length has a factor 2:
+        // there are no 20-point row kernels
+        if constexpr (Q == 20) {
+            return hipErrorInvalidValue;
+        } else {
 #define SFFT_MROW(K)                                                                               \
     if (ba) hipLaunchKernelGGL((k_mrow_b<R, K, Q, RL>), g, b, lds, st, ba->items, ba->n, ba->syms);     \
     else hipLaunchKernelGGL((k_mrow<R, K, Q, RL>), g, b, lds, st, pd, sp);
-        switch (pd.fast_kind) {
-            case ROW_R2C: SFFT_MROW(ROW_R2C) break;
-            case ROW_C2R: SFFT_MROW(ROW_C2R) break;
-            default: SFFT_MROW(ROW_MIDR) break;
-        }
+            switch (pd.fast_kind) {
+                case ROW_R2C: SFFT_MROW(ROW_R2C) break;
+                case ROW_C2R: SFFT_MROW(ROW_C2R) break;
+                default: SFFT_MROW(ROW_MIDR) break;
+            }
 #undef SFFT_MROW
+        }
     } else {
 #define SFFT_MCOL(M)                                                                               \
     if (ba) hipLaunchKernelGGL((k_mcol_b<R, M, Q, RL>), g, b, lds, st, ba->items, ba->n, ba->syms);     \
@@ -469,6 +504,7 @@ void launch_q(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t s
         }
 #undef SFFT_MCOL
     }
+    return hipGetLastError();
 }
 
 template <typename R>
@@ -477,19 +513,21 @@ hipError_t launch_m(const PassDesc& pd, const SymParams& sp, size_t lds, hipStre
     const int rl = mixed_radix_at(pd.mrad, pd.nst - 1);
     // (Q, last radix) pairs the planner's canonical order produces
     // (FP32 only for 20 and 25 points per thread: FP64 would hold one wave per SIMD)
-    if (pd.mq == 5 && rl == 5) launch_q<R, 5, 5>(pd, sp, lds, st, ba);
-    else if (pd.mq == 10 && rl == 2) launch_q<R, 10, 2>(pd, sp, lds, st, ba);
-    else if (pd.mq == 12 && rl == 4) launch_q<R, 12, 4>(pd, sp, lds, st, ba);
-    else if (pd.mq == 12 && rl == 2) launch_q<R, 12, 2>(pd, sp, lds, st, ba);
-    else if constexpr (sizeof(R) == 4) {
-        if (pd.mq == 20 && rl == 4) launch_q<R, 20, 4>(pd, sp, lds, st, ba);
-        else if (pd.mq == 20 && rl == 2) launch_q<R, 20, 2>(pd, sp, lds, st, ba);
-        else if (pd.mq == 25 && rl == 5) launch_q<R, 25, 5>(pd, sp, lds, st, ba);
-        else return hipErrorInvalidValue;
-    } else {
-        return hipErrorInvalidValue;
+    if (pd.mq == 5 && rl == 5) return launch_q<R, 5, 5>(pd, sp, lds, st, ba);
+    if (pd.mq == 10 && rl == 10) return launch_q<R, 10, 10>(pd, sp, lds, st, ba);
+    if (pd.mq == 10 && rl == 2) return launch_q<R, 10, 2>(pd, sp, lds, st, ba);
+    if (pd.mq == 10 && rl == 5) return launch_q<R, 10, 5>(pd, sp, lds, st, ba);
+    if (pd.mq == 12 && rl == 12) return launch_q<R, 12, 12>(pd, sp, lds, st, ba);
+    if (pd.mq == 12 && rl == 2) return launch_q<R, 12, 2>(pd, sp, lds, st, ba);
+    if (pd.mq == 12 && rl == 3) return launch_q<R, 12, 3>(pd, sp, lds, st, ba);
+    if constexpr (sizeof(R) == 4) {
+        if (pd.mq == 20 && rl == 20) return launch_q<R, 20, 20>(pd, sp, lds, st, ba);
+        if (pd.mq == 20 && rl == 2) return launch_q<R, 20, 2>(pd, sp, lds, st, ba);
+        if (pd.mq == 20 && rl == 5) return launch_q<R, 20, 5>(pd, sp, lds, st, ba);
+        if (pd.mq == 25 && rl == 25) return launch_q<R, 25, 25>(pd, sp, lds, st, ba);
+        if (pd.mq == 25 && rl == 5) return launch_q<R, 25, 5>(pd, sp, lds, st, ba);
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
 }  // namespace

@@ -49,46 +49,91 @@ static bool radix_list(int64_t L, int* out, int* nst) {
 
 static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
+// Stage list of a length L = Q^k * rest with Q points per thread: radix Q first,
+// radix Q last when k >= 2, the rest as the fewest proper divisors of Q in
+// between; with k = 1 the last radix is a 2 when an even radix remains (a middle
+// radix that holds one is split if needed), else the family's odd prime.
+static bool mixed_stages(int64_t L, int q, std::vector<int>* out) {
+    int64_t rest = L;
+    int kq = 0;
+    while (rest % q == 0) { rest /= q; ++kq; }
+    if (kq == 0) return false;
+    std::vector<int> mid;
+    for (int dv : {12, 10, 6, 5, 4, 3, 2}) {
+        if (dv >= q || q % dv) continue;
+        while (rest % dv == 0) { mid.push_back(dv); rest /= dv; }
+    }
+    if (rest != 1) return false;
+    std::vector<int> r{q};
+    if (kq >= 2) {
+        for (int i = 0; i < kq - 2; ++i) r.push_back(q);
+        r.insert(r.end(), mid.begin(), mid.end());
+        r.push_back(q);
+    } else {
+        if (mid.empty()) return false;
+        bool even = false;
+        for (int dv : mid) even = even || dv % 2 == 0;
+        const int last = even ? 2 : (q % 5 == 0 ? 5 : 3);
+        auto it = std::find(mid.begin(), mid.end(), last);
+        if (it != mid.end()) {
+            mid.erase(it);
+        } else {
+            auto jt = std::find_if(mid.begin(), mid.end(), [&](int dv) { return dv % last == 0; });
+            if (jt == mid.end()) return false;
+            *jt /= last;
+        }
+        r.insert(r.end(), mid.begin(), mid.end());
+        r.push_back(last);
+    }
+    *out = r;
+    return true;
+}
+
 bool mixed_family(int64_t L, bool column, bool f64, int* Q, int64_t* packed, int* nst) {
     if (tunables().no_fast || L < 2) return false;
     int64_t n = L;
-    int e2 = 0, e3 = 0, e5 = 0, e7 = 0;
+    int e2 = 0, e3 = 0, e5 = 0;
     while (n % 2 == 0) { n /= 2; ++e2; }
     while (n % 3 == 0) { n /= 3; ++e3; }
     while (n % 5 == 0) { n /= 5; ++e5; }
-    while (n % 7 == 0) { n /= 7; ++e7; }
     if (n != 1) return false;
-    std::vector<int> r;
-    int q = 0;
-    // Points per thread: rows (contiguous, any thread count coalesces) take the
-    // fewest (more waves per SIMD); columns take more so that a workgroup spans
-    // enough adjacent columns for full-width loads, within the register budget
-    // (FP64 points take twice the registers: 20 and 25 points would run one wave
-    // per SIMD).
-    if (e3 == 0 && e7 == 0 && e5 >= 1) {
-        if (!column || f64) q = e2 >= 1 ? 10 : 5;
-        else q = e2 >= 2 ? 20 : (e2 == 1 ? 10 : 25);
-        if (e2 == 0 && e5 < 2) return false;
-        for (int i = 0; i < e5; ++i) r.push_back(5);
-    } else if (e5 == 0 && e7 == 0 && e3 >= 1 && e2 >= 2) {
-        q = 12;
-        for (int i = 0; i < e3; ++i) r.push_back(3);
+    // Points per thread, most preferred first.  Every stage is one LDS exchange
+    // and the radix-Q stages cover most of the length, so more points per thread
+    // means fewer stages; but a long row is one workgroup of L/Q threads, and at
+    // 20 points (about 200 VGPRs) only two rows fit a CU, as at 10 points (about
+    // 110 VGPRs, twice the threads), so rows prefer 10 (measured equal on
+    // 4000-point rows, faster on short rows where many rows share a
+    // workgroup).  FP64 points take twice the registers: 20 or 25 of them would
+    // run one wave per SIMD.  An option caps the choice, rows and columns
+    // separately.
+    std::vector<int> pref;
+    if (e3 == 0 && e5 >= 1) {
+        if (e2 >= 2 && !f64 && column) pref.push_back(20);
+        if (e2 >= 1) pref.push_back(10);
+        if (e2 == 0 && !f64) pref.push_back(25);
+        pref.push_back(5);
+    } else if (e5 == 0 && e3 >= 1 && e2 >= 2) {
+        pref.push_back(12);
     } else {
         return false;
     }
-    if (q % 4 == 0) {
-        for (int i = 0; i < e2 / 2; ++i) r.push_back(4);
-        if (e2 % 2) r.push_back(2);
-    } else {
-        for (int i = 0; i < e2; ++i) r.push_back(2);
+    const int cap = column ? tunables().mixed_col_q : tunables().mixed_row_q;
+    std::vector<int> r;
+    int q = 0;
+    for (int c : pref) {
+        if (cap != 0 && c > cap && c != pref.back()) continue;
+        if (mixed_stages(L, c, &r)) { q = c; break; }
     }
+    if (q == 0) return false;
     const int64_t P = L / q;
     if (P < 1 || P > (column ? 64 : 512) || r.size() < 2 || (int)r.size() * kMRadBits > 64) return false;
-    int64_t pk = 0;
+    int64_t pk = 0, prod = 1;
     for (size_t i = 0; i < r.size(); ++i) {
         if (q % r[i]) return false;
+        prod *= r[i];
         pk |= (int64_t)r[i] << (kMRadBits * i);
     }
+    if (prod != L) return false;
     *Q = q;
     *packed = pk;
     *nst = (int)r.size();

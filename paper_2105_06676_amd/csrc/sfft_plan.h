@@ -76,6 +76,8 @@ struct Tunables {
     int aperiodic_cutoff = 0; // 0: per-shape default
     int no_fast = 0;          // 1: generic kernels only (testing)
     int aperiodic_graphs = 1; // 1: replay repeated aperiodic solves from captured graphs
+    int mixed_row_q = 0;      // most points per thread of mixed-radix row passes (0: default)
+    int mixed_col_q = 0;      // ... and of strided-axis passes
 };
 Tunables& tunables();
 

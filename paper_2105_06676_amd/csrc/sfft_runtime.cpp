@@ -74,7 +74,7 @@ const double2* DevCtx::phase_table(int64_t n) {
 
 std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f64, bool unfused) {
     std::ostringstream key;
-    key << d << ":" << B << ":" << f64 << ":" << tunables().col_max << ":" << tunables().no_fast << ":" << unfused
+    key << d << ":" << B << ":" << f64 << ":" << tunables().col_max << ":" << tunables().no_fast << ":" << tunables().mixed_row_q << ":" << tunables().mixed_col_q << ":" << unfused
         << ":" << tune_db().gen.load();
     for (int a = 0; a < d; ++a) key << ":" << dims[a];
     {
@@ -102,7 +102,7 @@ std::shared_ptr<Plan> DevCtx::plan(int d, const int64_t* dims, int64_t B, bool f
 std::shared_ptr<Plan> DevCtx::axis_plan(int64_t outer, int64_t n, int64_t inner, bool f64, bool inverse) {
     std::ostringstream key;
     key << "axis:" << outer << ":" << n << ":" << inner << ":" << f64 << ":" << inverse << ":"
-        << tunables().col_max << ":" << tunables().no_fast << ":" << tune_db().gen.load();
+        << tunables().col_max << ":" << tunables().no_fast << ":" << tunables().mixed_row_q << ":" << tunables().mixed_col_q << ":" << tune_db().gen.load();
     {
         std::lock_guard<std::mutex> g(mu);
         auto it = plans.find(key.str());
