@@ -20,6 +20,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -31,10 +32,29 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBS = 8000.0
 
 
+def kernel_source_files() -> list:
+    """The sources that decide what the pass kernels do: every .hip file, the
+    headers they include (transitively), and the planner and table code that set
+    their launch shapes and tables.  Host-only files (entry points, server, tuner,
+    verification) are left out, so changing them keeps counter summaries valid."""
+    csrc = os.path.join(ROOT, "paper_2105_06676_amd", "csrc")
+    names = {n for n in os.listdir(csrc) if n.endswith(".hip")}
+    names |= {"sfft_plan.cpp", "sfft_plan.h", "sfft_runtime.cpp"}
+    todo = sorted(names)
+    while todo:
+        n = todo.pop()
+        with open(os.path.join(csrc, n)) as f:
+            for inc in re.findall(r'#include "([^"/]+)"', f.read()):
+                if inc not in names and os.path.exists(os.path.join(csrc, inc)):
+                    names.add(inc)
+                    todo.append(inc)
+    return sorted(names)
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2105_06676_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in kernel_source_files():
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(name.encode())
             h.update(f.read())
@@ -433,6 +453,39 @@ def result_errors(sfft, torch, w, full=None):
     return out
 
 
+def mfma_probe(torch, n: int = 1 << 21, reps: int = 32):
+    """One measurement of a DFT stage as a matrix product on the matrix cores
+    against the butterflies the pass kernels use (paper_2105_06676_amd/probes):
+    n 16-point FP32 complex vectors, each transformed `reps` times in registers."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2105_06676_amd", "libsfft_probe.so")
+    lib = ctypes.CDLL(path)
+    f = lib.sfft_probe_dft16
+    f.restype = ctypes.c_float
+    f.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    x = torch.rand(n, 16, 2, generator=gen, dtype=torch.float32).to("cuda")
+    outs, res = [], {}
+    st = torch.cuda.current_stream().cuda_stream
+    for variant, name in ((0, "butterfly"), (1, "mfma")):
+        y = torch.empty_like(x)
+        f(variant, x.data_ptr(), y.data_ptr(), n, 1, st)  # warm-up
+        ms = min(f(variant, x.data_ptr(), y.data_ptr(), n, reps, st) for _ in range(3))
+        ms1 = min(f(variant, x.data_ptr(), y.data_ptr(), n, 1, st) for _ in range(3))
+        f(variant, x.data_ptr(), y.data_ptr(), n, reps, st)
+        torch.cuda.synchronize()
+        outs.append(y.double())
+        # arithmetic of one application: (reps-time - one-application time) / (reps - 1)
+        per = max(ms - ms1, 1e-9) / (reps - 1)
+        res[name] = {"ms_reps": ms, "ms_one": ms1, "dft16_per_s": n / (per * 1e-3)}
+    ref = outs[0]
+    err = float((outs[1] - ref).norm() / ref.norm())
+    res["mfma_vs_butterfly_rel_l2"] = err
+    res["speedup_mfma_over_butterfly"] = res["mfma"]["dft16_per_s"] / res["butterfly"]["dft16_per_s"]
+    res["config"] = {"vectors": n, "reps": reps, "dtype": "f32", "points": 16}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -449,6 +502,8 @@ def main():
                     help="comma-separated <workload>_<dtype> keys: time only these other workloads")
     ap.add_argument("--only-others", action="store_true",
                     help="profiling runs: time only the other workloads (prints their JSON, no headline line)")
+    ap.add_argument("--mfma-probe", action="store_true",
+                    help="measure a DFT stage on the matrix cores against butterflies (prints its JSON only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -459,6 +514,10 @@ def main():
     import torch
     import paper_2105_06676_amd as sfft
     import workloads as wl
+
+    if args.mfma_probe:
+        print(json.dumps({"mfma_probe": mfma_probe(torch)}))
+        return
 
     if args.only_others:
         print(json.dumps({"other_workloads": other_workloads(

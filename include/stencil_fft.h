@@ -288,6 +288,26 @@ int sfft_server_ticket_times(sfft_server* s, uint64_t ticket, double* submit_s, 
 void sfft_server_destroy(sfft_server* s);
 
 /*
+ * Host-side verification of the pass schedules a solve would run (no device
+ * needed, nothing enqueued).  Each pass kernel's indices are affine in its loop
+ * indices with non-negative strides, so the corner of each loop box bounds the
+ * addresses it can touch; every pass of the solve is checked that way against
+ * the buffers the solve hands it (spectrum workspace, real input and output
+ * views, symbol column table, twiddle and stage tables), and row counts and
+ * tile coverage against the transform extents.  kind 0: the periodic solve of
+ * 7-smooth dims (stencil_fft_periodic); 1 / 2: the aperiodic solve with a fixed /
+ * reflecting frame (stencil_fft_aperiodic_bc), whose whole RecursiveBoundary
+ * bookkeeping (interior, slab and recursion-level solves, base-case strips) runs
+ * with stand-in addresses under the current tunables.
+ *   report  HOST buffer of cap bytes (may be NULL) receiving JSON
+ *           {"checked": n, "failures": k, "errors": ["...", ...]} (first 64)
+ * Returns the number of failures (0: every check passed) or a negative error
+ * code (SFFT_EINVAL / SFFT_EUNSUPPORTED as the solve entry points would).
+ */
+int stencil_fft_verify(sfft_dtype dtype, int ndim, const int64_t* dims, const double* coeffs, int radius,
+                       int64_t T, int kind, char* report, int64_t cap);
+
+/*
  * Tunables (process-wide).  Names:
  *   "aperiodic_cutoff"  RecursiveBoundary recurses while T > cutoff; the base
  *                       case loops T' <= cutoff steps (default chosen per shape

@@ -28,5 +28,6 @@ from ._binding import (  # noqa: F401
     tune_clear,
     tune_load,
     tune_save,
+    verify,
     version,
 )

@@ -64,6 +64,8 @@ _profile = _sig("stencil_fft_profile", ctypes.c_int, [ctypes.c_int])
 _profile_read = _sig("stencil_fft_profile_read", ctypes.c_int, [ctypes.c_char_p, ctypes.c_int64])
 _plan_describe = _sig("stencil_fft_plan_describe", ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_char_p, ctypes.c_int64])
 _version = _sig("stencil_fft_version", ctypes.c_char_p, [])
+_verify = _sig("stencil_fft_verify", ctypes.c_int, [ctypes.c_int, ctypes.c_int, _i64p, _dp, ctypes.c_int, ctypes.c_int64,
+                                                   ctypes.c_int, ctypes.c_char_p, ctypes.c_int64])
 _tune = _sig("stencil_fft_tune", ctypes.c_int, [ctypes.c_int, _i64p, ctypes.c_int, ctypes.c_int, ctypes.c_char_p, ctypes.c_int64])
 _tune_save = _sig("stencil_fft_tune_save", ctypes.c_int, [ctypes.c_char_p])
 _tune_load = _sig("stencil_fft_tune_load", ctypes.c_int, [ctypes.c_char_p])
@@ -229,6 +231,20 @@ def aperiodic(grid, coeffs, T: int, stream=None, bc: str = "fixed"):
             _check(_aperiodic_bc(grid.data_ptr(), _dtype_code(grid), grid.dim(), dims,
                                  c.ctypes.data_as(_dp), r, int(T), _BCS[bc], _stream(grid, stream)))
     return grid
+
+
+def verify(dims: Sequence[int], coeffs, T: int, dtype: str = "f32", kind="periodic") -> dict:
+    """Host-side check of the pass schedules of a solve against its buffers (no
+    device).  kind: "periodic", "fixed" or "reflect" (aperiodic frames; dims are
+    interior extents).  Returns {"checked", "failures", "errors"}."""
+    kinds = {"periodic": 0, "fixed": 1, "reflect": 2}
+    c, r = _coeffs(coeffs, len(dims))
+    d = (ctypes.c_int64 * len(dims))(*dims)
+    buf = ctypes.create_string_buffer(1 << 16)
+    rc = _verify(SFFT_F64 if dtype == "f64" else SFFT_F32, len(dims), d, c.ctypes.data_as(_dp), r, int(T),
+                 kinds[kind], buf, len(buf))
+    _check(rc)
+    return json.loads(buf.value.decode())
 
 
 def symbol_power(out, dims: Sequence[int], coeffs, T: int, stream=None):

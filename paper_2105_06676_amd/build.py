@@ -1,7 +1,9 @@
 """Build ``libstencilfft.so`` in-tree with hipcc for gfx950.
 
 Every source under ``csrc/`` is compiled to an object in ``_build/`` (in
-parallel) and linked into ``paper_2105_06676_amd/libstencilfft.so``.
+parallel) and linked into ``paper_2105_06676_amd/libstencilfft.so``.  The
+measurement probes under ``probes/`` (not part of the solver) are linked into
+``paper_2105_06676_amd/libsfft_probe.so``.
 """
 from __future__ import annotations
 
@@ -15,6 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libstencilfft.so")
+PROBE_OUT = os.path.join(HERE, "libsfft_probe.so")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -51,9 +54,21 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, OUT)
+    build_probes()
     if verbose:
-        print(f"built {OUT}")
+        print(f"built {OUT} and {PROBE_OUT}")
     return OUT
+
+
+def build_probes() -> str:
+    srcs = sorted(glob.glob(os.path.join(HERE, "probes", "*.hip")))
+    tmp = PROBE_OUT + ".tmp"
+    cmd = [HIPCC] + COMMON + ["-shared", "-o", tmp] + srcs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"probe build failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_OUT)
+    return PROBE_OUT
 
 
 if __name__ == "__main__":

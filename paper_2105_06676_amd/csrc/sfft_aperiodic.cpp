@@ -33,6 +33,7 @@
 #include "sfft_kernels.h"
 #include "sfft_runtime.h"
 #include "sfft_solvers.h"
+#include "sfft_verify.h"
 
 namespace sfft {
 
@@ -93,6 +94,10 @@ struct Ap {
     // FFT parts never depend on it: a cell they keep has a dependency cone that
     // stays inside the interior, whatever the frame does.
     int bc = 0;
+    // Verification mode (dry runs only): every boxed solve's schedule and every
+    // base case's strips are checked against the buffers of the solve.
+    Verifier* verify = nullptr;
+    int nsolve = 0;
 };
 
 constexpr int kWsSlot = -1;  // the spectrum workspace of a stream
@@ -109,7 +114,9 @@ void* ap_buf(Ap& a, hipStream_t st, int slot, size_t bytes) {
     if (!a.dry && at + bytes > a.pool_cap)
         throw Error(-3, "aperiodic solve needs more than its " + std::to_string(a.pool_cap) + " reserved bytes");
     a.pool_used = at + bytes;
-    b = {a.dry ? (void*)(uintptr_t)(at + 256) : (void*)(a.pool + at), bytes};
+    // (dry runs hand out stand-in addresses far from the stand-in grid's)
+    b = {a.dry ? (void*)(((uintptr_t)1 << 40) + at) : (void*)(a.pool + at), bytes};
+    if (a.verify) a.verify->add(b.first, bytes, "buffer " + std::to_string(slot));
     return b.first;
 }
 
@@ -158,11 +165,25 @@ Boxed boxed_prepare(Ap& a, const void* src, void* dst, const int64_t* ext, int64
         std::string why;
         const int rc = build_schedule(a.d, pd, B, a.f64, &s, &why);
         if (rc) throw Error(rc == -1 ? -1 : -2, why);
-        ap_buf(a, st, kWsSlot, (size_t)s.spec_elems * (a.f64 ? 16 : 8));
-        if (a.d >= 2 && !a.coltab.count(ckey)) {
-            int64_t ncol = 1;
-            for (int k = 1; k < a.d; ++k) ncol *= s.sym.sdim[k];
+        void* ws = ap_buf(a, st, kWsSlot, (size_t)s.spec_elems * (a.f64 ? 16 : 8));
+        int64_t ncol = 1;
+        for (int k = 1; k < a.d; ++k) ncol *= s.sym.sdim[k];
+        if (a.d >= 2 && !a.coltab.count(ckey))
             a.coltab[ckey] = ap_buf(a, st, 300 + (int)a.coltab.size(), (size_t)ncol * symbol_column_bytes());
+        if (a.verify) {
+            RealView in, out;
+            std::memset(&in, 0, sizeof(in));
+            in.boff = boff;
+            for (int k = 0; k < a.d; ++k) {
+                in.stride[k] = a.sstride[k];
+                in.ext[k] = ext[k];
+            }
+            out = in;
+            in.ptr = const_cast<void*>(src);
+            out.ptr = dst;
+            a.verify->schedule(s, ws, in, out, a.d >= 2 ? a.coltab[ckey] : nullptr, ncol,
+                               "solve " + std::to_string(a.nsolve++) + " (B=" + std::to_string(B) + ", steps=" +
+                                   std::to_string(steps) + ")");
         }
         return b;
     }
@@ -445,6 +466,25 @@ void base_case(Ap& a, const void* src, void* dst, int64_t tau, hipStream_t st) {
         first += cnt;
         lds = std::max(lds, (size_t)f * a.esz);
     }
+    if (a.verify) {
+        // strips inside the interior and covered by their tiles; the loaded region
+        // (clipped by the kernel to the stored array) and the stores stay inside
+        // the source, frame and destination arrays
+        Verifier& v = *a.verify;
+        for (int i = 0; i < ns; ++i) {
+            const BaseStrip& s = bp.strip[i];
+            for (int k = 0; k < 3; ++k) {
+                ++v.checked;
+                if (s.lo[k] < 0 || s.lo[k] + s.ext[k] > bp.n[k] || s.tile[k] * s.ntiles[k] < s.ext[k])
+                    v.fail("base case strip " + std::to_string(i) + " axis " + std::to_string(k) + " outside the interior");
+            }
+        }
+        ++v.checked;
+        if (lds > (size_t)kBaseMaxCells * a.esz) v.fail("base case tile larger than its LDS budget");
+        v.range(src, a.total - 1, a.esz, "base case source");
+        v.range(dst, a.total - 1, a.esz, "base case destination");
+        v.range(a.grid, a.total - 1, a.esz, "base case frame");
+    }
     if (a.dry) return;
     hipEvent_t ev = nullptr;
     const bool prof = profiling();
@@ -684,6 +724,22 @@ size_t aperiodic_footprint(bool f64, int d, const int64_t* dims, const double* c
             recursive_path(a, T, a.st);
     }
     return (a.pool_used + 255) & ~size_t(255);
+}
+
+// Dry run of the whole solve with every schedule and base case checked against
+// its buffers (no device work); returns the verifier's findings.
+void verify_aperiodic(bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T, int bc,
+                      Verifier* v) {
+    void* grid = (void*)((uintptr_t)1 << 44);
+    Ap a = make_ap(grid, f64, d, dims, coeffs, r, bc, (hipStream_t)(uintptr_t)0x10);
+    a.dry = true;
+    a.verify = v;
+    v->add(grid, (size_t)a.total * a.esz, "grid");
+    if (T <= 0) return;
+    if (a.inert || T <= a.cutoff)
+        short_path(a, T);
+    else
+        recursive_path(a, T, a.st);
 }
 
 // solve_aperiodic with every device buffer taken from [pool, pool + cap)

@@ -11,6 +11,7 @@
 #include "sfft_kernels.h"
 #include "sfft_runtime.h"
 #include "sfft_solvers.h"
+#include "sfft_verify.h"
 
 namespace sfft {
 const char* last_error_cstr();
@@ -319,6 +320,54 @@ int stencil_fft_aperiodic_bc(void* grid, sfft_dtype dtype, int ndim, const int64
         if (T == 0) return;
         solve_aperiodic_cached(grid, dtype == SFFT_F64, ndim, dims, coeffs, radius, T, bc, (hipStream_t)stream);
     });
+}
+
+int stencil_fft_verify(sfft_dtype dtype, int ndim, const int64_t* dims, const double* coeffs, int radius, int64_t T,
+                       int kind, char* report, int64_t cap) {
+    Verifier v;
+    const int rc = guarded([&] {
+        void* const fake = (void*)((uintptr_t)1 << 44);
+        if (kind < 0 || kind > 2) throw Error(SFFT_EINVAL, "kind must be 0, 1 or 2");
+        validate(fake, dtype, ndim, dims, coeffs, radius, T, kind ? kMaxR : kMaxGeneralR);
+        const bool f64 = dtype == SFFT_F64;
+        if (kind) {
+            validate_bc(kind - 1, ndim, dims, radius);
+            verify_aperiodic(f64, ndim, dims, coeffs, radius, T, kind - 1, &v);
+            return;
+        }
+        for (int a = 0; a < ndim; ++a)
+            if (!is_7smooth(dims[a]))
+                throw Error(SFFT_EUNSUPPORTED, "verification covers 7-smooth periodic extents");
+        Schedule s;
+        std::string why;
+        const int brc = build_schedule(ndim, dims, 1, f64, &s, &why, radius > kMaxR);
+        if (brc) throw Error(brc == -1 ? SFFT_EINVAL : SFFT_EUNSUPPORTED, why);
+        int64_t cells = 1, ncol = 1;
+        for (int a = 0; a < ndim; ++a) cells *= dims[a];
+        for (int a = 1; a < ndim; ++a) ncol *= s.sym.sdim[a];
+        void* ws = (void*)((uintptr_t)1 << 40);
+        void* coltab = (void*)((uintptr_t)1 << 42);
+        v.add(fake, (size_t)cells * (f64 ? 8 : 4), "grid");
+        v.add(ws, (size_t)s.spec_elems * (f64 ? 16 : 8), "spectrum");
+        v.add(coltab, (size_t)ncol * symbol_column_bytes(), "symbol columns");
+        const RealView view = dense_view(fake, ndim, dims);
+        v.schedule(s, ws, view, view, ndim >= 2 ? coltab : nullptr, ncol, "periodic");
+    });
+    if (rc != SFFT_OK) return rc;
+    std::string js = "{\"checked\": " + std::to_string(v.checked) + ", \"failures\": " + std::to_string(v.nerr) +
+                     ", \"errors\": [";
+    for (size_t i = 0; i < v.errors.size(); ++i) {
+        std::string e;
+        for (char c : v.errors[i]) e += (c == '"' || c == '\\') ? ' ' : c;
+        js += (i ? ", \"" : "\"") + e + "\"";
+    }
+    js += "]}";
+    if (report && cap > 0) {
+        const size_t n = std::min<size_t>((size_t)cap - 1, js.size());
+        std::memcpy(report, js.data(), n);
+        report[n] = 0;
+    }
+    return (int)std::min<int64_t>(v.nerr, 1 << 30);
 }
 
 int stencil_fft_symbol_power(double* out, int ndim, const int64_t* dims, const double* coeffs, int radius,

@@ -28,5 +28,10 @@ void solve_aperiodic(void* grid, bool f64, int d, const int64_t* dims, const dou
 void solve_aperiodic_pooled(void* grid, bool f64, int d, const int64_t* dims, const double* coeffs, int r,
                             int64_t T, int bc, hipStream_t st, void* pool, size_t cap);
 size_t aperiodic_footprint(bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T, int bc);
+struct Verifier;
+// The aperiodic solve's bookkeeping with nothing enqueued, every pass schedule and
+// base case checked against its buffers.
+void verify_aperiodic(bool f64, int d, const int64_t* dims, const double* coeffs, int r, int64_t T, int bc,
+                      Verifier* v);
 
 }  // namespace sfft
