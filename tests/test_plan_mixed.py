@@ -1,0 +1,54 @@
+"""CPU checks of the mixed-radix stage lists the planner builds (no GPU): for
+every pass that runs on the register mixed-radix kernels, the radices multiply
+to the pass length, each divides the points per thread Q, the first is Q, and
+the last is one the kernels are instantiated for (Q itself, 2, or the family's
+odd prime); rows never take 20 points per thread, and the
+options that cap Q are honoured."""
+import pytest
+
+# (Q, last radix) pairs that have kernels, per dtype
+PAIRS = {"f32": {(5, 5), (10, 10), (10, 2), (10, 5), (12, 12), (12, 2), (12, 3), (20, 20), (20, 2), (20, 5),
+                 (25, 25), (25, 5)},
+         "f64": {(5, 5), (10, 10), (10, 2), (10, 5), (12, 12), (12, 2), (12, 3)}}
+
+SHAPES = [(8000, 8000), (4000, 4000), (2000, 1000), (250, 160), (96, 768), (75, 50), (20, 40, 100), (640,),
+          (1536, 40), (400, 400, 400), (800, 800, 800), (192, 96), (96, 48), (250,), (20, 500), (1250, 3000),
+          (625, 48), (3125,), (120, 360)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_mixed_stage_lists_are_valid(shape, dtype):
+    import paper_2105_06676_amd as sfft
+    for p in sfft.plan_describe(shape, dtype)["passes"]:
+        q = p["mixed_q"]
+        if not q:
+            continue
+        rad = p["radices"]
+        prod = 1
+        for x in rad:
+            assert q % x == 0, (shape, p)
+            prod *= x
+        assert prod == p["L"], (shape, p)
+        assert rad[0] == q and len(rad) >= 2, (shape, p)
+        assert (q, rad[-1]) in PAIRS[dtype], (shape, p)
+        if p["kind"] == "row":
+            assert q != 20, (shape, p)  # no 20-point row kernels
+
+
+def test_mixed_q_options_cap_points_per_thread():
+    import paper_2105_06676_amd as sfft
+    try:
+        sfft.set_option("mixed_col_q", 10)
+        for p in sfft.plan_describe((400, 400, 400), "f32")["passes"]:
+            if p["kind"] == "col" and p["mixed_q"]:
+                assert p["mixed_q"] <= 10
+        sfft.set_option("mixed_row_q", 5)
+        for p in sfft.plan_describe((8000, 8000), "f32")["passes"]:
+            if p["kind"] == "row" and p["mixed_q"]:
+                assert p["mixed_q"] == 5
+    finally:
+        sfft.set_option("mixed_col_q", 0)
+        sfft.set_option("mixed_row_q", 0)
+    with pytest.raises(sfft.SfftError):
+        sfft.set_option("mixed_row_q", 7)
