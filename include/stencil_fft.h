@@ -40,9 +40,10 @@
  * Errors: SFFT_EINVAL (null pointer, ndim outside 1..3, an extent < 1,
  * radius < 0, T < 0, a non-finite coefficient, an unknown dtype);
  * SFFT_EUNSUPPORTED (a shape the FFT planner cannot handle: a prime factor above
- * 7 in an extent of the fields, implicit or no-allocation entry points, a radius
- * above 8 (periodic) or above 2 (aperiodic, fields, implicit), a radius above 2
- * on an extent with a prime factor above 7);
+ * 7 in an extent of the no-allocation entry point, a radius above 8 (periodic) or
+ * above 2 (aperiodic, fields, implicit), a radius above 2 on an extent with a
+ * prime factor above 7, a 7-smooth 1-D extent of the fields or implicit entry
+ * points longer than one row);
  * SFFT_ENOMEM (device workspace);
  * SFFT_EHIP (a HIP runtime error; the grid is then unspecified).  When
  * validation fails the grid is untouched.
@@ -150,9 +151,11 @@ int stencil_fft_aperiodic_bc(void* grid, sfft_dtype dtype, int ndim, const int64
  *           before the call returns.
  * The forward transforms of all fields run as one batch, the m x m symbol matrix
  * of every mode is raised to the power T by repeated squaring in FP64 (deviation
- * form), and the inverse transforms follow.  Same extent rules as
- * stencil_fft_periodic, except that a 1-D extent must fit one row (n/2 <= 8192 for
- * even n, n <= 8192 for odd n).  Errors as for stencil_fft_periodic.
+ * form), and the inverse transforms follow.  Extents with a prime factor above 7
+ * take the chirp-z transforms of stencil_fft_periodic along those axes (all axes
+ * then complex, the symbol matrix applied over the full spectrum); a 7-smooth 1-D
+ * extent must fit one row (n/2 <= 8192 for even n, n <= 8192 for odd n).  Errors
+ * as for stencil_fft_periodic.
  */
 int stencil_fft_periodic_fields(void* grid, sfft_dtype dtype, int nfields, int ndim, const int64_t* dims,
                                 const double* coeffs, int radius, int64_t T, void* stream);

@@ -68,6 +68,12 @@ void validate(const void* ptr, int dtype, int ndim, const int64_t* dims, const d
 
 namespace sfft {
 
+bool all_7smooth(int ndim, const int64_t* dims) {
+    for (int a = 0; a < ndim; ++a)
+        if (!is_7smooth(dims[a])) return false;
+    return true;
+}
+
 void validate_bc(int bc, int ndim, const int64_t* dims, int radius) {
     if (bc != SFFT_BC_FIXED && bc != SFFT_BC_REFLECT) throw Error(SFFT_EINVAL, "unknown boundary condition");
     if (bc == SFFT_BC_REFLECT)
@@ -155,11 +161,11 @@ void solve_periodic_general(void* grid, bool f64, int d, const int64_t* dims, co
 // m coupled periodic fields (field-major grid): forward transforms of all fields
 // as one batch, the symbol-matrix power per mode, inverse transforms.
 // q_coeffs (m = 1 only): the implicit part Q of Q a_{t+1} = S a_t, S = coeffs.
-void solve_periodic_fields(void* grid, bool f64, int m, int d, const int64_t* dims, const double* coeffs, int r,
-                           int64_t T, hipStream_t st, const double* q_coeffs = nullptr) {
-    DevCtx& ctx = device_ctx();
-    auto plan = ctx.plan(d, dims, m, f64, true);
-    void* ws = ctx.workspace(st, (size_t)plan->s.spec_elems * (f64 ? 16 : 8));
+// The symbol-matrix constants of m coupled fields (and of an implicit stencil's Q):
+// K_ij = delta_ij - sum_o c_ij[o] (compensated sum), then the coefficients, then
+// (implicit) 1 - sum q and q.  Sets fp.m, nof, real_sym, implicit, qzero.
+std::vector<double> field_constants(int m, int d, const double* coeffs, int r, const double* q_coeffs,
+                                    FieldParams* fp) {
     int nof = 1;
     for (int a = 0; a < d; ++a) nof *= 2 * r + 1;
     // K_ij = delta_ij - sum_o c_ij[o] (compensated sum), then the coefficients
@@ -189,22 +195,33 @@ void solve_periodic_fields(void* grid, bool f64, int m, int d, const int64_t* di
         cK.push_back(sum + comp);
         cK.insert(cK.end(), q_coeffs, q_coeffs + nof);
     }
-    FieldParams fp;
-    fp.m = m;
-    fp.nof = nof;
-    fp.real_sym = q_coeffs ? 0 : 1;
+    std::memset(fp, 0, sizeof(*fp));
+    fp->m = m;
+    fp->nof = nof;
+    fp->real_sym = q_coeffs ? 0 : 1;
     for (int b = 0; b < m * m; ++b)
         for (int o = 0; o < nof; ++o)
-            if (coeffs[(size_t)b * nof + o] != coeffs[(size_t)b * nof + (nof - 1 - o)]) fp.real_sym = 0;
+            if (coeffs[(size_t)b * nof + o] != coeffs[(size_t)b * nof + (nof - 1 - o)]) fp->real_sym = 0;
+    fp->implicit = q_coeffs ? 1 : 0;
+    // lambda_Q counts as zero below the rounding bound of its evaluation
+    fp->qzero = 16.0 * 2.220446049250313e-16 * qabs;
+    return cK;
+}
+
+void solve_periodic_fields(void* grid, bool f64, int m, int d, const int64_t* dims, const double* coeffs, int r,
+                           int64_t T, hipStream_t st, const double* q_coeffs = nullptr) {
+    DevCtx& ctx = device_ctx();
+    auto plan = ctx.plan(d, dims, m, f64, true);
+    void* ws = ctx.workspace(st, (size_t)plan->s.spec_elems * (f64 ? 16 : 8));
+    FieldParams fp;
+    const std::vector<double> cK = field_constants(m, d, coeffs, r, q_coeffs, &fp);
+    const int nof = fp.nof;
     fp.fstride = plan->s.spec_elems / m;
     fp.pitch = plan->s.sym.sdim[d - 1];
     fp.rows = fp.fstride / fp.pitch;
     fp.ws = ws;
     fp.cK = (const double*)ctx.upload(st, 60, cK.data(), sizeof(double) * cK.size());
-    fp.implicit = q_coeffs ? 1 : 0;
     fp.qK = q_coeffs ? fp.cK + (size_t)m * m * (1 + nof) : nullptr;
-    // lambda_Q counts as zero below the rounding bound of its evaluation
-    fp.qzero = 16.0 * 2.220446049250313e-16 * qabs;
     SymParams sp = plan->s.sym;
     sp.d = d;
     sp.r = r;
@@ -284,11 +301,11 @@ int stencil_fft_periodic_fields(void* grid, sfft_dtype dtype, int nfields, int n
         for (int a = 0; a < ndim; ++a) nof *= 2 * radius + 1;
         for (int i = 0; i < nfields * nfields * nof; ++i)
             if (!std::isfinite(coeffs[i])) throw Error(SFFT_EINVAL, "coefficient " + std::to_string(i) + " is not finite");
-        for (int a = 0; a < ndim; ++a)
-            if (!is_7smooth(dims[a]))
-                throw Error(SFFT_EUNSUPPORTED, "extent " + std::to_string(dims[a]) + " has a prime factor above 7");
         if (T == 0) return;
-        solve_periodic_fields(grid, dtype == SFFT_F64, nfields, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
+        if (!all_7smooth(ndim, dims))
+            solve_fields_any(grid, dtype == SFFT_F64, nfields, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
+        else
+            solve_periodic_fields(grid, dtype == SFFT_F64, nfields, ndim, dims, coeffs, radius, T, (hipStream_t)stream);
     });
 }
 
@@ -298,12 +315,13 @@ int stencil_fft_periodic_implicit(void* grid, sfft_dtype dtype, int ndim, const 
     return guarded([&] {
         validate(grid, dtype, ndim, dims, s_coeffs, radius, T);
         validate(grid, dtype, ndim, dims, q_coeffs, radius, T);
-        for (int a = 0; a < ndim; ++a)
-            if (!is_7smooth(dims[a]))
-                throw Error(SFFT_EUNSUPPORTED, "extent " + std::to_string(dims[a]) + " has a prime factor above 7");
         if (T == 0) return;
-        solve_periodic_fields(grid, dtype == SFFT_F64, 1, ndim, dims, s_coeffs, radius, T, (hipStream_t)stream,
-                              q_coeffs);
+        if (!all_7smooth(ndim, dims))
+            solve_fields_any(grid, dtype == SFFT_F64, 1, ndim, dims, s_coeffs, radius, T, (hipStream_t)stream,
+                             q_coeffs);
+        else
+            solve_periodic_fields(grid, dtype == SFFT_F64, 1, ndim, dims, s_coeffs, radius, T, (hipStream_t)stream,
+                                  q_coeffs);
     });
 }
 

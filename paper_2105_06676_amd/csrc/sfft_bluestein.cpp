@@ -16,6 +16,7 @@
 #include <vector>
 
 #include "sfft_bluestein.h"
+#include "sfft_fields.h"
 #include "sfft_kernels.h"
 #include "sfft_runtime.h"
 #include "sfft_solvers.h"
@@ -229,6 +230,63 @@ void solve_periodic_any(void* grid, bool f64, int d, const int64_t* dims, const 
         axis_transform(ws, tmp, outer, dims[a], inner, f64, true, nullptr, a, st);
     }
     timed(st, "narrow", f64, N * (esz + (int64_t)csz), [&] { return launch_narrow(ws, grid, N, f64, st); });
+}
+
+// m coupled fields (appendix on vector-valued fields), or an implicit stencil on
+// one field (appendix on implicit stencils), on any extents: the m fields are one
+// more outer axis of the widened array, every axis is transformed as above, and
+// the symbol-matrix power (sfft_fields.hip) runs over the full spectrum with every
+// axis's stored positions mapped to frequencies.
+void solve_fields_any(void* grid, bool f64, int m, int d, const int64_t* dims, const double* coeffs, int r,
+                      int64_t T, hipStream_t st, const double* q_coeffs) {
+    DevCtx& ctx = device_ctx();
+    const size_t csz = f64 ? 16 : 8;
+    int64_t N = 1;
+    for (int a = 0; a < d; ++a) N *= dims[a];
+    int64_t tmp_elems = 1;
+    for (int a = 0; a < d; ++a)
+        if (!is_7smooth(dims[a])) tmp_elems = std::max(tmp_elems, (int64_t)m * (N / dims[a]) * conv_len(dims[a]));
+    void* ws = ctx.workspace(st, (size_t)m * N * csz);
+    void* tmp = ctx.scratch(st, 72, (size_t)tmp_elems * csz);
+    FieldParams fp;
+    const std::vector<double> cK = field_constants(m, d, coeffs, r, q_coeffs, &fp);
+    fp.full = 1;
+    fp.rows = N / dims[d - 1];
+    fp.pitch = dims[d - 1];
+    fp.fstride = N;
+    fp.ws = ws;
+    fp.cK = (const double*)ctx.upload(st, 61, cK.data(), sizeof(double) * cK.size());
+    fp.qK = q_coeffs ? fp.cK + (size_t)m * m * (1 + fp.nof) : nullptr;
+    SymParams sp;
+    std::memset(&sp, 0, sizeof(sp));
+    sp.d = d;
+    sp.r = r;
+    sp.T = T;
+    sp.scale = 1.0 / (double)N;
+    for (int a = 0; a < 3; ++a) {
+        sp.n[a] = a < d ? dims[a] : 1;
+        sp.sdim[a] = sp.n[a];
+    }
+    sp.hcount = dims[d - 1];
+    for (int a = 0; a < d; ++a) sp.eph[a] = ctx.phase_table(dims[a]);
+
+    const int64_t esz = f64 ? 8 : 4;
+    timed(st, "widen", f64, m * N * (esz + (int64_t)csz), [&] { return launch_widen(grid, ws, m * N, f64, st); });
+    for (int a = 0; a < d; ++a) {
+        int64_t outer = m, inner = 1;
+        for (int b = 0; b < a; ++b) outer *= dims[b];
+        for (int b = a + 1; b < d; ++b) inner *= dims[b];
+        axis_transform(ws, tmp, outer, dims[a], inner, f64, false, &sp, a, st);
+    }
+    timed(st, "fields_symbol_full", f64, 2 * m * N * (int64_t)csz,
+          [&] { return launch_fields_symbol(fp, sp, f64, st); });
+    for (int a = d - 1; a >= 0; --a) {
+        int64_t outer = m, inner = 1;
+        for (int b = 0; b < a; ++b) outer *= dims[b];
+        for (int b = a + 1; b < d; ++b) inner *= dims[b];
+        axis_transform(ws, tmp, outer, dims[a], inner, f64, true, nullptr, a, st);
+    }
+    timed(st, "narrow", f64, m * N * (esz + (int64_t)csz), [&] { return launch_narrow(ws, grid, m * N, f64, st); });
 }
 
 }  // namespace sfft

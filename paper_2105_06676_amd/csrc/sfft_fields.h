@@ -26,6 +26,10 @@ struct FieldParams {
     int implicit;
     const double* qK;
     double qzero;
+    // 1: full spectrum of a complex transform (every axis, the last one included,
+    // maps stored positions to frequencies through sp.nlev / sp.sub); 0: the half
+    // spectrum of the real-data passes (last axis in natural order)
+    int full;
 };
 
 hipError_t launch_fields_symbol(const FieldParams& fp, const SymParams& sp, bool f64, hipStream_t st);

@@ -206,9 +206,10 @@ __global__ __launch_bounds__(256) void k_fields_symbol(FieldParams fp, SymParams
         }
     }
     const int last = sp.d - 1;
-    if (last == 0) f[0] = kl;
-    else if (last == 1) f[1] = kl;
-    else f[2] = kl;
+    const uint32_t fl = fp.full ? pos_to_freq32(sp, last, kl) : kl;
+    if (last == 0) f[0] = fl;
+    else if (last == 1) f[1] = fl;
+    else f[2] = fl;
 
     // E_a(o f_a) for o = 1..r on every axis
     dcx E[3][kMaxR + 1];

@@ -56,11 +56,11 @@ def test_invalid_arguments_are_rejected_without_a_gpu():
     p = (ctypes.c_int64 * 2)((1 << 31) + 1, 8)
     assert f(fake, 0, 2, p, cp, 1, 5, None) == -2
     assert "2^30" in s._binding._last_error().decode()
-    # the fields entry point still needs 7-smooth extents
+    # the fields entry point takes at most 4 fields (checked before any device work)
     ff = s._binding._periodic_fields
     p = (ctypes.c_int64 * 2)(11, 8)
-    assert ff(fake, 0, 1, 2, p, cp, 1, 5, None) == -2
-    assert "prime factor" in s._binding._last_error().decode()
+    assert ff(fake, 0, 5, 2, p, cp, 1, 5, None) == -2
+    assert "4 fields" in s._binding._last_error().decode()
     # boundary conditions of the aperiodic entry point
     fb = lib.stencil_fft_aperiodic_bc
     fb.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int64),

@@ -142,7 +142,7 @@ def test_fields_rejects_bad_arguments_without_touching_the_grid():
     assert e.value.code == -2
     g2 = to_dev(np.ones((2, 13, 16)), "f64")
     with pytest.raises(sfft.SfftError) as e:
-        sfft.periodic_fields(g2, np.zeros((2, 2, 3, 3)), 3)
+        sfft.periodic_fields(g2, np.zeros((2, 2, 7, 7)), 3)  # radius 3
     assert e.value.code == -2
     g3 = to_dev(np.ones((2, 32768)), "f32")
     with pytest.raises(sfft.SfftError) as e:

@@ -118,7 +118,7 @@ def test_implicit_rejects_bad_arguments():
     import paper_2105_06676_amd as sfft
     g = to_dev(np.ones((13, 16)), "f64")
     with pytest.raises(sfft.SfftError) as e:
-        sfft.periodic_implicit(g, _ident(2), _ident(2), 3)
+        sfft.periodic_implicit(g, _ident(2, 3), _ident(2, 3), 3)  # radius 3
     assert e.value.code == -2
     with pytest.raises(ValueError):
         sfft.periodic_implicit(to_dev(np.ones((16, 16)), "f64"), _ident(2, 2), _ident(2, 1), 3)
