@@ -1,26 +1,28 @@
-// StencilFFT-A and RecursiveBoundary (Sec. 4) on one GPU.
+// StencilFFT-A and RecursiveBoundary (Sec. 4) on one GPU, with the entry-time
+// bands of the appendix on l-shells.
 //
-// The stored array has extents n_a + 2r; its r-wide frame holds fixed boundary
-// values.  dist(cell) = 1 + min over faces of the index distance to the frame.
-// After T steps only cells with dist <= r*T see the frame (region of influence),
-// so the result is assembled from
-//   * the periodic solve (StencilFFT-P) of the whole interior, kept where
-//     dist > r*T, and
-//   * RecursiveBoundary(T), which produces dist <= r*T from the band
-//     dist <= 2 r T of the initial array:
-//       T <= cutoff: loop T steps in LDS on the band (base-case kernel);
+// The stored array has extents n_a + 2r; its r-wide frame holds the boundary
+// values.  A face of axis a at distance dist (1-based) from a cell enters it
+// after ceil(dist / s_a) steps, s_a the stencil's reach along axis a; ell(cell)
+// = min over the faces the stencil reads toward.  After T steps only cells with
+// ell <= T see the frame (region of influence), so the result is assembled from
+//   * the periodic solve (StencilFFT-P) of the whole interior, kept where ell > T,
+//   * RecursiveBoundary(T), which produces ell <= T from the band ell <= 2T of
+//     the initial array:
+//       T <= cutoff: loop T steps in LDS on the band (base-case kernel, which
+//                    also applies the boundary condition);
 //       else T1 = floor(T/2), T2 = T - T1, and
-//         step 1: periodic solves of the 2d slabs of band (0, 2rT] for T1 steps,
-//                 kept on (r T1, r T + r T2], plus RecursiveBoundary(T1) for
-//                 (0, r T1], giving the band at time T1;
-//         step 2: periodic solves of the slabs of band (0, r T + r T2] for T2
-//                 steps, kept on (r T2, r T], plus RecursiveBoundary(T2) for
-//                 (0, r T2].
-// A slab of face f spans the band's depth along f's normal and the whole interior
-// along the other axes; a cell is taken from the slab of its nearest face, where
-// its r*steps cone stays inside the slab and away from every other face.  Slab
-// and interior transforms may therefore be zero-padded to 7-smooth extents.  The
-// two slabs of one axis share a shape and run as one batched solve.
+//         step 1: periodic solves of the slabs of band (0, 2T] for T1 steps,
+//                 kept on (T1, T + T2], plus RecursiveBoundary(T1) for (0, T1],
+//                 giving the band at time T1;
+//         step 2: periodic solves of the slabs of band (0, T + T2] for T2
+//                 steps, kept on (T2, T], plus RecursiveBoundary(T2) for (0, T2].
+// The slab of a face of axis a spans s_a cells per step of entry time along a and
+// the whole interior along the other axes; a cell is taken from the slab of the
+// face that enters it first, where its dependency cone (s_b cells per step along
+// each axis b) stays inside the slab and away from every other face.  Slab and
+// interior transforms may therefore be zero-padded to 7-smooth extents.  The two
+// slabs of one axis share a shape and run as one batched solve.
 #include <algorithm>
 #include <climits>
 #include <cstring>
@@ -80,13 +82,15 @@ struct Ap {
     std::map<std::pair<hipStream_t, int>, std::pair<void*, size_t>> bufs;
     int64_t cutoff;
     // Entry-time bookkeeping (appendix on l-shells): sig[a] = the stencil's largest
-    // reach along axis a; face (a, side) is active when the stencil reads toward it
-    // (its boundary values then enter the interior sig[a] cells per step at most).
-    // Bands are measured in units of su = the largest reach toward any active face
-    // (su cells of distance per step of entry time; a conservative common scale).
+    // reach along axis a (either direction); face (a, side) is active when the
+    // stencil reads toward it.  A face's values enter the interior at most sig[a]
+    // cells per step, and a cell's dependency cone grows by at most sig[a] cells
+    // per step along axis a, so entry times along axis a are ceil(dist / sig[a])
+    // and the slab and base-case widths of a face of axis a are sig[a] cells per
+    // step of entry time (half_axes: the axes with sig = 2).
     int64_t sig[3];
     bool act[3][2];
-    int64_t su;
+    int half_axes = 0;
     int64_t maxell;      // largest entry time of any interior cell (LLONG_MAX: none)
     bool inert;          // no active face: the frame never influences the interior
     // boundary condition, applied by the base case only (Sec. 4): 0 fixed frame
@@ -234,9 +238,9 @@ void boxed_periodic(Ap& a, const void* src, void* dst, const int64_t* ext, int64
     boxed_run(b, st, 0, b.npass);
 }
 
-// Keep rule for entry times (lo, hi], expressed in the kernels' distance form:
-// distances in cells scale by su, and a face the stencil never reads toward is
-// moved kBig cells away so that it is never the nearest.
+// Keep rule for entry times (lo, hi]: the kernels form entry times from face
+// distances with the per-axis scales of half_axes, and a face the stencil never
+// reads toward is moved kBig cells away so that it never enters first.
 constexpr int64_t kBig = (int64_t)1 << 40;
 
 KeepRule make_keep(const Ap& a, int64_t lo, int64_t hi) {
@@ -245,8 +249,9 @@ KeepRule make_keep(const Ap& a, int64_t lo, int64_t hi) {
     k.enabled = 1;
     k.face_axis = -1;
     k.face_side = -1;
-    k.lo = lo * a.su;
-    k.hi = hi == LLONG_MAX ? LLONG_MAX : hi * a.su;
+    k.half_axes = a.half_axes;
+    k.lo = lo;
+    k.hi = hi;
     for (int i = 0; i < a.d; ++i) {
         const int64_t off_lo = a.act[i][0] ? 0 : kBig, off_hi = a.act[i][1] ? 0 : kBig;
         k.gdim[i] = a.n[i] + off_lo + off_hi;
@@ -291,8 +296,8 @@ Forked slab_solve(Ap& a, const void* src, void* dst, int64_t w, int64_t steps, i
         // cells attached to this axis' faces lie within half the axis (both faces
         // active) or the whole axis (one) of their face
         const int64_t reach = lo_f && hi_f ? ceil_half(a.n[ax]) : a.n[ax];
-        if (a.su * lo >= reach) continue;  // none of them has an entry time above lo
-        const int64_t ta = std::min(a.su * w, a.n[ax]);
+        if (a.sig[ax] * lo >= reach) continue;  // none of them has an entry time above lo
+        const int64_t ta = std::min(a.sig[ax] * w, a.n[ax]);
         int64_t ext[3];
         for (int k = 0; k < a.d; ++k) ext[k] = k == ax ? ta : a.n[k];
         KeepRule keep = make_keep(a, lo, hi);
@@ -371,10 +376,10 @@ void base_case(Ap& a, const void* src, void* dst, int64_t tau, hipStream_t st) {
     }
     bp.ncoef = m;
     // strips covering entry times <= tau without overlap: face (k, side) covers
-    // wo[k][side] = su * tau cells (0 for an inactive face)
+    // wo[k][side] = sig[k] * tau cells (0 for an inactive face)
     int64_t wo[3][2];
     for (int k = 0; k < a.d; ++k)
-        for (int side = 0; side < 2; ++side) wo[k][side] = a.act[k][side] ? a.su * tau : 0;
+        for (int side = 0; side < 2; ++side) wo[k][side] = a.act[k][side] ? a.sig[k] * tau : 0;
     int64_t first = 0;
     size_t lds = 0;
     int ns = 0;
@@ -567,14 +572,14 @@ Ap make_ap(void* grid, bool f64, int d, const int64_t* dims, const double* coeff
     }
     int64_t sig_max = 0;
     a.inert = true;
-    a.su = 0;
     for (int k = 0; k < 3; ++k) {
         a.sig[k] = k < d ? std::max(toward[k][0], toward[k][1]) : 0;
         for (int side = 0; side < 2; ++side) {
             a.act[k][side] = k < d && toward[k][side] > 0;
             a.inert = a.inert && !a.act[k][side];
-            if (a.act[k][side]) a.su = std::max(a.su, a.sig[k]);
         }
+        if (a.sig[k] > 2) throw Error(-2, "aperiodic reach above 2 cells per step");
+        if (a.sig[k] == 2) a.half_axes |= 1 << k;
         sig_max = std::max(sig_max, a.sig[k]);
     }
     a.maxell = LLONG_MAX;
@@ -583,7 +588,7 @@ Ap make_ap(void* grid, bool f64, int d, const int64_t* dims, const double* coeff
         // the deepest cell along this axis: half way (two active faces) or at the
         // inactive end (one)
         const int64_t depth = a.act[k][0] && a.act[k][1] ? ceil_half(a.n[k]) : a.n[k];
-        a.maxell = std::min(a.maxell, (depth + a.su - 1) / a.su);
+        a.maxell = std::min(a.maxell, (depth + a.sig[k] - 1) / a.sig[k]);
     }
     // base-case reach: the halo sig * cutoff must fit an LDS tile
     const int64_t reach = d == 1 ? 256 : d == 2 ? 16 : 4;

@@ -383,9 +383,14 @@ __device__ __forceinline__ int64_t pick3(const int64_t* a, int i) {
 }
 
 struct RowKeep {
-    int64_t dpre;   // min face distance over axes 0..d-2 (huge if none)
-    int fpre;       // first face (in face order) at that distance
+    int64_t epre;   // min face entry time over axes 0..d-2 (huge if none)
+    int fpre;       // first face (in face order) with that entry time
 };
+
+// Entry time of a face at distance dist (1-based) along axis a.
+__device__ __forceinline__ int64_t entry_time(const KeepRule& kr, int a, int64_t dist) {
+    return ((kr.half_axes >> a) & 1) ? (dist + 1) >> 1 : dist;
+}
 
 __device__ __forceinline__ RowKeep keep_row(const KeepRule& kr, int d, int64_t b, const int64_t* i) {
     RowKeep rk{INT64_MAX, -1};
@@ -393,9 +398,9 @@ __device__ __forceinline__ RowKeep keep_row(const KeepRule& kr, int d, int64_t b
     for (int a = 0; a < 2; ++a) {
         if (a < d - 1) {
             const int64_t g = kr.gorg[a] + b * kr.gbstep[a] + i[a];
-            const int64_t lo = g + 1, hi = kr.gdim[a] - g;
-            if (lo < rk.dpre) { rk.dpre = lo; rk.fpre = 2 * a; }
-            if (hi < rk.dpre) { rk.dpre = hi; rk.fpre = 2 * a + 1; }
+            const int64_t lo = entry_time(kr, a, g + 1), hi = entry_time(kr, a, kr.gdim[a] - g);
+            if (lo < rk.epre) { rk.epre = lo; rk.fpre = 2 * a; }
+            if (hi < rk.epre) { rk.epre = hi; rk.fpre = 2 * a + 1; }
         }
     }
     return rk;
@@ -405,12 +410,12 @@ __device__ __forceinline__ RowKeep keep_row(const KeepRule& kr, int d, int64_t b
 __device__ __forceinline__ bool keep_last(const KeepRule& kr, const RowKeep& rk, int d, int64_t b, int64_t m) {
     const int L = d - 1;
     const int64_t g = pick3(kr.gorg, L) + b * pick3(kr.gbstep, L) + m;
-    const int64_t lo = g + 1, hi = pick3(kr.gdim, L) - g;
-    int64_t dist = rk.dpre;
+    const int64_t lo = entry_time(kr, L, g + 1), hi = entry_time(kr, L, pick3(kr.gdim, L) - g);
+    int64_t ell = rk.epre;
     int first = rk.fpre;
-    if (lo < dist) { dist = lo; first = 2 * L; }
-    if (hi < dist) { dist = hi; first = 2 * L + 1; }
-    if (!(dist > kr.lo && dist <= kr.hi)) return false;
+    if (lo < ell) { ell = lo; first = 2 * L; }
+    if (hi < ell) { ell = hi; first = 2 * L + 1; }
+    if (!(ell > kr.lo && ell <= kr.hi)) return false;
     if (kr.face_axis < 0) return true;
     if (first / 2 != kr.face_axis) return false;
     const int side = kr.face_side == 2 ? (int)b : kr.face_side;
@@ -418,12 +423,12 @@ __device__ __forceinline__ bool keep_last(const KeepRule& kr, const RowKeep& rk,
 }
 
 // May any cell of a row along the last axis pass keep_last?  False only when none
-// can: every cell's distance is at most dpre, and a last-axis face is the first
-// face only when it is strictly nearer than dpre.
+// can: every cell's entry time is at most epre, and a last-axis face is the first
+// face only when its entry time is strictly below epre.
 __device__ __forceinline__ bool row_may_keep(const KeepRule& kr, const RowKeep& rk, int d, int64_t b) {
-    if (rk.dpre <= kr.lo) return false;
+    if (rk.epre <= kr.lo) return false;
     if (kr.face_axis >= 0 && kr.face_axis != d - 1) {
-        if (rk.dpre > kr.hi) return false;
+        if (rk.epre > kr.hi) return false;
         if (rk.fpre / 2 != kr.face_axis) return false;
         const int side = kr.face_side == 2 ? (int)b : kr.face_side;
         if (side >= 0 && (rk.fpre & 1) != side) return false;

@@ -349,14 +349,16 @@ __device__ __forceinline__ void frow_tile(const PassDesc& pd, const SymParams& s
     const RowKeep rk = keep_row(pd.keep, pd.d, b, ii);
     // A slab whose face axis is not the last axis keeps, in a row that reaches
     // this point (row_may_keep held), exactly the cells whose last-axis faces
-    // are no nearer than dpre: one interval [mlo, mhi] of the row.
+    // enter no earlier than epre: one interval [mlo, mhi] of the row.
     const bool interval = KIND == ROW_C2R && pd.keep.enabled && pd.keep.face_axis >= 0 && pd.keep.face_axis != pd.d - 1;
     int64_t mlo = 0, mhi = -1;
     if (interval) {
         const int la = pd.d - 1;
         const int64_t goff = pick3(pd.keep.gorg, la) + b * pick3(pd.keep.gbstep, la);
-        mlo = rk.dpre - 1 - goff;
-        mhi = pick3(pd.keep.gdim, la) - rk.dpre - goff;
+        // entry time >= epre along the last axis: distance above s (epre - 1) from both faces
+        const int64_t s = 1 + ((pd.keep.half_axes >> la) & 1);
+        mlo = s * (rk.epre - 1) - goff;
+        mhi = pick3(pd.keep.gdim, la) - s * (rk.epre - 1) - 1 - goff;
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) {

@@ -335,8 +335,10 @@ __device__ __forceinline__ void mrow_tile(const PassDesc& pd, const SymParams& s
     if (interval) {
         const int la = pd.d - 1;
         const int64_t goff = pick3(pd.keep.gorg, la) + b * pick3(pd.keep.gbstep, la);
-        mlo = rk.dpre - 1 - goff;
-        mhi = pick3(pd.keep.gdim, la) - rk.dpre - goff;
+        // entry time >= epre along the last axis: distance above s (epre - 1) from both faces
+        const int64_t s = 1 + ((pd.keep.half_axes >> la) & 1);
+        mlo = s * (rk.epre - 1) - goff;
+        mhi = pick3(pd.keep.gdim, la) - s * (rk.epre - 1) - 1 - goff;
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {

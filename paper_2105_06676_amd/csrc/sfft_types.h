@@ -47,16 +47,18 @@ struct RealView {
     int64_t ext[3];       // cells at index >= ext along an axis read as zero and are never written
 };
 
-// Which output cells the last pass stores (Sec. 4 region bookkeeping).
-// dist(g) = 1 + min over faces of the index distance of global interior cell g to
-// the frame.  A cell is stored iff lo < dist <= hi and, when face_axis >= 0, the
-// first face (axis 0 low, axis 0 high, axis 1 low, ...) at distance dist is the
-// slab's own face.
+// Which output cells the last pass stores (Sec. 4 region bookkeeping, with the
+// entry times of the appendix on l-shells).  A face at index distance dist_f - 1
+// from global interior cell g enters it after ell_f = ceil(dist_f / s_a) steps,
+// s_a the stencil's reach per step along the face's axis a (1 or 2: 2 for the axes
+// in half_axes); ell(g) = min over faces.  A cell is stored iff lo < ell <= hi
+// and, when face_axis >= 0, the first face (axis 0 low, axis 0 high, axis 1 low,
+// ...) with that entry time is the slab's own face.
 struct KeepRule {
     int enabled;
     int face_axis;        // -1: no face test
     int face_side;        // 0 low, 1 high, -1 either side, 2 = the batch index
-    int pad_;
+    int half_axes;        // bit a: entry time along axis a is ceil(dist / 2)
     int64_t lo, hi;
     int64_t gdim[3];      // interior extents
     int64_t gorg[3];      // global coordinate of local cell 0 of batch item 0

@@ -156,6 +156,11 @@ BIASED = [
     ("radius2_reach1_2d", (70, 60), ([(-1, 0), (1, 0), (0, -1), (0, 1), (0, 0)], 2, 2), 50, 0),
     ("upwind_3d", (20, 18, 16), ([(-1, 0, 0), (0, -1, 0), (0, 0, -1), (0, 0, 0)], 1, 3), 24, 0),
     ("axis2_only_3d", (12, 10, 40), ([(0, 0, -1), (0, 0, 1), (0, 0, 0)], 1, 3), 30, 2),
+    # reach differs between axes: per-axis entry times (2 cells per step along one axis)
+    ("reach2_axis0_reach1_axis1", (150, 130), ([(-2, 0), (2, 0), (0, -1), (0, 1), (0, 0)], 2, 2), 70, 0),
+    ("reach1_axis0_reach2_axis1", (90, 160), ([(-1, 0), (1, 0), (0, -2), (0, 2), (0, 0), (1, 1)], 2, 2), 45, 3),
+    ("reach_2_1_1_3d", (30, 24, 20), ([(-2, 0, 0), (2, 0, 0), (0, -1, 0), (0, 0, 1), (0, 0, 0)], 2, 3), 14, 1),
+    ("upwind_reach2_axis1_2d", (64, 120), ([(0, -2), (0, -1), (-1, 0), (0, 0)], 2, 2), 40, 2),
 ]
 
 

@@ -98,6 +98,8 @@ BIASED = [
     ("downwind_2d", (90, 110), [(1, 0), (0, 1), (0, 0), (1, 1)], 1, 45, 3),
     ("radius2_reach1_2d", (70, 60), [(-1, 0), (1, 0), (0, -1), (0, 1), (0, 0)], 2, 50, 0),
     ("axis2_only_3d", (12, 10, 40), [(0, 0, -1), (0, 0, 1), (0, 0, 0)], 1, 30, 2),
+    ("reach2_axis0_reach1_axis1", (150, 130), [(-2, 0), (2, 0), (0, -1), (0, 1), (0, 0)], 2, 70, 0),
+    ("reach_2_1_1_3d", (30, 24, 20), [(-2, 0, 0), (2, 0, 0), (0, -1, 0), (0, 0, 1), (0, 0, 0)], 2, 14, 1),
 ]
 
 

@@ -4,11 +4,14 @@ in place of the GPU's slab solves and base case must reproduce the aperiodic
 loop bit for bit.
 
 The executor below is test harness code, not a CPU path of the product: it
-restates the plan (interior kept at dist > rT; RB(T) = base case for T <= cutoff,
-else step 1 = slabs of band (0, 2rT] over T1 = floor(T/2) steps kept on
-(rT1, rT + rT2] plus RB(T1); step 2 = slabs of band (0, rT + rT2] over T2 steps
-kept on (rT2, rT] plus RB(T2); each cell taken from the slab of its nearest
-face, slabs zero-padded to 7-smooth extents) so that the reading itself is pinned.
+restates the plan in entry times (a face of axis k enters a cell at distance dist
+after ceil(dist / reach_k) steps; ell = min over the faces the stencil reads
+toward; interior kept at ell > T; RB(T) = base case for T <= cutoff, else
+step 1 = slabs of band (0, 2T] over T1 = floor(T/2) steps kept on (T1, T + T2]
+plus RB(T1); step 2 = slabs of band (0, T + T2] over T2 steps kept on (T2, T]
+plus RB(T2); a slab of axis k is reach_k cells deep per step of entry time; each
+cell taken from the slab of the face that enters it first, slabs zero-padded to
+7-smooth extents) so that the reading itself is pinned.
 """
 import numpy as np
 import pytest
@@ -32,34 +35,53 @@ def _rb_execute(a, c, r, T, cutoff):
     d = a.ndim
     n = [s - 2 * r for s in a.shape]
     inner = tuple(slice(r, r + x) for x in n)
-    maxdist = min((x + 1) // 2 for x in n)
+    # reach per axis and the faces the stencil reads toward
+    nz = [tuple(i - r for i in idx) for idx in np.ndindex(*c.shape) if c[idx] != 0]
+    reach = [max([abs(o[k]) for o in nz] + [0]) for k in range(d)]
+    act = [[any(o[k] < 0 for o in nz), any(o[k] > 0 for o in nz)] for k in range(d)]
+    big = 1 << 40
 
-    def faces(g):
-        fd = []
+    def ent(g):
+        """(first face, entry time): ceil(distance / reach) per face, min over the
+        active faces in face order (axis 0 low, axis 0 high, axis 1 low, ...)."""
+        best, face = big, -1
         for k in range(d):
-            fd += [g[k] + 1, n[k] - g[k]]
-        dd = min(fd)
-        return fd.index(dd), dd
+            for side in (0, 1):
+                if not act[k][side]:
+                    continue
+                dist = g[k] + 1 if side == 0 else n[k] - g[k]
+                e = -(-dist // reach[k])
+                if e < best:
+                    best, face = e, 2 * k + side
+        return face, best
+
+    depth = [(-(-n[k] // 2) if act[k][0] and act[k][1] else n[k]) for k in range(d)]
+    maxell = min([-(-depth[k] // reach[k]) for k in range(d) if act[k][0] or act[k][1]] + [big])
 
     def slabs(src, dst, w, steps, lo, hi):
-        if lo >= maxdist or hi <= lo:
+        if lo >= maxell or hi <= lo:
             return
         for ax in range(d):
-            ta = min(w, n[ax])
+            if not (act[ax][0] or act[ax][1]) or reach[ax] * lo >= depth[ax]:
+                continue
+            ta = min(reach[ax] * w, n[ax])
             ext = [ta if k == ax else n[k] for k in range(d)]
-            sides = [0, 1] if ta < n[ax] else [-1]
+            if ta >= n[ax]:
+                sides = [-1]
+            else:
+                sides = [s_ for s_ in (0, 1) if act[ax][s_]]
             for side in sides:
                 org = [0] * d
                 if side == 1:
                     org[ax] = n[ax] - ta
                 box = src[tuple(slice(r + o, r + o + e) for o, e in zip(org, ext))]
-                big = np.zeros([_pad7(e) for e in ext])
-                big[tuple(slice(0, e) for e in ext)] = box
-                res = oracle.periodic(big, c, steps)
+                big_box = np.zeros([_pad7(e) for e in ext])
+                big_box[tuple(slice(0, e) for e in ext)] = box
+                res = oracle.periodic(big_box, c, steps)
                 for idx in np.ndindex(*ext):
                     g = [o + i for o, i in zip(org, idx)]
-                    f, dd = faces(g)
-                    if lo < dd <= hi and f // 2 == ax and (side < 0 or (f & 1) == side):
+                    f, e = ent(g)
+                    if lo < e <= hi and f // 2 == ax and (side < 0 or (f & 1) == side):
                         dst[tuple(r + x for x in g)] = res[idx]
 
     def base(src, dst, tau):
@@ -67,7 +89,7 @@ def _rb_execute(a, c, r, T, cutoff):
         fr[inner] = src[inner]
         res = oracle.aperiodic(fr, c, tau)
         for idx in np.ndindex(*n):
-            if faces(idx)[1] <= r * tau:
+            if ent(idx)[1] <= tau:
                 g = tuple(r + i for i in idx)
                 dst[g] = res[g]
 
@@ -78,9 +100,9 @@ def _rb_execute(a, c, r, T, cutoff):
         T1 = T // 2
         T2 = T - T1
         mid = np.full_like(a, np.nan)
-        slabs(src, mid, 2 * r * T, T1, r * T1, r * T + r * T2)
+        slabs(src, mid, 2 * T, T1, T1, T + T2)
         rb(src, mid, T1)
-        slabs(mid, dst, r * T + r * T2, T2, r * T2, r * T)
+        slabs(mid, dst, T + T2, T2, T2, T)
         rb(mid, dst, T2)
 
     out = a.copy()
@@ -89,8 +111,34 @@ def _rb_execute(a, c, r, T, cutoff):
     rb(a, band, T)
     for idx in np.ndindex(*n):
         g = tuple(r + i for i in idx)
-        out[g] = per[idx] if faces(idx)[1] > r * T else band[g]
+        out[g] = per[idx] if ent(idx)[1] > T else band[g]
     return out
+
+
+def _offsets_stencil(offs, r, d, seed):
+    c = np.zeros((2 * r + 1,) * d)
+    w = wl.uniform(seed, "coef", len(offs)) + 0.1
+    for o, x in zip(offs, w / w.sum()):
+        c[tuple(oi + r for oi in o)] = x
+    return c
+
+
+@pytest.mark.parametrize("dims,offs,r,T,cutoff", [
+    ((31,), [(-2,), (-1,), (0,)], 2, 9, 1),                                       # upwind, reach 2
+    ((26, 22), [(-2, 0), (2, 0), (0, -1), (0, 1), (0, 0)], 2, 7, 1),             # reach 2 / 1
+    ((20, 24), [(-2, 0), (-1, -1), (0, 0), (1, 1), (0, 1)], 2, 6, 1),            # biased, reach 2 / 1
+    ((12, 14, 10), [(0, -2, 0), (0, 2, 0), (-1, 0, 0), (0, 0, 1), (0, 0, 0)], 2, 5, 1),
+])
+def test_per_axis_entry_times_reproduce_loop(dims, offs, r, T, cutoff):
+    """Stencils whose reach differs between axes: bands, slabs and base-case strips
+    scale per axis (ceil(distance / reach)), and the result is still the loop's."""
+    d = len(dims)
+    c = _offsets_stencil(offs, r, d, 60 + T)
+    store = tuple(x + 2 * r for x in dims)
+    a = wl.uniform(61 + T, "grid", int(np.prod(store))).reshape(store)
+    ref = oracle.aperiodic(a, c, T)
+    got = _rb_execute(a, c, r, T, cutoff)
+    assert np.array_equal(got, ref)
 
 
 @pytest.mark.parametrize("dims,r,T,cutoff", [((10,), 1, 2, 1), ((23,), 2, 9, 1), ((13, 29), 1, 17, 3),
