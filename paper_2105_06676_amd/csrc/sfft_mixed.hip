@@ -450,12 +450,21 @@ __device__ __forceinline__ int batch_find_m(const BatchItem* it, int n, uint32_t
     return lo;
 }
 
+// Waves per SIMD the row kernels are compiled for.  A long row is one workgroup
+// of L / Q threads; at 10 FP32 points per thread the unconstrained kernels take
+// about 110 VGPRs, four waves per SIMD, so only two 7-wave rows fit a CU.  Six
+// waves per SIMD (80 VGPRs, a few words of spill) fit three.
+template <typename R, int KIND, int Q>
+constexpr int mrow_waves() { return (sizeof(R) == 4 && Q == 10 && KIND != ROW_MIDR) ? 6 : 1; }
+
 template <typename R, int KIND, int Q, int RL>
-__global__ __launch_bounds__(kMRowThreads) void k_mrow(PassDesc pd, SymParams sp) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, kMRowThreads), amdgpu_waves_per_eu(mrow_waves<R, KIND, Q>())))
+void k_mrow(PassDesc pd, SymParams sp) {
     mrow_tile<R, KIND, Q, RL>(pd, sp, blockIdx.x);
 }
 template <typename R, int KIND, int Q, int RL>
-__global__ __launch_bounds__(kMRowThreads) void k_mrow_b(const BatchItem* it, int n, const SymParams* sy) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, kMRowThreads), amdgpu_waves_per_eu(mrow_waves<R, KIND, Q>())))
+void k_mrow_b(const BatchItem* it, int n, const SymParams* sy) {
     const int i = batch_find_m(it, n, blockIdx.x);
     mrow_tile<R, KIND, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
 }
