@@ -468,12 +468,19 @@ void k_mrow_b(const BatchItem* it, int n, const SymParams* sy) {
     const int i = batch_find_m(it, n, blockIdx.x);
     mrow_tile<R, KIND, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
 }
+// The 20- and 25-point FP32 fused middle passes take about 190 VGPRs unconstrained
+// (two waves per SIMD); three waves per SIMD fit one more workgroup per CU.
+template <typename R, int MODE, int Q>
+constexpr int mcol_waves() { return (sizeof(R) == 4 && Q >= 20 && MODE == MODE_MID) ? 3 : 1; }
+
 template <typename R, int MODE, int Q, int RL>
-__global__ __launch_bounds__(kMColThreads) void k_mcol(PassDesc pd, SymParams sp) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, kMColThreads), amdgpu_waves_per_eu(mcol_waves<R, MODE, Q>())))
+void k_mcol(PassDesc pd, SymParams sp) {
     mcol_tile<R, MODE, Q, RL>(pd, sp, blockIdx.x);
 }
 template <typename R, int MODE, int Q, int RL>
-__global__ __launch_bounds__(kMColThreads) void k_mcol_b(const BatchItem* it, int n, const SymParams* sy) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, kMColThreads), amdgpu_waves_per_eu(mcol_waves<R, MODE, Q>())))
+void k_mcol_b(const BatchItem* it, int n, const SymParams* sy) {
     const int i = batch_find_m(it, n, blockIdx.x);
     mcol_tile<R, MODE, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
 }
