@@ -305,7 +305,11 @@ def time_solve(sfft, torch, w, dtype, reps=5, warmup=1):
         def fn(g, c, T):
             return sfft.periodic_implicit(g, w.implicit_q, c, T)
     else:
-        fn = sfft.aperiodic if w.aperiodic else (sfft.periodic_fields if w.fields > 1 else sfft.periodic)
+        if w.aperiodic:
+            def fn(g, c, T):
+                return sfft.aperiodic(g, c, T, bc=w.bc)
+        else:
+            fn = sfft.periodic_fields if w.fields > 1 else sfft.periodic
     for _ in range(warmup):
         fn(grid, w.coeffs, w.T)
     ts = []
@@ -330,7 +334,8 @@ def other_workloads(sfft, torch, only=None, reps=5, warmup=1):
     import workloads as wl
     out = {}
     for name, dts in (("heat1d_65536", ("f64",)), ("star3d_512", ("f32",)),
-                      ("box2d_aperiodic_4096", ("f64", "f32")), ("upwind2d_aperiodic_4096", ("f64", "f32")),
+                      ("box2d_aperiodic_4096", ("f64", "f32")), ("box2d_reflect_4096", ("f64", "f32")),
+                      ("upwind2d_aperiodic_4096", ("f64", "f32")),
                       ("wave2d_leapfrog_4096", ("f32", "f64")),
                       ("heat2d_backward_euler_4096", ("f32", "f64")), ("jacobi2d_6300x6720_smooth", ("f32",)),
                       ("jacobi2d_8000_smooth", ("f32", "f64")), ("heat3d_800_smooth", ("f32",)),

@@ -179,3 +179,28 @@ def test_reflect_rejects_bad_arguments():
         sfft.aperiodic(g, c, 3, bc="reflect")
     with pytest.raises(ValueError):
         sfft.aperiodic(to_dev(np.zeros(9), "f64"), c, 3, bc="mirror")
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_reflect_4096_full_size_sampled(dtype):
+    """Full 4096^2, T = 512, reflecting frame: two corners and an edge strip against
+    the oracle run on sub-boxes of the stored array that hold each checked cell's
+    whole r*T dependency cone (a box's cut edges, reflecting in the oracle run, lie
+    more than r*T cells from every checked cell; Sec. 4)."""
+    w = wl.config("box2d_reflect_4096")
+    a = w.grid()
+    got = gpu_reflect(a, w.coeffs, w.T, dtype)
+    src = rounded_input(a, dtype)
+    s, K, n = w.radius * w.T, 128, w.dims[0]
+    box = src[: K + s + 2, : K + s + 2]
+    ref = oracle.aperiodic(box, w.coeffs, w.T, bc="reflect")
+    assert_close(got[1:K + 1, 1:K + 1], ref[1:K + 1, 1:K + 1], TOL[dtype])
+    box = src[-(K + s + 2):, -(K + s + 2):]
+    ref = oracle.aperiodic(box, w.coeffs, w.T, bc="reflect")
+    assert_close(got[-(K + 1):-1, -(K + 1):-1], ref[-(K + 1):-1, -(K + 1):-1], TOL[dtype])
+    c0, h = n // 2, K // 2
+    box = src[: 2 * s + h + 2, c0 - h - s: c0 + h + s + 2]
+    ref = oracle.aperiodic(box, w.coeffs, w.T, bc="reflect")
+    rows = slice(1, 1 + s + h)
+    assert_close(got[rows, c0 - h + 1: c0 + h + 1], ref[rows, s + 1: s + 1 + K], TOL[dtype])

@@ -116,6 +116,7 @@ class Workload:
     notes: str = ""
     fields: int = 1                # coupled fields (coeffs then (m, m) + (2r+1,)*ndim)
     implicit_q: Optional[np.ndarray] = None  # implicit update Q a_{t+1} = S a_t (coeffs = S)
+    bc: str = "fixed"              # aperiodic boundary: "fixed" frame or "reflect" (zero flux)
 
     @property
     def storage_dims(self) -> Tuple[int, ...]:
@@ -215,6 +216,10 @@ def config(name: str) -> Workload:
         return Workload("box2d_aperiodic_4096", 2, (4096, 4096), 1, 512, box_random_coeffs(4, 2, 1), 4,
                         "uniform", aperiodic=True, dtypes=("f64", "f32"),
                         notes="2-D aperiodic 9-point box, fixed frame")
+    if name == "box2d_reflect_4096":
+        return Workload("box2d_reflect_4096", 2, (4096, 4096), 1, 512, box_random_coeffs(4, 2, 1), 4,
+                        "uniform", aperiodic=True, dtypes=("f64", "f32"), bc="reflect",
+                        notes="2-D aperiodic 9-point box, reflecting (zero-flux) frame")
     if name == "upwind2d_aperiodic_4096":
         c = np.zeros((3, 3), dtype=np.float64)
         c[1, 1], c[0, 1], c[1, 0] = 0.5, 0.25, 0.25
