@@ -124,6 +124,59 @@ struct RootTab<25> {
                                      -0.6845471059286887, -0.48175367410171527, -0.2486898871648548};
 };
 
+template <>
+struct RootTab<14> {
+    static constexpr double c[14] = {1.0, 0.9009688679024191, 0.6234898018587335,
+                                     0.2225209339563144, -0.2225209339563144,
+                                     -0.6234898018587335, -0.9009688679024191, -1.0,
+                                     -0.9009688679024191, -0.6234898018587335,
+                                     -0.2225209339563144, 0.2225209339563144,
+                                     0.6234898018587335, 0.9009688679024191};
+    static constexpr double s[14] = {0.0, 0.4338837391175581, 0.7818314824680298,
+                                     0.9749279121818236, 0.9749279121818236, 0.7818314824680298,
+                                     0.4338837391175581, 0.0, -0.4338837391175581,
+                                     -0.7818314824680298, -0.9749279121818236,
+                                     -0.9749279121818236, -0.7818314824680298,
+                                     -0.4338837391175581};
+};
+template <>
+struct RootTab<15> {
+    static constexpr double c[15] = {1.0, 0.9135454576426009, 0.6691306063588582,
+                                     0.30901699437494745, -0.10452846326765347, -0.5,
+                                     -0.8090169943749475, -0.9781476007338057,
+                                     -0.9781476007338057, -0.8090169943749475, -0.5,
+                                     -0.10452846326765347, 0.30901699437494745,
+                                     0.6691306063588582, 0.9135454576426009};
+    static constexpr double s[15] = {0.0, 0.4067366430758002, 0.7431448254773942,
+                                     0.9510565162951535, 0.9945218953682733, 0.8660254037844386,
+                                     0.5877852522924731, 0.20791169081775934,
+                                     -0.20791169081775934, -0.5877852522924731,
+                                     -0.8660254037844386, -0.9945218953682733,
+                                     -0.9510565162951535, -0.7431448254773942,
+                                     -0.4067366430758002};
+};
+template <>
+struct RootTab<21> {
+    static constexpr double c[21] = {1.0, 0.9555728057861407, 0.8262387743159949,
+                                     0.6234898018587335, 0.36534102436639504,
+                                     0.07473009358642425, -0.2225209339563144, -0.5,
+                                     -0.7330518718298263, -0.9009688679024191,
+                                     -0.9888308262251285, -0.9888308262251285,
+                                     -0.9009688679024191, -0.7330518718298263, -0.5,
+                                     -0.2225209339563144, 0.07473009358642425,
+                                     0.36534102436639504, 0.6234898018587335,
+                                     0.8262387743159949, 0.9555728057861407};
+    static constexpr double s[21] = {0.0, 0.2947551744109042, 0.5633200580636221,
+                                     0.7818314824680298, 0.9308737486442042, 0.9972037971811801,
+                                     0.9749279121818236, 0.8660254037844386, 0.6801727377709194,
+                                     0.4338837391175581, 0.14904226617617444,
+                                     -0.14904226617617444, -0.4338837391175581,
+                                     -0.6801727377709194, -0.8660254037844386,
+                                     -0.9749279121818236, -0.9972037971811801,
+                                     -0.9308737486442042, -0.7818314824680298,
+                                     -0.5633200580636221, -0.2947551744109042};
+};
+
 template <typename R, bool INV>
 __device__ __forceinline__ void dft2(cx<R>* v) {
     cx<R> a = v[0], b = v[1];
@@ -252,7 +305,10 @@ __device__ __forceinline__ void dft(cx<R>* v) {
     else if constexpr (RAD == 6) dft_ab<R, 3, 2, INV>(v);
     else if constexpr (RAD == 10) dft_ab<R, 5, 2, INV>(v);
     else if constexpr (RAD == 12) dft_ab<R, 4, 3, INV>(v);
+    else if constexpr (RAD == 14) dft_ab<R, 7, 2, INV>(v);
+    else if constexpr (RAD == 15) dft_ab<R, 5, 3, INV>(v);
     else if constexpr (RAD == 20) dft_ab<R, 4, 5, INV>(v);
+    else if constexpr (RAD == 21) dft_ab<R, 7, 3, INV>(v);
     else if constexpr (RAD == 25) dft_ab<R, 5, 5, INV>(v);
     else dft_odd<R, RAD, INV>(v);
 }

@@ -53,7 +53,13 @@ struct MColIdx {
 template <typename R, int Q, int RAD, bool INV, bool FIRST, bool LAST, typename IDX>
 __device__ __forceinline__ void mstage(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, int P, int L, int NS,
                                        const cx<R>* tab, int tmul) {
-    constexpr int NB = Q / RAD;
+    // A middle stage whose radix does not divide Q spreads its L / RAD butterflies
+    // over the P threads unevenly: NB = ceil(Q / RAD) per thread, the last ones
+    // guarded.  The first and the last stage hold the point registers and need
+    // RAD | Q.
+    constexpr bool EXACT = Q % RAD == 0;
+    static_assert(EXACT || (!FIRST && !LAST), "register stages need a radix dividing Q");
+    constexpr int NB = (Q + RAD - 1) / RAD;
     const int span = L / RAD;
     cx<R> w[NB][RAD];
     const UDiv dns = udiv((uint32_t)NS);
@@ -67,12 +73,17 @@ __device__ __forceinline__ void mstage(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int j = q + P * b;
+            if (!EXACT && j >= span) {
+#pragma unroll
+                for (int t = 0; t < RAD; ++t) w[b][t] = cx<R>{R(0), R(0)};
+                continue;
+            }
 #pragma unroll
             for (int t = 0; t < RAD; ++t) w[b][t] = lds[idx(j + t * span)];
             uint32_t jq;
             const int k = (int)udiv_qr((uint32_t)j, dns, &jq);
             const cx<R> w1 = tab[k * step];
-            if constexpr (RAD <= 5) {
+            if constexpr (RAD <= 5 || RAD == 7) {
                 cx<R> wt = w1;
 #pragma unroll
                 for (int t = 1; t < RAD; ++t) {
@@ -82,7 +93,7 @@ __device__ __forceinline__ void mstage(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q
             } else {
                 // w1^t for t = a BS + c as (w1^BS)^a w1^c, both factors by short
                 // product chains from two table entries (a few roundings, not RAD)
-                constexpr int BS = RAD % 5 == 0 ? 5 : (RAD % 4 == 0 ? 4 : 3);
+                constexpr int BS = RAD % 7 == 0 ? 7 : (RAD % 5 == 0 ? 5 : (RAD % 4 == 0 ? 4 : 3));
                 const cx<R> wb = tab[k * BS * step];
                 cx<R> lo[BS];
                 lo[0] = cx<R>{R(1), R(0)};
@@ -110,6 +121,7 @@ __device__ __forceinline__ void mstage(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
             const int j = q + P * b;
+            if (!EXACT && j >= span) continue;
             uint32_t jq;
             const int k = (int)udiv_qr((uint32_t)j, dns, &jq);
             const int d = (int)jq * NS * RAD + k;
@@ -126,22 +138,32 @@ __device__ __forceinline__ void mstage(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q
     }
 }
 
+// Middle stages: the radices that divide Q, and for the families that mix 3, 5
+// and 7 (Q = 12, 14, 15, 21) also 2, 3, 4, 5 and 7 with guarded butterflies.
 template <typename R, int Q, bool INV, bool FIRST, bool LAST, typename IDX>
 __device__ __forceinline__ void mstage_rad(int rad, cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, int P, int L, int NS,
                                            const cx<R>* tab, int tmul) {
 #define SFFT_MST(RAD)                                                                                      if constexpr (Q % RAD == 0) mstage<R, Q, RAD, INV, FIRST, LAST>(v, lds, idx, q, P, L, NS, tab, tmul);
+#define SFFT_MSTG(RAD)                                                                                     \
+    if constexpr (Q % RAD == 0 || Q == 12 || Q == 14 || Q == 15 || Q == 21)                                \
+        mstage<R, Q, RAD, INV, FIRST, LAST>(v, lds, idx, q, P, L, NS, tab, tmul);
     switch (rad) {
-        case 2: SFFT_MST(2) break;
-        case 3: SFFT_MST(3) break;
-        case 4: SFFT_MST(4) break;
-        case 5: SFFT_MST(5) break;
+        case 2: SFFT_MSTG(2) break;
+        case 3: SFFT_MSTG(3) break;
+        case 4: SFFT_MSTG(4) break;
+        case 5: SFFT_MSTG(5) break;
+        case 7: SFFT_MSTG(7) break;
         case 6: SFFT_MST(6) break;
         case 10: SFFT_MST(10) break;
         case 12: SFFT_MST(12) break;
+        case 14: SFFT_MST(14) break;
+        case 15: SFFT_MST(15) break;
         case 20: SFFT_MST(20) break;
+        case 21: SFFT_MST(21) break;
         default: SFFT_MST(25) break;
     }
 #undef SFFT_MST
+#undef SFFT_MSTG
 }
 
 // Stage lists (the planner's canonical order): the first stage has radix Q (a
@@ -538,12 +560,21 @@ hipError_t launch_m(const PassDesc& pd, const SymParams& sp, size_t lds, hipStre
     if (pd.mq == 12 && rl == 12) return launch_q<R, 12, 12>(pd, sp, lds, st, ba);
     if (pd.mq == 12 && rl == 2) return launch_q<R, 12, 2>(pd, sp, lds, st, ba);
     if (pd.mq == 12 && rl == 3) return launch_q<R, 12, 3>(pd, sp, lds, st, ba);
+    if (pd.mq == 14 && rl == 14) return launch_q<R, 14, 14>(pd, sp, lds, st, ba);
+    if (pd.mq == 14 && rl == 2) return launch_q<R, 14, 2>(pd, sp, lds, st, ba);
+    if (pd.mq == 14 && rl == 7) return launch_q<R, 14, 7>(pd, sp, lds, st, ba);
+    if (pd.mq == 15 && rl == 15) return launch_q<R, 15, 15>(pd, sp, lds, st, ba);
+    if (pd.mq == 15 && rl == 3) return launch_q<R, 15, 3>(pd, sp, lds, st, ba);
+    if (pd.mq == 15 && rl == 5) return launch_q<R, 15, 5>(pd, sp, lds, st, ba);
     if constexpr (sizeof(R) == 4) {
         if (pd.mq == 20 && rl == 20) return launch_q<R, 20, 20>(pd, sp, lds, st, ba);
         if (pd.mq == 20 && rl == 2) return launch_q<R, 20, 2>(pd, sp, lds, st, ba);
         if (pd.mq == 20 && rl == 5) return launch_q<R, 20, 5>(pd, sp, lds, st, ba);
         if (pd.mq == 25 && rl == 25) return launch_q<R, 25, 25>(pd, sp, lds, st, ba);
         if (pd.mq == 25 && rl == 5) return launch_q<R, 25, 5>(pd, sp, lds, st, ba);
+        if (pd.mq == 21 && rl == 21) return launch_q<R, 21, 21>(pd, sp, lds, st, ba);
+        if (pd.mq == 21 && rl == 3) return launch_q<R, 21, 3>(pd, sp, lds, st, ba);
+        if (pd.mq == 21 && rl == 7) return launch_q<R, 21, 7>(pd, sp, lds, st, ba);
     }
     return hipErrorInvalidValue;
 }

@@ -49,42 +49,39 @@ static bool radix_list(int64_t L, int* out, int* nst) {
 
 static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
-// Stage list of a length L = Q^k * rest with Q points per thread: radix Q first,
-// radix Q last when k >= 2, the rest as the fewest proper divisors of Q in
-// between; with k = 1 the last radix is a 2 when an even radix remains (a middle
-// radix that holds one is split if needed), else the family's odd prime.
-static bool mixed_stages(int64_t L, int q, std::vector<int>* out) {
-    int64_t rest = L;
-    int kq = 0;
-    while (rest % q == 0) { rest /= q; ++kq; }
-    if (kq == 0) return false;
-    std::vector<int> mid;
-    for (int dv : {12, 10, 6, 5, 4, 3, 2}) {
-        if (dv >= q || q % dv) continue;
-        while (rest % dv == 0) { mid.push_back(dv); rest /= dv; }
+// Stage list of a length L with Q points per thread (Q | L): radix Q first; radix Q
+// last when Q^2 | L, else the largest prime of Q that divides L / Q (none: no
+// list); the rest in between as the fewest radices, largest first, from the
+// proper divisors of Q and (general: the families mixing 3, 5 and 7) the primes
+// 2..7 with 4 — a middle radix that does not divide Q spreads its butterflies
+// unevenly over the threads, and the kernels of those families carry the guarded
+// stages for it.
+static bool mixed_stages(int64_t L, int q, bool general, std::vector<int>* out) {
+    if (L % q) return false;
+    int64_t rest = L / q;
+    int last = 0;
+    if (rest % q == 0 && rest > 1) {
+        last = q;
+    } else {
+        for (int p : {7, 5, 3, 2})
+            if (q % p == 0 && rest % p == 0) { last = p; break; }
     }
+    if (last == 0 || rest < last) return false;
+    rest /= last;
+    std::vector<int> cand;
+    for (int dv : {25, 21, 20, 15, 14, 12, 10, 6})
+        if (dv < q && q % dv == 0) cand.push_back(dv);
+    for (int dv : {7, 5, 4, 3, 2})
+        if (general || q % dv == 0) cand.push_back(dv);
+    // Q itself for the inner stages when it divides the rest
+    std::vector<int> mid;
+    while (rest % q == 0 && rest > 1) { mid.push_back(q); rest /= q; }
+    for (int dv : cand)
+        while (rest % dv == 0) { mid.push_back(dv); rest /= dv; }
     if (rest != 1) return false;
     std::vector<int> r{q};
-    if (kq >= 2) {
-        for (int i = 0; i < kq - 2; ++i) r.push_back(q);
-        r.insert(r.end(), mid.begin(), mid.end());
-        r.push_back(q);
-    } else {
-        if (mid.empty()) return false;
-        bool even = false;
-        for (int dv : mid) even = even || dv % 2 == 0;
-        const int last = even ? 2 : (q % 5 == 0 ? 5 : 3);
-        auto it = std::find(mid.begin(), mid.end(), last);
-        if (it != mid.end()) {
-            mid.erase(it);
-        } else {
-            auto jt = std::find_if(mid.begin(), mid.end(), [&](int dv) { return dv % last == 0; });
-            if (jt == mid.end()) return false;
-            *jt /= last;
-        }
-        r.insert(r.end(), mid.begin(), mid.end());
-        r.push_back(last);
-    }
+    r.insert(r.end(), mid.begin(), mid.end());
+    r.push_back(last);
     *out = r;
     return true;
 }
@@ -92,48 +89,52 @@ static bool mixed_stages(int64_t L, int q, std::vector<int>* out) {
 bool mixed_family(int64_t L, bool column, bool f64, int* Q, int64_t* packed, int* nst) {
     if (tunables().no_fast || L < 2) return false;
     int64_t n = L;
-    int e2 = 0, e3 = 0, e5 = 0;
+    int e2 = 0, e3 = 0, e5 = 0, e7 = 0;
     while (n % 2 == 0) { n /= 2; ++e2; }
     while (n % 3 == 0) { n /= 3; ++e3; }
     while (n % 5 == 0) { n /= 5; ++e5; }
+    while (n % 7 == 0) { n /= 7; ++e7; }
     if (n != 1) return false;
-    // Points per thread, most preferred first.  Every stage is one LDS exchange
-    // and the radix-Q stages cover most of the length, so more points per thread
-    // means fewer stages; but a long row is one workgroup of L/Q threads, and at
-    // 20 points (about 200 VGPRs) only two rows fit a CU, as at 10 points (about
-    // 110 VGPRs, twice the threads), so rows prefer 10 (measured equal on
-    // 4000-point rows, faster on short rows where many rows share a
-    // workgroup).  FP64 points take twice the registers: 20 or 25 of them would
-    // run one wave per SIMD.  An option caps the choice, rows and columns
-    // separately.
+    // Points per thread, most preferred first.  Every stage is one LDS exchange and
+    // the radix-Q stages cover most of the length, so more points per thread means
+    // fewer stages; but a long row is one workgroup of L/Q threads, and at 20
+    // points (about 200 VGPRs) only two rows fit a CU, as at 10 points (about 110
+    // VGPRs, twice the threads), so even rows prefer 10 (measured equal on
+    // 4000-point rows, faster on short rows where many rows share a workgroup).
+    // FP64 points take twice the registers: 20, 21 or 25 of them would run one
+    // wave per SIMD.  The 2^a 5^b, 2^a 3^b and 5^b lengths keep their families;
+    // the others take the first of 12, 14, 15, 21, 10 that divides them and leaves
+    // a last radix.  An option caps the choice, rows and columns separately.
     std::vector<int> pref;
-    if (e3 == 0 && e5 >= 1) {
+    bool general = false;
+    if (e3 == 0 && e7 == 0 && e5 >= 1) {
         if (e2 >= 2 && !f64 && column) pref.push_back(20);
         if (e2 >= 1) pref.push_back(10);
         if (e2 == 0 && !f64) pref.push_back(25);
         pref.push_back(5);
-    } else if (e5 == 0 && e3 >= 1 && e2 >= 2) {
+    } else if (e5 == 0 && e7 == 0 && e3 >= 1 && e2 >= 2) {
         pref.push_back(12);
     } else {
-        return false;
+        pref = {12, 14, 15};
+        if (!f64) pref.push_back(21);
+        general = true;
     }
     const int cap = column ? tunables().mixed_col_q : tunables().mixed_row_q;
     std::vector<int> r;
     int q = 0;
     for (int c : pref) {
         if (cap != 0 && c > cap && c != pref.back()) continue;
-        if (mixed_stages(L, c, &r)) { q = c; break; }
+        if (mixed_stages(L, c, general || c == 12, &r)) { q = c; break; }
     }
     if (q == 0) return false;
     const int64_t P = L / q;
     if (P < 1 || P > (column ? 64 : 512) || r.size() < 2 || (int)r.size() * kMRadBits > 64) return false;
     int64_t pk = 0, prod = 1;
     for (size_t i = 0; i < r.size(); ++i) {
-        if (q % r[i]) return false;
         prod *= r[i];
         pk |= (int64_t)r[i] << (kMRadBits * i);
     }
-    if (prod != L) return false;
+    if (prod != L || q % r.back()) return false;
     *Q = q;
     *packed = pk;
     *nst = (int)r.size();

@@ -22,6 +22,13 @@ SHAPES = [
     (640,),           # 1-D whole solve, L = 320 = 2^6 * 5
     (1536,),          # 1-D whole solve, L = 768 = 2^8 * 3
     (8000, 64),       # the paper's 8000: columns 8000 = 64 x 125
+    # lengths mixing 3, 5 and 7 (12-, 14-, 15- and 21-point threads, middle stages
+    # whose radix does not divide the points per thread)
+    (630, 420),       # columns 630 = 2 3^2 5 7, rows 210
+    (1470, 90),       # columns 1470 = 2 3 5 7^2, rows 45 = 3^2 5
+    (210, 3360),      # rows 1680 = 2^4 3 5 7 (the 6720 rows of the 6300 x 6720 torus halved twice)
+    (63, 105, 42),    # 3-D: 63 = 3^2 7, 105 = 3 5 7, rows 21
+    (6300, 16),       # columns 6300 = 2^2 3^2 5^2 7 split in levels
 ]
 
 
@@ -36,7 +43,7 @@ def test_mixed_radix_full_spectrum(shape, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("shape", [(2000, 1000), (96, 768), (20, 40, 100), (640,)])
+@pytest.mark.parametrize("shape", [(2000, 1000), (96, 768), (20, 40, 100), (640,), (630, 420), (210, 3360)])
 def test_mixed_radix_long_damped(shape, dtype):
     rng = np.random.default_rng(31)
     c = np.abs(rng.uniform(size=(3,) * len(shape)))

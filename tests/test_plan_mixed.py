@@ -1,19 +1,22 @@
 """CPU checks of the mixed-radix stage lists the planner builds (no GPU): for
 every pass that runs on the register mixed-radix kernels, the radices multiply
-to the pass length, each divides the points per thread Q, the first is Q, and
+to the pass length, the register stages divide the points per thread Q (middle
+stages may also take 2, 3, 4, 5 or 7), the first is Q, and
 the last is one the kernels are instantiated for (Q itself, 2, or the family's
 odd prime); rows never take 20 points per thread, and the
 options that cap Q are honoured."""
 import pytest
 
 # (Q, last radix) pairs that have kernels, per dtype
-PAIRS = {"f32": {(5, 5), (10, 10), (10, 2), (10, 5), (12, 12), (12, 2), (12, 3), (20, 20), (20, 2), (20, 5),
-                 (25, 25), (25, 5)},
-         "f64": {(5, 5), (10, 10), (10, 2), (10, 5), (12, 12), (12, 2), (12, 3)}}
+PAIRS = {"f32": {(5, 5), (10, 10), (10, 2), (10, 5), (12, 12), (12, 2), (12, 3), (14, 14), (14, 2), (14, 7),
+                 (15, 15), (15, 3), (15, 5), (20, 20), (20, 2), (20, 5), (21, 21), (21, 3), (21, 7), (25, 25),
+                 (25, 5)},
+         "f64": {(5, 5), (10, 10), (10, 2), (10, 5), (12, 12), (12, 2), (12, 3), (14, 14), (14, 2), (14, 7),
+                 (15, 15), (15, 3), (15, 5)}}
 
 SHAPES = [(8000, 8000), (4000, 4000), (2000, 1000), (250, 160), (96, 768), (75, 50), (20, 40, 100), (640,),
           (1536, 40), (400, 400, 400), (800, 800, 800), (192, 96), (96, 48), (250,), (20, 500), (1250, 3000),
-          (625, 48), (3125,), (120, 360)]
+          (625, 48), (3125,), (120, 360), (6300, 6720), (630, 420), (1470, 90), (210, 3360), (63, 105, 42)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -27,8 +30,10 @@ def test_mixed_stage_lists_are_valid(shape, dtype):
         rad = p["radices"]
         prod = 1
         for x in rad:
-            assert q % x == 0, (shape, p)
+            # register stages (first, last) divide Q; middle stages may take 2, 3, 4, 5, 7
+            assert q % x == 0 or x in (2, 3, 4, 5, 7), (shape, p)
             prod *= x
+        assert q % rad[-1] == 0, (shape, p)
         assert prod == p["L"], (shape, p)
         assert rad[0] == q and len(rad) >= 2, (shape, p)
         assert (q, rad[-1]) in PAIRS[dtype], (shape, p)
