@@ -491,6 +491,46 @@ def mfma_probe(torch, n: int = 1 << 21, reps: int = 32):
     return res
 
 
+def strip_probe(torch, pitch: int = 4112, cols: int = 4097, reps: int = 20):
+    """The memory side of a one-pass strided 8192-point transform
+    (paper_2105_06676_amd/probes/strip_probe.hip): W = 1 or 2 columns of the
+    8192^2 workload's half spectrum per workgroup (8 or 16 bytes per row and wave
+    access), one LDS exchange, no arithmetic; against a plain device copy of the
+    same bytes."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2105_06676_amd", "libsfft_probe.so"))
+    f = lib.sfft_probe_strip
+    f.restype = ctypes.c_float
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_int, ctypes.c_void_p]
+    gen = torch.Generator(device="cpu").manual_seed(6)
+    x = torch.rand(8192, pitch, 2, generator=gen, dtype=torch.float32).to("cuda")
+    y = torch.zeros_like(x)
+    st = torch.cuda.current_stream().cuda_stream
+    nbytes = 2 * 8192 * cols * 8
+    res = {"config": {"rows": 8192, "pitch": pitch, "columns": cols, "dtype": "f32 complex",
+                      "bytes_per_launch": nbytes}}
+    for W in (1, 2):
+        for remap in (0, 1):
+            if f(W, remap, x.data_ptr(), y.data_ptr(), pitch, cols, 2, st) < 0:
+                raise RuntimeError("strip probe launch failed")
+            ms = min(f(W, remap, x.data_ptr(), y.data_ptr(), pitch, cols, reps, st) for _ in range(3))
+            torch.cuda.synchronize()
+            ok = bool(torch.equal(y[:, :cols], x[:, :cols]))
+            res[f"W{W}_remap{remap}"] = {"us": ms * 1e3, "GBps": nbytes / (ms * 1e-3) / 1e9, "exact_copy": ok}
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        y.copy_(x)
+    a.record()
+    for _ in range(reps):
+        y.copy_(x)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    res["device_copy"] = {"us": ms * 1e3, "GBps": 2 * x.numel() * 4 / (ms * 1e-3) / 1e9}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -507,6 +547,8 @@ def main():
                     help="comma-separated <workload>_<dtype> keys: time only these other workloads")
     ap.add_argument("--only-others", action="store_true",
                     help="profiling runs: time only the other workloads (prints their JSON, no headline line)")
+    ap.add_argument("--strip-probe", action="store_true",
+                    help="measure the memory side of a one-pass strided 8192-point transform (prints its JSON only)")
     ap.add_argument("--mfma-probe", action="store_true",
                     help="measure a DFT stage on the matrix cores against butterflies (prints its JSON only)")
     args = ap.parse_args()
@@ -522,6 +564,9 @@ def main():
 
     if args.mfma_probe:
         print(json.dumps({"mfma_probe": mfma_probe(torch)}))
+        return
+    if args.strip_probe:
+        print(json.dumps({"strip_probe": strip_probe(torch)}))
         return
 
     if args.only_others:
