@@ -28,6 +28,20 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(s.lib, n), n
 
 
+def test_measurement_probes_load_and_reject_bad_shapes():
+    """The probe library (measurements only, not the solver) exports both probes;
+    the strip probe refuses shapes it cannot run before any device work."""
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2105_06676_amd", "libsfft_probe.so"))
+    assert hasattr(lib, "sfft_probe_dft16") and hasattr(lib, "sfft_probe_strip")
+    f = lib.sfft_probe_strip
+    f.restype = ctypes.c_float
+    f.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                  ctypes.c_int, ctypes.c_void_p]
+    assert f(3, 0, None, None, 16, 8, 1, None) < 0      # W must be 1 or 2
+    assert f(1, 0, None, None, 8, 16, 1, None) < 0      # columns beyond the pitch
+    assert f(2, 1, None, None, 16, 8, 0, None) < 0      # no repetitions
+
+
 def test_invalid_arguments_are_rejected_without_a_gpu():
     import paper_2105_06676_amd as s
     lib = s.lib
