@@ -157,8 +157,39 @@ bool valid_split(int64_t n, const std::vector<int64_t>& lev) {
     return p == n;
 }
 
-// Split n (7-smooth) into 1..3 factors, each <= cap, as balanced as possible,
-// unless the tuning database holds a factorisation for (n, f64).
+// Register mixed-radix column tile of length L (a register family, at least
+// four columns per workgroup, at most 128 KB of LDS); the tile geometry in *W,
+// *bytes when given.
+static bool mixed_col_fit(int64_t L, bool f64, int* mq, int64_t* mrad, int* mst, int64_t* W = nullptr,
+                          size_t* bytes = nullptr) {
+    if (!mixed_family(L, true, f64, mq, mrad, mst)) return false;
+    const int64_t P = L / *mq;
+    const int64_t Wm = std::min<int64_t>(64, 256 / P);
+    const size_t b = (size_t)std::max<int64_t>(L * (Wm + 1), 256 * (int64_t)*mq) * (f64 ? 16 : 8);
+    if (Wm < 4 || b > 128 * 1024) return false;
+    if (W) *W = Wm;
+    if (bytes) *bytes = b;
+    return true;
+}
+
+// A strided level of L points runs on the register kernels (power-of-two or
+// mixed-radix) rather than the generic ones.
+static bool col_register(int64_t L, bool f64) {
+    if (is_pow2(L)) return L >= kFastMinL && L <= kFastMaxColL && !tunables().no_fast;
+    int mq = 0, mst = 0;
+    int64_t mrad = 0;
+    return mixed_col_fit(L, f64, &mq, &mrad, &mst);
+}
+
+// Split n (7-smooth) into 1..3 strided levels, unless the tuning database holds
+// a factorisation for (n, f64).  Measured on one MI355X (strided axes of 600 to
+// 8000 points, 2-D and 3-D, FP32 and FP64): every split moves the spectrum
+// through HBM twice more, so one pass wins whenever a register kernel covers
+// the whole axis (up to 1024 points with the default cap); otherwise a
+// power-of-two level of at least 16 points with a register-kernel rest of at
+// least 16 points (FP32: last, in the fused middle pass; FP64: first), else
+// the most balanced split whose levels both run on register kernels, else the
+// most balanced one.
 static bool split_axis(int64_t n, int64_t cap, std::vector<int64_t>* out, bool f64) {
     out->clear();
     {
@@ -171,26 +202,31 @@ static bool split_axis(int64_t n, int64_t cap, std::vector<int64_t>* out, bool f
         }
     }
     if (n <= cap) { out->push_back(n); return true; }
-    // A power-of-two factor of at least kFastMinL points runs on the register
-    // kernels, several times faster than the mixed-radix ones: when n has one, the
-    // largest such factor up to cap leads (its level runs first, the rest of n in
-    // the next level) provided the rest also fits (8000 -> 64 x 125).
+    const bool dflt = tunables().col_max == 0;
+    if (dflt && n <= kMaxTunedLevel && col_register(n, f64)) { out->push_back(n); return true; }
+    const int64_t lmax = dflt ? kMaxTunedLevel : cap;
+    auto level_ok = [&](int64_t s) { return s <= cap || (s <= lmax && col_register(s, f64)); };
     if (!is_pow2(n)) {
-        int64_t p2 = 1;
-        while (n % (p2 * 2) == 0 && p2 * 2 <= cap) p2 *= 2;
-        if (p2 >= kFastMinL && n / p2 <= cap) {
-            out->push_back(p2);
-            out->push_back(n / p2);
+        int64_t p2 = 0;
+        for (int64_t p = kFastMinL; p <= cap && n % p == 0; p *= 2) {
+            const int64_t r = n / p;
+            if (r >= kFastMinL && level_ok(r) && col_register(r, f64)) p2 = p;
+        }
+        if (p2) {
+            out->push_back(f64 ? p2 : n / p2);
+            out->push_back(f64 ? n / p2 : p2);
             return true;
         }
     }
     int64_t best = 0, b0 = 0;
-    for (int64_t s0 = 2; s0 <= cap && s0 < n; ++s0) {
+    bool best_reg = false;
+    for (int64_t s0 = 2; s0 <= lmax && s0 < n; ++s0) {
         if (n % s0) continue;
         const int64_t s1 = n / s0;
-        if (s1 > cap) continue;
+        if (!level_ok(s0) || !level_ok(s1)) continue;
+        const bool reg = col_register(s0, f64) && col_register(s1, f64);
         const int64_t score = std::min(s0, s1);
-        if (score > best) { best = score; b0 = s0; }
+        if ((reg && !best_reg) || (reg == best_reg && score > best)) { best = score; b0 = s0; best_reg = reg; }
     }
     if (b0) { out->push_back(b0); out->push_back(n / b0); return true; }
     int64_t bs = 0, c0 = 0, c1 = 0;
@@ -378,24 +414,20 @@ static PassPlan make_col(const Ctx& c, int64_t outer, int L, int64_t inner, int 
         two_level(L, &p.f_lo, &p.f_hi);
     } else {
         int mq = 0, mst = 0;
-        int64_t mrad = 0;
-        if (mixed_family(L, true, c.f64, &mq, &mrad, &mst)) {
-            // register mixed-radix columns: P = L / Q threads per column, W columns
-            const int64_t P = L / mq;
-            const int64_t Wm = std::min<int64_t>(64, 256 / P);
-            const size_t bytes = (size_t)std::max<int64_t>((int64_t)L * (Wm + 1), 256 * (int64_t)mq) * c.csz;
-            if (Wm >= 4 && bytes <= 128 * 1024) {
-                pd.mq = mq;
-                pd.mrad = mrad;
-                pd.nst = mst;
-                for (int i = 0; i < mst; ++i) pd.radix[i] = mixed_radix_at(mrad, i);
-                pd.W = (int)Wm;
-                pd.mthreads = (int)(Wm * P);
-                pd.tiles_inner = (inner + Wm - 1) / Wm;
-                pd.ntiles = outer * pd.tiles_inner;
-                pd.xcd_remap = 1;
-                p.lds_bytes = bytes;
-            }
+        int64_t mrad = 0, Wm = 0;
+        size_t bytes = 0;
+        // register mixed-radix columns: P = L / Q threads per column, W columns
+        if (mixed_col_fit(L, c.f64, &mq, &mrad, &mst, &Wm, &bytes)) {
+            pd.mq = mq;
+            pd.mrad = mrad;
+            pd.nst = mst;
+            for (int i = 0; i < mst; ++i) pd.radix[i] = mixed_radix_at(mrad, i);
+            pd.W = (int)Wm;
+            pd.mthreads = (int)(Wm * (L / mq));
+            pd.tiles_inner = (inner + Wm - 1) / Wm;
+            pd.ntiles = outer * pd.tiles_inner;
+            pd.xcd_remap = 1;
+            p.lds_bytes = bytes;
         }
     }
     return p;

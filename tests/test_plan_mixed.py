@@ -57,3 +57,45 @@ def test_mixed_q_options_cap_points_per_thread():
         sfft.set_option("mixed_row_q", 0)
     with pytest.raises(sfft.SfftError):
         sfft.set_option("mixed_row_q", 7)
+
+
+def _strided_levels(shape, dtype):
+    import paper_2105_06676_amd as sfft
+    d = sfft.plan_describe(shape, dtype)
+    return [p for p in d["passes"] if p["kind"] == "col"], d["levels"]
+
+
+def _register(p):
+    return bool(p["fast"] or p["mixed_q"])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape", [(600, 4096), (640, 4096), (720, 4096), (768, 4096), (1024, 4096),
+                                   (640, 200, 256), (256, 768, 64)])
+def test_strided_axis_up_to_1024_in_one_register_pass(shape, dtype):
+    """One pass over an axis the register kernels cover whole (every split moves the
+    spectrum through HBM twice more)."""
+    cols, _ = _strided_levels(shape, dtype)
+    axes = len(shape) - 1  # strided axes: forward and inverse passes, one fused middle pass
+    assert len(cols) == 2 * axes - 1, (shape, cols)
+    assert all(_register(p) for p in cols), (shape, cols)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n", [1200, 1280, 1500, 1536, 1600, 8000, 6300, 960])
+def test_split_levels_run_on_register_kernels(n, dtype):
+    """Axes split into two levels put both on the register kernels and never leave a
+    level of fewer than 16 points behind a large power-of-two factor (1536 once went
+    512 x 3, the 3-point level on the generic kernels)."""
+    cols, _ = _strided_levels((n, 64), dtype)
+    assert len(cols) == 3, cols
+    assert all(_register(p) for p in cols), (n, cols)
+    assert all(p["L"] >= 16 for p in cols), (n, cols)
+
+
+def test_power_of_two_level_placement():
+    """FP32 runs the power-of-two level in the fused middle pass, FP64 first."""
+    c32, _ = _strided_levels((8000, 8000), "f32")
+    c64, _ = _strided_levels((8000, 8000), "f64")
+    assert [p["L"] for p in c32] == [125, 64, 125]
+    assert [p["L"] for p in c64] == [64, 125, 64]
