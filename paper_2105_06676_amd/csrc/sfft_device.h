@@ -68,6 +68,14 @@ struct RootTab<7> {
 };
 
 template <>
+struct RootTab<9> {
+    static constexpr double c[9] = {1.0, 0.766044443118978, 0.17364817766693036, -0.5, -0.9396926207859084,
+                                    -0.9396926207859084, -0.5, 0.17364817766693036, 0.766044443118978};
+    static constexpr double s[9] = {0.0, 0.6427876096865394, 0.984807753012208, 0.8660254037844386,
+                                    0.3420201433256687, -0.3420201433256687, -0.8660254037844386,
+                                    -0.984807753012208, -0.6427876096865394};
+};
+template <>
 struct RootTab<6> {
     static constexpr double c[6] = {1.0, 0.5, -0.5, -1.0, -0.5, 0.5};
     static constexpr double s[6] = {0.0, 0.8660254037844386, 0.8660254037844386, 0.0, -0.8660254037844386,
@@ -303,6 +311,7 @@ __device__ __forceinline__ void dft(cx<R>* v) {
     else if constexpr (RAD == 4) dft4<R, INV>(v[0], v[1], v[2], v[3]);
     else if constexpr (RAD == 8) dft8<R, INV>(v);
     else if constexpr (RAD == 6) dft_ab<R, 3, 2, INV>(v);
+    else if constexpr (RAD == 9) dft_ab<R, 3, 3, INV>(v);
     else if constexpr (RAD == 10) dft_ab<R, 5, 2, INV>(v);
     else if constexpr (RAD == 12) dft_ab<R, 4, 3, INV>(v);
     else if constexpr (RAD == 14) dft_ab<R, 7, 2, INV>(v);

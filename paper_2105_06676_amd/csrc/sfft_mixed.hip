@@ -139,13 +139,13 @@ __device__ __forceinline__ void mstage(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q
 }
 
 // Middle stages: the radices that divide Q, and for the families that mix 3, 5
-// and 7 (Q = 12, 14, 15, 21) also 2, 3, 4, 5 and 7 with guarded butterflies.
+// and 7 (Q = 7, 9, 12, 14, 15, 21) also 2, 3, 4, 5 and 7 with guarded butterflies.
 template <typename R, int Q, bool INV, bool FIRST, bool LAST, typename IDX>
 __device__ __forceinline__ void mstage_rad(int rad, cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, int P, int L, int NS,
                                            const cx<R>* tab, int tmul) {
 #define SFFT_MST(RAD)                                                                                      if constexpr (Q % RAD == 0) mstage<R, Q, RAD, INV, FIRST, LAST>(v, lds, idx, q, P, L, NS, tab, tmul);
 #define SFFT_MSTG(RAD)                                                                                     \
-    if constexpr (Q % RAD == 0 || Q == 12 || Q == 14 || Q == 15 || Q == 21)                                \
+    if constexpr (Q % RAD == 0 || Q == 7 || Q == 9 || Q == 12 || Q == 14 || Q == 15 || Q == 21)            \
         mstage<R, Q, RAD, INV, FIRST, LAST>(v, lds, idx, q, P, L, NS, tab, tmul);
     switch (rad) {
         case 2: SFFT_MSTG(2) break;
@@ -154,6 +154,7 @@ __device__ __forceinline__ void mstage_rad(int rad, cx<R> (&v)[Q], cx<R>* lds, I
         case 5: SFFT_MSTG(5) break;
         case 7: SFFT_MSTG(7) break;
         case 6: SFFT_MST(6) break;
+        case 9: SFFT_MST(9) break;
         case 10: SFFT_MST(10) break;
         case 12: SFFT_MST(12) break;
         case 14: SFFT_MST(14) break;
@@ -176,6 +177,11 @@ __device__ __forceinline__ void mstage_rad(int rad, cx<R> (&v)[Q], cx<R>* lds, I
 
 // Length-L transform of the Q points held by each of the P threads (stage
 // radices in pd.mrad, pd.nst >= 2 stages, the first of radix Q, the last RL).
+// RL = 1 (gather): the last radix does not divide Q, so every stage after the
+// first goes through LDS like a middle one; Stockham's self-sorting order leaves
+// the outputs in natural order there, and each thread reads its Q points back
+// (one more exchange, for lengths no register family takes otherwise, such as
+// 35, 42 or 210 points).
 template <typename R, int Q, int RL, bool INV, typename IDX>
 __device__ __forceinline__ void mfft(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, int P, const PassDesc& pd) {
     const cx<R>* tab = (const cx<R>*)pd.st_tab;
@@ -183,12 +189,20 @@ __device__ __forceinline__ void mfft(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, 
     const uint64_t rads = (uint64_t)pd.mrad;
     mstage<R, Q, Q, INV, true, false>(v, lds, idx, q, P, L, 1, tab, tmul);
     int NS = Q;
-    for (int s = 1; s < nst - 1; ++s) {
+    constexpr int NMID_END = RL == 1 ? 0 : 1;  // stages left for the register stage
+    for (int s = 1; s < nst - NMID_END; ++s) {
         const int rad = mixed_radix_at((int64_t)rads, s);
         mstage_rad<R, Q, INV, false, false>(rad, v, lds, idx, q, P, L, NS, tab, tmul);
         NS *= rad;
     }
-    mstage<R, Q, RL, INV, false, true>(v, lds, idx, q, P, L, NS, tab, tmul);
+    if constexpr (RL == 1) {
+        // (the last stage's barrier orders its LDS writes before these reads; every
+        // later writer of this LDS starts with a barrier)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = lds[idx(q + P * i)];
+    } else {
+        mstage<R, Q, RL, INV, false, true>(v, lds, idx, q, P, L, NS, tab, tmul);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -553,7 +567,22 @@ hipError_t launch_m(const PassDesc& pd, const SymParams& sp, size_t lds, hipStre
     const int rl = mixed_radix_at(pd.mrad, pd.nst - 1);
     // (Q, last radix) pairs the planner's canonical order produces
     // (FP32 only for 20 and 25 points per thread: FP64 would hold one wave per SIMD)
+    // last radix not dividing Q: the gather form (families 7, 9, 12, 14, 15, 21)
+    if (pd.mq % rl != 0) {
+        if (pd.mq == 7) return launch_q<R, 7, 1>(pd, sp, lds, st, ba);
+        if (pd.mq == 9) return launch_q<R, 9, 1>(pd, sp, lds, st, ba);
+        if (pd.mq == 12) return launch_q<R, 12, 1>(pd, sp, lds, st, ba);
+        if (pd.mq == 14) return launch_q<R, 14, 1>(pd, sp, lds, st, ba);
+        if (pd.mq == 15) return launch_q<R, 15, 1>(pd, sp, lds, st, ba);
+        if constexpr (sizeof(R) == 4) {
+            if (pd.mq == 21) return launch_q<R, 21, 1>(pd, sp, lds, st, ba);
+        }
+        return hipErrorInvalidValue;
+    }
     if (pd.mq == 5 && rl == 5) return launch_q<R, 5, 5>(pd, sp, lds, st, ba);
+    if (pd.mq == 7 && rl == 7) return launch_q<R, 7, 7>(pd, sp, lds, st, ba);
+    if (pd.mq == 9 && rl == 9) return launch_q<R, 9, 9>(pd, sp, lds, st, ba);
+    if (pd.mq == 9 && rl == 3) return launch_q<R, 9, 3>(pd, sp, lds, st, ba);
     if (pd.mq == 10 && rl == 10) return launch_q<R, 10, 10>(pd, sp, lds, st, ba);
     if (pd.mq == 10 && rl == 2) return launch_q<R, 10, 2>(pd, sp, lds, st, ba);
     if (pd.mq == 10 && rl == 5) return launch_q<R, 10, 5>(pd, sp, lds, st, ba);

@@ -50,13 +50,15 @@ static bool radix_list(int64_t L, int* out, int* nst) {
 static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 // Stage list of a length L with Q points per thread (Q | L): radix Q first; radix Q
-// last when Q^2 | L, else the largest prime of Q that divides L / Q (none: no
-// list); the rest in between as the fewest radices, largest first, from the
-// proper divisors of Q and (general: the families mixing 3, 5 and 7) the primes
-// 2..7 with 4 — a middle radix that does not divide Q spreads its butterflies
-// unevenly over the threads, and the kernels of those families carry the guarded
-// stages for it.
-static bool mixed_stages(int64_t L, int q, bool general, std::vector<int>* out) {
+// last when Q^2 | L, else the largest prime of Q that divides L / Q; the rest in
+// between as the fewest radices, largest first, from the proper divisors of Q and
+// (general: the families mixing 3, 5 and 7) the primes 2..7 with 4 — a middle
+// radix that does not divide Q spreads its butterflies unevenly over the threads,
+// and the kernels of those families carry the guarded stages for it.  When no
+// prime of Q divides L / Q, `gather` allows a last radix that does not divide Q:
+// the kernels then run it through LDS like a middle stage and read the outputs
+// back in natural order.
+static bool mixed_stages(int64_t L, int q, bool general, bool gather, std::vector<int>* out) {
     if (L % q) return false;
     int64_t rest = L / q;
     int last = 0;
@@ -66,8 +68,11 @@ static bool mixed_stages(int64_t L, int q, bool general, std::vector<int>* out) 
         for (int p : {7, 5, 3, 2})
             if (q % p == 0 && rest % p == 0) { last = p; break; }
     }
-    if (last == 0 || rest < last) return false;
-    rest /= last;
+    if (last == 0 && !gather) return false;
+    if (last != 0) {
+        if (rest < last) return false;
+        rest /= last;
+    }
     std::vector<int> cand;
     for (int dv : {25, 21, 20, 15, 14, 12, 10, 6})
         if (dv < q && q % dv == 0) cand.push_back(dv);
@@ -81,9 +86,14 @@ static bool mixed_stages(int64_t L, int q, bool general, std::vector<int>* out) 
     if (rest != 1) return false;
     std::vector<int> r{q};
     r.insert(r.end(), mid.begin(), mid.end());
-    r.push_back(last);
+    if (last != 0) r.push_back(last);
     *out = r;
     return true;
+}
+
+// Families whose kernels carry the gather form (a last radix not dividing Q).
+static bool gather_family(int q, bool f64) {
+    return q == 7 || q == 9 || q == 12 || q == 14 || q == 15 || (q == 21 && !f64);
 }
 
 bool mixed_family(int64_t L, bool column, bool f64, int* Q, int64_t* packed, int* nst) {
@@ -102,9 +112,11 @@ bool mixed_family(int64_t L, bool column, bool f64, int* Q, int64_t* packed, int
     // VGPRs, twice the threads), so even rows prefer 10 (measured equal on
     // 4000-point rows, faster on short rows where many rows share a workgroup).
     // FP64 points take twice the registers: 20, 21 or 25 of them would run one
-    // wave per SIMD.  The 2^a 5^b, 2^a 3^b and 5^b lengths keep their families;
-    // the others take the first of 12, 14, 15, 21, 10 that divides them and leaves
-    // a last radix.  An option caps the choice, rows and columns separately.
+    // wave per SIMD.  The 2^a 5^b, 2^a 3^b (a >= 2), 5^b, 7^b and 3^b (times at
+    // most one 2) lengths keep their families; the others take the first of 12,
+    // 14, 15, 21, 9, 7 that divides them and leaves a last radix, else the first
+    // whose gather form fits.  An option caps the choice, rows and columns
+    // separately.
     std::vector<int> pref;
     bool general = false;
     if (e3 == 0 && e7 == 0 && e5 >= 1) {
@@ -114,17 +126,27 @@ bool mixed_family(int64_t L, bool column, bool f64, int* Q, int64_t* packed, int
         pref.push_back(5);
     } else if (e5 == 0 && e7 == 0 && e3 >= 1 && e2 >= 2) {
         pref.push_back(12);
+    } else if (e2 == 0 && e3 == 0 && e5 == 0 && e7 >= 2) {
+        pref.push_back(7);
+    } else if (e5 == 0 && e7 == 0 && e3 >= 2 && e2 <= 1) {
+        pref.push_back(9);
+        general = true;
     } else {
         pref = {12, 14, 15};
         if (!f64) pref.push_back(21);
+        pref.push_back(9);
+        pref.push_back(7);
         general = true;
     }
     const int cap = column ? tunables().mixed_col_q : tunables().mixed_row_q;
     std::vector<int> r;
     int q = 0;
-    for (int c : pref) {
-        if (cap != 0 && c > cap && c != pref.back()) continue;
-        if (mixed_stages(L, c, general || c == 12, &r)) { q = c; break; }
+    for (int gather = 0; gather <= 1 && q == 0; ++gather) {
+        for (int c : pref) {
+            if (cap != 0 && c > cap && c != pref.back()) continue;
+            if (gather && !gather_family(c, f64)) continue;
+            if (mixed_stages(L, c, general || c == 12, gather != 0, &r)) { q = c; break; }
+        }
     }
     if (q == 0) return false;
     const int64_t P = L / q;
@@ -134,7 +156,7 @@ bool mixed_family(int64_t L, bool column, bool f64, int* Q, int64_t* packed, int
         prod *= r[i];
         pk |= (int64_t)r[i] << (kMRadBits * i);
     }
-    if (prod != L || q % r.back()) return false;
+    if (prod != L || (q % r.back() && !gather_family(q, f64))) return false;
     *Q = q;
     *packed = pk;
     *nst = (int)r.size();

@@ -1,5 +1,5 @@
-"""The register mixed-radix kernels (transform lengths 2^a 5^b, 2^a 3^b, 5^b held
-10, 12, 20 or 25 points per thread) against the FP64 loop oracle: every family,
+"""The register mixed-radix kernels (7-smooth transform lengths held 5, 7, 9, 10,
+12, 14, 15, 20, 21 or 25 points per thread) against the FP64 loop oracle: every family,
 rows (real-to-complex, complex-to-real, the whole 1-D solve) and strided axes
 (forward, inverse, fused middle pass, split twiddles), every mode visible (T = 1
 with an asymmetric stencil) and long damped runs; batched launches that mix these
@@ -29,6 +29,18 @@ SHAPES = [
     (210, 3360),      # rows 1680 = 2^4 3 5 7 (the 6720 rows of the 6300 x 6720 torus halved twice)
     (63, 105, 42),    # 3-D: 63 = 3^2 7, 105 = 3 5 7, rows 21
     (6300, 16),       # columns 6300 = 2^2 3^2 5^2 7 split in levels
+    # 7- and 9-point threads (7^b, 3^b, 2 3^b) and the gather form (a last radix
+    # that divides no Q: the outputs are read back from LDS in natural order)
+    (49, 98),         # columns 49 = 7^2, rows 49
+    (343, 16),        # columns 343 = 7^3
+    (27, 162),        # columns 27 = 3^3, rows 81 = 3^4
+    (54, 486),        # columns 54 = 2 3^3 (radix 2 guarded), rows 243 = 3^5
+    (35, 84),         # columns 35 = 5 7 (gather), rows 42 = 2 3 7 (gather)
+    (210, 60),        # columns 210 = 2 3 5 7 (gather), rows 30 = 2 3 5 (gather)
+    (105, 70, 20),    # 3-D: 105 = 3 5 7 and 70 = 2 5 7 (gather)
+    (175, 126),       # columns 175 = 5^2 7 (gather), rows 63 = 3^2 7
+    (189, 20),        # columns 189 = 3^3 7
+    (1050, 16),       # columns 1050 = 2 3 5^2 7 split in levels
 ]
 
 
@@ -43,7 +55,8 @@ def test_mixed_radix_full_spectrum(shape, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("shape", [(2000, 1000), (96, 768), (20, 40, 100), (640,), (630, 420), (210, 3360)])
+@pytest.mark.parametrize("shape", [(2000, 1000), (96, 768), (20, 40, 100), (640,), (630, 420), (210, 3360),
+                                   (49, 98), (35, 84), (210, 60), (54, 486)])
 def test_mixed_radix_long_damped(shape, dtype):
     rng = np.random.default_rng(31)
     c = np.abs(rng.uniform(size=(3,) * len(shape)))
