@@ -102,9 +102,10 @@ def time_path(sfft, torch, w, dtype: str, steps: int, warmup: int):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = a.elapsed_time(b)
-    # (2) latency
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
-    for i in range(steps):
+    # (2) latency (at least 200 samples, so that p99 is not just the largest of a few)
+    nlat = max(steps, 200)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(nlat)]
+    for i in range(nlat):
         ev[i][0].record(stream)
         sfft.periodic(grid, w.coeffs, w.T)
         ev[i][1].record(stream)
@@ -390,7 +391,41 @@ def cpu_baseline(w, budget_s: float = 12.0):
     rec = {"value": cells * steps / dt, "unit": "cell-updates/s", "cores": nthr, "kind": "oracle",
            "sample": f"full {w.dims[0]}x{w.dims[1]} grid, {steps} of the {w.T} steps "
                      f"(FP64 nested loop, OpenMP, {dt:.1f} s)"}
+    # one thread on a shortened problem (the first rows of the grid, periodic on
+    # that crop), and the host it ran on
+    rows = max(1, min(w.dims[0], (1 << 23) // w.dims[1]))
+    crop = np.ascontiguousarray(a0[:rows])
+    t0 = time.perf_counter()
+    oracle.periodic(crop, w.coeffs, 1, nthreads=1)
+    t1 = time.perf_counter() - t0
+    s1 = int(max(1, min(16, 3.0 / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.periodic(crop, w.coeffs, s1, nthreads=1)
+    dt1 = time.perf_counter() - t0
+    one = crop.size * s1 / dt1
+    rec["one_thread"] = {"value": one, "unit": "cell-updates/s",
+                         "sample": f"{rows}x{w.dims[1]} crop, {s1} steps ({dt1:.1f} s)",
+                         "parallel_speedup": rec["value"] / one}
+    rec["host"] = host_info()
     return rec, a0, steps, ref
+
+
+def host_info() -> dict:
+    """CPU model name and core counts of the host the oracle ran on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
 
 
 def _errors(y: np.ndarray, ref: np.ndarray) -> dict:
