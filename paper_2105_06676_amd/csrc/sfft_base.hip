@@ -25,7 +25,10 @@
 namespace sfft {
 
 // MAXC: LDS cells per thread, at least the largest loaded region / kBaseThreads.
-template <typename R, int MAXC>
+// NC > 0: the stencil's coefficients and LDS offsets are unrolled into registers
+// (NC entries, the ones past bp.ncoef zero with offset 0, adding +0), so a term
+// costs one LDS read and one multiply-add; NC = 0 reads them from LDS per term.
+template <typename R, int MAXC, int NC>
 __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     R* A = reinterpret_cast<R*>(smem_raw);
@@ -58,9 +61,20 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
     const int le0 = (int)(rext[1] * rext[2]);
     const int cells = (int)(rext[0] * rext[1] * rext[2]);
 
-    for (int i = threadIdx.x; i < bp.ncoef; i += kBaseThreads) {
-        offs[i] = bp.off[i][0] * le0 + bp.off[i][1] * le1 + bp.off[i][2];
-        coef[i] = (R)bp.c[i];
+    if constexpr (NC == 0) {
+        for (int i = threadIdx.x; i < bp.ncoef; i += kBaseThreads) {
+            offs[i] = bp.off[i][0] * le0 + bp.off[i][1] * le1 + bp.off[i][2];
+            coef[i] = (R)bp.c[i];
+        }
+    }
+    constexpr int NR = NC > 0 ? NC : 1;
+    int roff[NR];
+    R rcoef[NR];
+#pragma unroll
+    for (int j = 0; j < NR; ++j) {
+        const bool use = NC > 0 && j < bp.ncoef;
+        roff[j] = use ? bp.off[j][0] * le0 + bp.off[j][1] * le1 + bp.off[j][2] : 0;
+        rcoef[j] = use ? (R)bp.c[j] : R(0);
     }
 
     const R* src = (const R*)bp.src;
@@ -128,7 +142,12 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
         for (int k = 0; k < MAXC; ++k) {
             if (step <= lim[k]) {
                 R acc = R(0);
-                for (int j = 0; j < bp.ncoef; ++j) acc += coef[j] * A[idx[k] + offs[j]];
+                if constexpr (NC > 0) {
+#pragma unroll
+                    for (int j = 0; j < NC; ++j) acc += rcoef[j] * A[idx[k] + roff[j]];
+                } else {
+                    for (int j = 0; j < bp.ncoef; ++j) acc += coef[j] * A[idx[k] + offs[j]];
+                }
                 nv[k] = acc;
             }
         }
@@ -153,18 +172,32 @@ __global__ __launch_bounds__(kBaseThreads) void k_base(BaseParams bp) {
     }
 }
 
-template <typename R>
-hipError_t launch_r(const BaseParams& bp, int64_t nblocks, size_t lds, hipStream_t st) {
+template <typename R, int NC>
+hipError_t launch_nc(const BaseParams& bp, int64_t nblocks, size_t lds, hipStream_t st) {
     // per-thread slots for the largest region (lds bytes of R cells): unused slots
     // still cost issue slots in the unrolled step loop, so use the smallest that fits
     const int64_t cells = (int64_t)(lds / sizeof(R));
     const dim3 g((unsigned)nblocks), b(kBaseThreads);
-    if (cells <= 4 * kBaseThreads) hipLaunchKernelGGL((k_base<R, 4>), g, b, lds, st, bp);
-    else if (cells <= 8 * kBaseThreads) hipLaunchKernelGGL((k_base<R, 8>), g, b, lds, st, bp);
-    else if (cells <= 16 * kBaseThreads) hipLaunchKernelGGL((k_base<R, 16>), g, b, lds, st, bp);
-    else if (cells <= kBaseMaxCells) hipLaunchKernelGGL((k_base<R, kBaseMaxCells / kBaseThreads>), g, b, lds, st, bp);
+    if (cells <= 4 * kBaseThreads) hipLaunchKernelGGL((k_base<R, 4, NC>), g, b, lds, st, bp);
+    else if (cells <= 8 * kBaseThreads) hipLaunchKernelGGL((k_base<R, 8, NC>), g, b, lds, st, bp);
+    else if (cells <= 16 * kBaseThreads) hipLaunchKernelGGL((k_base<R, 16, NC>), g, b, lds, st, bp);
+    else if (cells <= kBaseMaxCells) hipLaunchKernelGGL((k_base<R, kBaseMaxCells / kBaseThreads, NC>), g, b, lds, st, bp);
     else return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_r(const BaseParams& bp, int64_t nblocks, size_t lds, hipStream_t st) {
+    // the stencils' common term counts (1-D, 5- and 7-point stars, 3 x 3 and
+    // 3 x 3 x 3 boxes, 5 x 5 boxes; shorter lists pad up with zero terms)
+    const int n = bp.ncoef;
+    if (n <= 3) return launch_nc<R, 3>(bp, nblocks, lds, st);
+    if (n <= 5) return launch_nc<R, 5>(bp, nblocks, lds, st);
+    if (n <= 7) return launch_nc<R, 7>(bp, nblocks, lds, st);
+    if (n <= 9) return launch_nc<R, 9>(bp, nblocks, lds, st);
+    if (n <= 25) return launch_nc<R, 25>(bp, nblocks, lds, st);
+    if (n <= 27) return launch_nc<R, 27>(bp, nblocks, lds, st);
+    return launch_nc<R, 0>(bp, nblocks, lds, st);
 }
 
 hipError_t launch_base(const BaseParams& bp, bool f64, int64_t nblocks, size_t lds, hipStream_t st) {
