@@ -22,10 +22,11 @@ __host__ __device__ inline int mixed_radix_at(int64_t packed, int s) {
 // (rows: P = L / Q <= 512 threads; columns: P <= 64).
 bool mixed_family(int64_t L, bool column, bool f64, int* Q, int64_t* packed, int* nst);
 
-// FP64 symbol chains are evaluated G at a time: 4, 5, 3 or 2, the first that
-// divides Q (7 points: all seven at once).
+// FP64 symbol chains are evaluated G at a time: 4, 5, 3 or 7, the first that
+// divides Q (independent chains hide the FP64 latency; 14 points take two
+// groups of seven rather than seven of two).
 template <int Q>
-constexpr int kMGroup() { return Q == 7 ? 7 : (Q % 4 == 0 ? 4 : (Q % 5 == 0 ? 5 : (Q % 3 == 0 ? 3 : 2))); }
+constexpr int kMGroup() { return Q % 4 == 0 ? 4 : (Q % 5 == 0 ? 5 : (Q % 3 == 0 ? 3 : (Q % 7 == 0 ? 7 : 2))); }
 
 hipError_t launch_mixed_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t lds, hipStream_t st);
 hipError_t launch_mixed_batch(const PassDesc& proto, const BatchItem* items, int n, const SymParams* syms,
