@@ -22,11 +22,13 @@ __host__ __device__ inline int mixed_radix_at(int64_t packed, int s) {
 // (rows: P = L / Q <= 512 threads; columns: P <= 64).
 bool mixed_family(int64_t L, bool column, bool f64, int* Q, int64_t* packed, int* nst);
 
-// FP64 symbol chains are evaluated G at a time: 4, 5, 3 or 7, the first that
-// divides Q (independent chains hide the FP64 latency; 14 points take two
-// groups of seven rather than seven of two).
+// FP64 symbol chains are evaluated G at a time: the largest divisor of Q up to
+// 7 (independent chains hide the FP64 latency; 14 points take two groups of
+// seven rather than seven of two).
 template <int Q>
-constexpr int kMGroup() { return Q % 4 == 0 ? 4 : (Q % 5 == 0 ? 5 : (Q % 3 == 0 ? 3 : (Q % 7 == 0 ? 7 : 2))); }
+constexpr int kMGroup() {
+    return Q % 7 == 0 ? 7 : (Q % 6 == 0 ? 6 : (Q % 5 == 0 ? 5 : (Q % 4 == 0 ? 4 : (Q % 3 == 0 ? 3 : 2))));
+}
 
 hipError_t launch_mixed_pass(const PassDesc& pd, const SymParams& sp, bool f64, size_t lds, hipStream_t st);
 hipError_t launch_mixed_batch(const PassDesc& proto, const BatchItem* items, int n, const SymParams* syms,
