@@ -8,7 +8,9 @@
 namespace sfft {
 
 // fast row pass kinds (PassDesc::fast_kind)
-enum FastRowKind { ROW_R2C = 0, ROW_C2R = 1, ROW_MIDR = 2, ROW_MIDC = 3, ROW_CFWD = 4, ROW_CINV = 5 };
+enum FastRowKind { ROW_R2C = 0, ROW_C2R = 1, ROW_MIDR = 2, ROW_MIDC = 3, ROW_CFWD = 4, ROW_CINV = 5,
+                   // odd real lengths (register mixed-radix rows only)
+                   ROW_R2C_ODD = 6, ROW_C2R_ODD = 7, ROW_MIDR_ODD = 8 };
 
 constexpr int kFastMinL = 16;
 constexpr int kFastMaxRowL = 4096;   // 256 threads x 16 points

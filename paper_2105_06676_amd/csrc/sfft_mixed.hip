@@ -393,6 +393,127 @@ __device__ __forceinline__ void mrow_tile(const PassDesc& pd, const SymParams& s
     }
 }
 
+// Rows of odd real length n (RT_ODD): one n-point complex transform of (x, 0)
+// per row.  The first pass stores the h = (n + 1) / 2 entries of the half
+// spectrum; the last pass takes the others as the conjugates of their mirrors
+// X[n - k], read straight from the stored half (no exchange), transforms back and
+// keeps the real parts; the whole 1-D solve multiplies all n modes by the symbol
+// power between the two transforms.  Odd Q only (an odd length has no even factor).
+template <typename R, int KIND, int Q, int RL>
+__device__ __forceinline__ void mrow_odd_tile(const PassDesc& pd, const SymParams& sp, uint32_t bid) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
+    const int L = pd.L;
+    const int P = L / Q;
+    const int NTR = pd.W;
+    const int LS = L + L / 16 + 2;
+    uint32_t rr_u;
+    const int q = (int)udiv_qr((uint32_t)threadIdx.x, udiv((uint32_t)P), &rr_u);
+    const int rr = (int)rr_u;
+    const int64_t row = (int64_t)bid * NTR + rr;
+    bool active = row < pd.outer;
+    const MRowIdx idx{rr * LS};
+    cx<R> v[Q];
+
+    int64_t ii[3] = {0, 0, 0};
+    int64_t b = 0;
+    {
+        int64_t rem = active ? row : 0;
+#pragma unroll
+        for (int a = 1; a >= 0; --a) {
+            if (a <= pd.d - 2) {
+                const int64_t n = a == 1 ? pd.rdims[1] : pd.rdims[0];
+                const int64_t qq = rem / n;
+                ii[a] = rem - qq * n;
+                rem = qq;
+            }
+        }
+        b = rem;
+    }
+    if (KIND == ROW_C2R_ODD && active && pd.keep.enabled &&
+        !row_may_keep(pd.keep, keep_row(pd.keep, pd.d, b, ii), pd.d, b))
+        active = false;
+    auto row_base = [&](const RealView& rv) -> int64_t {
+        int64_t off = b * rv.boff;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            if (a < pd.d - 1) {
+                if (ii[a] >= rv.ext[a]) return -1;
+                off += ii[a] * rv.stride[a];
+            }
+        }
+        return off;
+    };
+
+    // ---------------- load
+    if (KIND == ROW_C2R_ODD) {
+        const cx<R>* src = (const cx<R>*)pd.buf + (active ? row : 0) * pd.ostride;
+        const int h = pd.hcount;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int k = q + P * i;
+            v[i] = !active ? cx<R>{R(0), R(0)} : (k < h ? src[k] : conj(src[L - k]));
+        }
+    } else {
+        const R* src = (const R*)pd.rv.ptr;
+        const int64_t base = active ? row_base(pd.rv) : -1;
+        const int64_t sl = pick3(pd.rv.stride, pd.d - 1), el = pick3(pd.rv.ext, pd.d - 1);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int m = q + P * i;
+            v[i] = cx<R>{(base >= 0 && m < el) ? src[base + (int64_t)m * sl] : R(0), R(0)};
+        }
+        mfft<R, Q, RL, false>(v, lds, idx, q, P, pd);
+    }
+
+    if (KIND == ROW_R2C_ODD) {
+        if (active) {
+            cx<R>* dst = (cx<R>*)pd.buf + row * pd.ostride;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int k = q + P * i;
+                if (k < pd.hcount) dst[k] = v[i];
+            }
+        }
+        return;
+    }
+    if (KIND == ROW_MIDR_ODD) {
+        // 1-D whole solve: thread q holds frequencies q + P i of all n
+        const SymCol col = symbol_column_1d(sp);
+        apply_symbol<R, kMRowThreads, Q, kMGroup<Q>()>(v, lds, sp, col, (uint32_t)q, (uint32_t)P);
+    }
+    mfft<R, Q, RL, true>(v, lds, idx, q, P, pd);
+
+    // ---------------- store the real parts
+    if (!active) return;
+    R* out = (R*)pd.rvo.ptr;
+    const int64_t base = row_base(pd.rvo);
+    if (base < 0) return;
+    const int64_t sl = pick3(pd.rvo.stride, pd.d - 1), el = pick3(pd.rvo.ext, pd.d - 1);
+    const RowKeep rk = keep_row(pd.keep, pd.d, b, ii);
+    const bool interval = KIND == ROW_C2R_ODD && pd.keep.enabled && pd.keep.face_axis >= 0 &&
+                          pd.keep.face_axis != pd.d - 1;
+    int64_t mlo = 0, mhi = -1;
+    if (interval) {
+        const int la = pd.d - 1;
+        const int64_t goff = pick3(pd.keep.gorg, la) + b * pick3(pd.keep.gbstep, la);
+        const int64_t s = 1 + ((pd.keep.half_axes >> la) & 1);
+        mlo = s * (rk.epre - 1) - goff;
+        mhi = pick3(pd.keep.gdim, la) - s * (rk.epre - 1) - 1 - goff;
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int64_t m = q + P * i;
+        if (m >= el) continue;
+        if (interval) {
+            if (m < mlo || m > mhi) continue;
+        } else if (pd.keep.enabled && !keep_last(pd.keep, rk, pd.d, b, m)) {
+            continue;
+        }
+        out[base + m * sl] = v[i].x;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Column passes
 // ---------------------------------------------------------------------------
@@ -496,13 +617,17 @@ constexpr int mrow_waves() { return (sizeof(R) == 4 && Q == 10 && KIND != ROW_MI
 template <typename R, int KIND, int Q, int RL>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, kMRowThreads), amdgpu_waves_per_eu(mrow_waves<R, KIND, Q>())))
 void k_mrow(PassDesc pd, SymParams sp) {
-    mrow_tile<R, KIND, Q, RL>(pd, sp, blockIdx.x);
+    if constexpr (KIND >= ROW_R2C_ODD) mrow_odd_tile<R, KIND, Q, RL>(pd, sp, blockIdx.x);
+    else mrow_tile<R, KIND, Q, RL>(pd, sp, blockIdx.x);
 }
 template <typename R, int KIND, int Q, int RL>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, kMRowThreads), amdgpu_waves_per_eu(mrow_waves<R, KIND, Q>())))
 void k_mrow_b(const BatchItem* it, int n, const SymParams* sy) {
     const int i = batch_find_m(it, n, blockIdx.x);
-    mrow_tile<R, KIND, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
+    if constexpr (KIND >= ROW_R2C_ODD)
+        mrow_odd_tile<R, KIND, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
+    else
+        mrow_tile<R, KIND, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
 }
 // The 20- and 25-point FP32 fused middle passes take about 190 VGPRs unconstrained
 // (two waves per SIMD); three waves per SIMD fit one more workgroup per CU.
@@ -543,7 +668,19 @@ hipError_t launch_q(const PassDesc& pd, const SymParams& sp, size_t lds, hipStre
             switch (pd.fast_kind) {
                 case ROW_R2C: SFFT_MROW(ROW_R2C) break;
                 case ROW_C2R: SFFT_MROW(ROW_C2R) break;
-                default: SFFT_MROW(ROW_MIDR) break;
+                case ROW_MIDR: SFFT_MROW(ROW_MIDR) break;
+                default:
+                    // odd real lengths: odd Q only
+                    if constexpr (Q % 2 == 1) {
+                        switch (pd.fast_kind) {
+                            case ROW_R2C_ODD: SFFT_MROW(ROW_R2C_ODD) break;
+                            case ROW_C2R_ODD: SFFT_MROW(ROW_C2R_ODD) break;
+                            case ROW_MIDR_ODD: SFFT_MROW(ROW_MIDR_ODD) break;
+                            default: return hipErrorInvalidValue;
+                        }
+                    } else {
+                        return hipErrorInvalidValue;
+                    }
             }
 #undef SFFT_MROW
         }

@@ -41,6 +41,16 @@ SHAPES = [
     (175, 126),       # columns 175 = 5^2 7 (gather), rows 63 = 3^2 7
     (189, 20),        # columns 189 = 3^3 7
     (1050, 16),       # columns 1050 = 2 3 5^2 7 split in levels
+    # odd real rows: one n-point complex transform per row, the half spectrum
+    # stored, the mirrors rebuilt as conjugates on the way back
+    (64, 125),        # rows 125 = 5^3
+    (30, 49),         # rows 49 = 7^2
+    (20, 27),         # rows 27 = 3^3
+    (12, 105),        # rows 105 = 3 5 7 (gather)
+    (10, 12, 35),     # 3-D, rows 35 = 5 7 (gather)
+    (125,),           # 1-D whole solve, odd
+    (343,),           # 1-D whole solve, 7^3
+    (945,),           # 1-D whole solve, 3^3 5 7
 ]
 
 
@@ -56,7 +66,7 @@ def test_mixed_radix_full_spectrum(shape, dtype):
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("shape", [(2000, 1000), (96, 768), (20, 40, 100), (640,), (630, 420), (210, 3360),
-                                   (49, 98), (35, 84), (210, 60), (54, 486)])
+                                   (49, 98), (35, 84), (210, 60), (54, 486), (64, 125), (945,)])
 def test_mixed_radix_long_damped(shape, dtype):
     rng = np.random.default_rng(31)
     c = np.abs(rng.uniform(size=(3,) * len(shape)))

@@ -117,3 +117,14 @@ def test_lengths_mixing_primes_take_register_columns(L, dtype):
     prime with any Q (35, 42, 210, ...) run on the register kernels."""
     cols, _ = _strided_levels((L, 64), dtype)
     assert len(cols) == 1 and cols[0]["mixed_q"], (L, cols)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("shape", [(64, 125), (30, 49), (20, 27), (12, 105), (125,), (343,), (945,), (10, 12, 35)])
+def test_odd_real_rows_take_register_kernels(shape, dtype):
+    """Odd last extents: the rows are n-point complex transforms on the register
+    kernels (odd points per thread), not the generic ones."""
+    import paper_2105_06676_amd as sfft
+    rows = [p for p in sfft.plan_describe(shape, dtype)["passes"] if p["kind"] == "row"]
+    assert rows and all(p["mixed_q"] % 2 == 1 for p in rows), (shape, rows)
+    assert all(p["L"] == shape[-1] for p in rows), (shape, rows)
