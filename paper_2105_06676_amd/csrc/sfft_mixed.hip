@@ -514,6 +514,41 @@ __device__ __forceinline__ void mrow_odd_tile(const PassDesc& pd, const SymParam
     }
 }
 
+// Complex middle rows of a 1-D axis split into strided levels and a row level
+// (ROW_MIDC): load the row, forward transform, multiply position k by the symbol
+// power of its axis-0 frequency (the digit-reversed prefix of the strided levels
+// plus (n / L) k), inverse transform, store.
+template <typename R, int Q, int RL>
+__device__ __forceinline__ void mrow_c2c_tile(const PassDesc& pd, const SymParams& sp, uint32_t bid) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
+    const int L = pd.L;
+    const int P = L / Q;
+    const int NTR = pd.W;
+    const int LS = L + L / 16 + 2;
+    uint32_t rr_u;
+    const int q = (int)udiv_qr((uint32_t)threadIdx.x, udiv((uint32_t)P), &rr_u);
+    const int rr = (int)rr_u;
+    const int64_t row = (int64_t)bid * NTR + rr;
+    const bool active = row < pd.outer;
+    const MRowIdx idx{rr * LS};
+    cx<R> v[Q];
+    const cx<R>* src = (const cx<R>*)pd.buf + (active ? row : 0) * pd.ostride + q;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = active ? src[P * i] : cx<R>{R(0), R(0)};
+    mfft<R, Q, RL, false>(v, lds, idx, q, P, pd);
+    const int64_t qd = active ? (row % pd.q_mod) : 0;
+    const int64_t fp = pos_to_freq(sp, 0, qd * L);
+    const int64_t M = sp.n[0] / L;
+    const SymCol col = symbol_column_1d(sp);
+    apply_symbol<R, kMRowThreads, Q, kMGroup<Q>()>(v, lds, sp, col, (uint32_t)(fp + M * q), (uint32_t)(M * P));
+    mfft<R, Q, RL, true>(v, lds, idx, q, P, pd);
+    if (!active) return;
+    cx<R>* dst = (cx<R>*)pd.buf + row * pd.ostride + q;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[P * i] = v[i];
+}
+
 // ---------------------------------------------------------------------------
 // Column passes
 // ---------------------------------------------------------------------------
@@ -612,12 +647,13 @@ __device__ __forceinline__ int batch_find_m(const BatchItem* it, int n, uint32_t
 // about 110 VGPRs, four waves per SIMD, so only two 7-wave rows fit a CU.  Six
 // waves per SIMD (80 VGPRs, a few words of spill) fit three.
 template <typename R, int KIND, int Q>
-constexpr int mrow_waves() { return (sizeof(R) == 4 && Q == 10 && KIND != ROW_MIDR) ? 6 : 1; }
+constexpr int mrow_waves() { return (sizeof(R) == 4 && Q == 10 && KIND != ROW_MIDR && KIND != ROW_MIDC) ? 6 : 1; }
 
 template <typename R, int KIND, int Q, int RL>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, kMRowThreads), amdgpu_waves_per_eu(mrow_waves<R, KIND, Q>())))
 void k_mrow(PassDesc pd, SymParams sp) {
     if constexpr (KIND >= ROW_R2C_ODD) mrow_odd_tile<R, KIND, Q, RL>(pd, sp, blockIdx.x);
+    else if constexpr (KIND == ROW_MIDC) mrow_c2c_tile<R, Q, RL>(pd, sp, blockIdx.x);
     else mrow_tile<R, KIND, Q, RL>(pd, sp, blockIdx.x);
 }
 template <typename R, int KIND, int Q, int RL>
@@ -626,6 +662,8 @@ void k_mrow_b(const BatchItem* it, int n, const SymParams* sy) {
     const int i = batch_find_m(it, n, blockIdx.x);
     if constexpr (KIND >= ROW_R2C_ODD)
         mrow_odd_tile<R, KIND, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
+    else if constexpr (KIND == ROW_MIDC)
+        mrow_c2c_tile<R, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
     else
         mrow_tile<R, KIND, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
 }
@@ -669,6 +707,7 @@ hipError_t launch_q(const PassDesc& pd, const SymParams& sp, size_t lds, hipStre
                 case ROW_R2C: SFFT_MROW(ROW_R2C) break;
                 case ROW_C2R: SFFT_MROW(ROW_C2R) break;
                 case ROW_MIDR: SFFT_MROW(ROW_MIDR) break;
+                case ROW_MIDC: SFFT_MROW(ROW_MIDC) break;
                 default:
                     // odd real lengths: odd Q only
                     if constexpr (Q % 2 == 1) {

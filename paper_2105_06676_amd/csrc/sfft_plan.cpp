@@ -365,7 +365,8 @@ static PassPlan make_row(const Ctx& c, int64_t rows, int L, int rowtrans, int mo
     }
     int mq = 0, mst = 0;
     int64_t mrad = 0;
-    if (!fast_ok && allow_fast && (rowtrans == RT_HALF || (rowtrans == RT_ODD && L % 2 == 1)) &&
+    if (!fast_ok && allow_fast &&
+        (rowtrans == RT_HALF || (rowtrans == RT_ODD && L % 2 == 1) || (rowtrans == RT_C2C && mode == MODE_MID)) &&
         mixed_family(L, false, c.f64, &mq, &mrad, &mst)) {
         // register mixed-radix rows: P = L / Q threads per row, NTR rows per workgroup
         const int64_t P = L / mq;
@@ -385,7 +386,9 @@ static PassPlan make_row(const Ctx& c, int64_t rows, int L, int rowtrans, int mo
             pd.W = (int)ntr;
             pd.mthreads = (int)(ntr * P);
             pd.ntiles = (rows + ntr - 1) / ntr;
-            if (rowtrans == RT_ODD)
+            if (rowtrans == RT_C2C)
+                pd.fast_kind = ROW_MIDC;
+            else if (rowtrans == RT_ODD)
                 pd.fast_kind = mode == MODE_FWD ? ROW_R2C_ODD : mode == MODE_INV ? ROW_C2R_ODD : ROW_MIDR_ODD;
             else
                 pd.fast_kind = mode == MODE_FWD ? ROW_R2C : mode == MODE_INV ? ROW_C2R : ROW_MIDR;

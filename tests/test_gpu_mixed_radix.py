@@ -51,6 +51,10 @@ SHAPES = [
     (125,),           # 1-D whole solve, odd
     (343,),           # 1-D whole solve, 7^3
     (945,),           # 1-D whole solve, 3^3 5 7
+    # long 1-D axes: strided levels, then a complex row middle pass on these kernels
+    (100000,),        # 25 x 4000
+    (62500,),         # 20 x 3125
+    (18522,),         # 6 x 3087 = 3^2 7^3
 ]
 
 

@@ -128,3 +128,11 @@ def test_odd_real_rows_take_register_kernels(shape, dtype):
     rows = [p for p in sfft.plan_describe(shape, dtype)["passes"] if p["kind"] == "row"]
     assert rows and all(p["mixed_q"] % 2 == 1 for p in rows), (shape, rows)
     assert all(p["L"] == shape[-1] for p in rows), (shape, rows)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n", [100000, 40000, 18522, 1000000])
+def test_long_1d_complex_middle_rows_take_register_kernels(n, dtype):
+    import paper_2105_06676_amd as sfft
+    mids = [p for p in sfft.plan_describe((n,), dtype)["passes"] if p["kind"] == "row"]
+    assert len(mids) == 1 and mids[0]["mixed_q"], (n, mids)
