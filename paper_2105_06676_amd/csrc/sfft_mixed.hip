@@ -1,26 +1,31 @@
-// Register mixed-radix pass kernels (gfx950) for lengths of the form
-// 2^a 5^b, 2^a 3^b and 5^b (5, 10, 12, 20 or 25 points per thread).
+// Register mixed-radix pass kernels (gfx950) for 7-smooth lengths: 5, 7, 9, 10,
+// 12, 14, 15, 20, 21 or 25 points per thread, by the length's family.
 //
 // A transform of L points is done by P = L/Q threads that each hold Q points
-// (Q a compile-time constant of the length's family, every stage radix dividing
-// it): thread q holds x[q + P i], i < Q, on entry and on exit (natural order).
-// The first Stockham stage has radix Q: a thread's Q registers are one butterfly,
-// computed as a composite in-register DFT (Q = A B: B transforms of length A, the
-// constant twiddles, A transforms of length B).  The last stage leaves its
-// outputs in the registers; every stage in between exchanges the points through
+// (Q a compile-time constant of the length's family): thread q holds x[q + P i],
+// i < Q, on entry and on exit (natural order).  The first Stockham stage has
+// radix Q: a thread's Q registers are one butterfly, computed as a composite
+// in-register DFT (Q = A B: B transforms of length A, the constant twiddles, A
+// transforms of length B).  The last stage leaves its outputs in the registers
+// when its radix divides Q; every stage in between exchanges the points through
 // LDS once, with the stage twiddles read from the pass's table
-// exp(-2 pi i m / (L st_mul)).  Most of a length is covered by radix-Q stages, so
-// a transform takes few LDS exchanges and barriers.  The stage list is packed in
+// exp(-2 pi i m / (L st_mul)).  Middle stages whose radix does not divide Q
+// spread their butterflies unevenly over the threads (guarded); a last radix that
+// divides no Q runs like a middle stage and the threads read their outputs back
+// from LDS (gather).  Most of a length is covered by radix-Q stages, so a
+// transform takes few LDS exchanges and barriers.  The stage list is packed in
 // PassDesc::mrad (5 bits per stage), so the kernels index no array at run time;
 // divisions by the run-time, workgroup-uniform P, W and Ns go through the float
 // reciprocal of sfft_device.h.  The same tile code (loads, the real-data
 // untangling, the fused symbol step, keep rules, stores) as the power-of-two
-// register kernels; lengths outside these families run on the generic kernels.
+// register kernels.
 //
 // Kernels:
-//  k_mrow<R, KIND, Q, RL>  rows: R2C first pass, C2R last pass, whole 1-D real solve
+//  k_mrow<R, KIND, Q, RL>  rows: R2C first pass, C2R last pass, whole 1-D real
+//                          solve (even and odd real lengths), complex middle rows
+//                          of split 1-D axes
 //  k_mcol<R, MODE, Q, RL>  strided axis: forward / inverse / fused middle pass
-// (RL: radix of the last stage)
+// (RL: radix of the last stage; 1 for the gather form)
 #include <hip/hip_runtime.h>
 
 #include "sfft_device.h"
