@@ -82,7 +82,12 @@ def test_verify_aperiodic_full_size_workload(dtype):
 @pytest.mark.parametrize("dims", [(8192, 8192), (8000, 8000), (6300, 6720), (4000, 4000), (512, 512, 512),
                                   (400, 400, 400), (800, 800, 800), (65536,), (16384,), (1 << 20,), (2000, 1000),
                                   (250, 160), (96, 768), (75, 50), (20, 40, 100), (640,), (1536, 40), (3, 5),
-                                  (1,), (2, 2, 2)])
+                                  (1,), (2, 2, 2),
+                                  # 7- and 9-point families, gather stages, odd real rows, long 1-D
+                                  # axes with complex middle rows, single strided passes up to 1024
+                                  (49, 98), (343, 16), (54, 486), (35, 84), (210, 60), (105, 70, 20),
+                                  (64, 125), (12, 105), (10, 12, 35), (125,), (945,), (100000,), (18522,),
+                                  (1536, 4096), (1280, 64), (640, 200, 256), (1470, 2800)])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_verify_periodic_schedules(dims, dtype):
     import paper_2105_06676_amd as sfft
