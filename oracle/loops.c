@@ -76,7 +76,7 @@ int oracle_periodic(double* a, int ndim, const int64_t* dims, const double* coef
     double* dst = b;
     if (nthreads <= 0) nthreads = oracle_threads();
     for (int64_t t = 0; t < T; ++t) {
-#pragma omp parallel for schedule(static) num_threads(nthreads)
+#pragma omp parallel for collapse(3) schedule(static) num_threads(nthreads)
         for (int64_t i0 = 0; i0 < n[0]; ++i0) {
             for (int64_t i1 = 0; i1 < n[1]; ++i1) {
                 for (int64_t i2 = 0; i2 < n[2]; ++i2) {
@@ -151,7 +151,7 @@ int oracle_aperiodic_bc(double* a, int ndim, const int64_t* dims, const double* 
                     }
         }
         if (t == T) break;
-#pragma omp parallel for schedule(static) num_threads(nthreads)
+#pragma omp parallel for collapse(3) schedule(static) num_threads(nthreads)
         for (int64_t i0 = rr[0]; i0 < rr[0] + n[0]; ++i0) {
             for (int64_t i1 = rr[1]; i1 < rr[1] + n[1]; ++i1) {
                 for (int64_t i2 = rr[2]; i2 < rr[2] + n[2]; ++i2) {
@@ -200,7 +200,7 @@ int oracle_periodic_fields(double* a, int m, int ndim, const int64_t* dims, cons
     if (nthreads <= 0) nthreads = oracle_threads();
     for (int64_t t = 0; t < T; ++t) {
         for (int i = 0; i < m; ++i) {
-#pragma omp parallel for schedule(static) num_threads(nthreads)
+#pragma omp parallel for collapse(3) schedule(static) num_threads(nthreads)
             for (int64_t i0 = 0; i0 < n[0]; ++i0) {
                 for (int64_t i1 = 0; i1 < n[1]; ++i1) {
                     for (int64_t i2 = 0; i2 < n[2]; ++i2) {
