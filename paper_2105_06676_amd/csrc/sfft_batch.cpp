@@ -144,8 +144,12 @@ BatchProgram build_batch(std::vector<ProblemRun>& runs, const BatchMem& mem, con
             // one launch per kernel variant (for the mixed-radix kernels: points per
             // thread and last-stage radix, and the workgroup size, since the tile
             // code assumes W * P threads)
-            auto key = pd.mq ? std::make_tuple(2, pd.kind, pd.mode, pd.fast_kind, pd.mq,
-                                               mixed_radix_at(pd.mrad, pd.nst - 1), (int)f64, pd.mthreads)
+            // (10-point rows with a radix-4 middle stage run a kernel variant of their own)
+            int variant = mixed_radix_at(pd.mrad, pd.nst - 1);
+            if (pd.mq == 10 && pd.kind == PASS_ROW)
+                for (int s = 1; s + 1 < pd.nst; ++s)
+                    if (mixed_radix_at(pd.mrad, s) == 4) variant += 100;
+            auto key = pd.mq ? std::make_tuple(2, pd.kind, pd.mode, pd.fast_kind, pd.mq, variant, (int)f64, pd.mthreads)
                        : pd.fast ? std::make_tuple(1, pd.kind, pd.mode, pd.fast_kind, pd.logL, 0, (int)f64, 0)
                                  : std::make_tuple(0, pd.kind, 0, 0, 0, 0, (int)f64, 0);
             groups[key].push_back((int)i);

@@ -144,13 +144,16 @@ __device__ __forceinline__ void mstage(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q
 }
 
 // Middle stages: the radices that divide Q, and for the families that mix 3, 5
-// and 7 (Q = 7, 9, 12, 14, 15, 21) also 2, 3, 4, 5 and 7 with guarded butterflies.
-template <typename R, int Q, bool INV, bool FIRST, bool LAST, typename IDX>
+// and 7 (Q = 7, 9, 12, 14, 15, 21) also 2, 3, 4, 5 and 7 with guarded butterflies;
+// X4: also a guarded radix 4 (10-point first-pass rows, where it replaces two
+// radix-2 exchanges by one; a separate kernel variant, so the other 10-point
+// kernels keep their registers).
+template <typename R, int Q, bool INV, bool FIRST, bool LAST, bool X4 = false, typename IDX>
 __device__ __forceinline__ void mstage_rad(int rad, cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, int P, int L, int NS,
                                            const cx<R>* tab, int tmul) {
 #define SFFT_MST(RAD)                                                                                      if constexpr (Q % RAD == 0) mstage<R, Q, RAD, INV, FIRST, LAST>(v, lds, idx, q, P, L, NS, tab, tmul);
 #define SFFT_MSTG(RAD)                                                                                     \
-    if constexpr (Q % RAD == 0 || Q == 7 || Q == 9 || Q == 12 || Q == 14 || Q == 15 || Q == 21)            \
+    if constexpr (Q % RAD == 0 || Q == 7 || Q == 9 || Q == 12 || Q == 14 || Q == 15 || Q == 21 || (X4 && RAD == 4)) \
         mstage<R, Q, RAD, INV, FIRST, LAST>(v, lds, idx, q, P, L, NS, tab, tmul);
     switch (rad) {
         case 2: SFFT_MSTG(2) break;
@@ -187,7 +190,7 @@ __device__ __forceinline__ void mstage_rad(int rad, cx<R> (&v)[Q], cx<R>* lds, I
 // the outputs in natural order there, and each thread reads its Q points back
 // (one more exchange, for lengths no register family takes otherwise, such as
 // 35, 42 or 210 points).
-template <typename R, int Q, int RL, bool INV, typename IDX>
+template <typename R, int Q, int RL, bool INV, bool X4 = false, typename IDX>
 __device__ __forceinline__ void mfft(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, int P, const PassDesc& pd) {
     const cx<R>* tab = (const cx<R>*)pd.st_tab;
     const int L = pd.L, tmul = pd.st_mul, nst = pd.nst;
@@ -197,7 +200,7 @@ __device__ __forceinline__ void mfft(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, 
     constexpr int NMID_END = RL == 1 ? 0 : 1;  // stages left for the register stage
     for (int s = 1; s < nst - NMID_END; ++s) {
         const int rad = mixed_radix_at((int64_t)rads, s);
-        mstage_rad<R, Q, INV, false, false>(rad, v, lds, idx, q, P, L, NS, tab, tmul);
+        mstage_rad<R, Q, INV, false, false, X4>(rad, v, lds, idx, q, P, L, NS, tab, tmul);
         NS *= rad;
     }
     if constexpr (RL == 1) {
@@ -213,7 +216,7 @@ __device__ __forceinline__ void mfft(cx<R> (&v)[Q], cx<R>* lds, IDX idx, int q, 
 // ---------------------------------------------------------------------------
 // Row passes
 // ---------------------------------------------------------------------------
-template <typename R, int KIND, int Q, int RL>
+template <typename R, int KIND, int Q, int RL, bool X4 = false>
 __device__ __forceinline__ void mrow_tile(const PassDesc& pd, const SymParams& sp, uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
@@ -293,7 +296,7 @@ __device__ __forceinline__ void mrow_tile(const PassDesc& pd, const SymParams& s
     if (KIND == ROW_C2R) {
         if (q == 0) lds[idx(L)] = active ? ((const cx<R>*)pd.buf)[row * pd.ostride + L] : cx<R>{R(0), R(0)};
     } else {
-        mfft<R, Q, RL, false>(v, lds, idx, q, P, pd);
+        mfft<R, Q, RL, false, X4>(v, lds, idx, q, P, pd);
     }
 
     if (KIND == ROW_R2C || KIND == ROW_MIDR) {
@@ -354,7 +357,7 @@ __device__ __forceinline__ void mrow_tile(const PassDesc& pd, const SymParams& s
     }
     __syncthreads();
 
-    mfft<R, Q, RL, true>(v, lds, idx, q, P, pd);
+    mfft<R, Q, RL, true, X4>(v, lds, idx, q, P, pd);
 
     // ---------------- store: x[2m] = Re z[m], x[2m+1] = Im z[m]
     if (!active) return;
@@ -523,7 +526,7 @@ __device__ __forceinline__ void mrow_odd_tile(const PassDesc& pd, const SymParam
 // (ROW_MIDC): load the row, forward transform, multiply position k by the symbol
 // power of its axis-0 frequency (the digit-reversed prefix of the strided levels
 // plus (n / L) k), inverse transform, store.
-template <typename R, int Q, int RL>
+template <typename R, int Q, int RL, bool X4 = false>
 __device__ __forceinline__ void mrow_c2c_tile(const PassDesc& pd, const SymParams& sp, uint32_t bid) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     cx<R>* lds = reinterpret_cast<cx<R>*>(smem_raw);
@@ -541,13 +544,13 @@ __device__ __forceinline__ void mrow_c2c_tile(const PassDesc& pd, const SymParam
     const cx<R>* src = (const cx<R>*)pd.buf + (active ? row : 0) * pd.ostride + q;
 #pragma unroll
     for (int i = 0; i < Q; ++i) v[i] = active ? src[P * i] : cx<R>{R(0), R(0)};
-    mfft<R, Q, RL, false>(v, lds, idx, q, P, pd);
+    mfft<R, Q, RL, false, X4>(v, lds, idx, q, P, pd);
     const int64_t qd = active ? (row % pd.q_mod) : 0;
     const int64_t fp = pos_to_freq(sp, 0, qd * L);
     const int64_t M = sp.n[0] / L;
     const SymCol col = symbol_column_1d(sp);
     apply_symbol<R, kMRowThreads, Q, kMGroup<Q>()>(v, lds, sp, col, (uint32_t)(fp + M * q), (uint32_t)(M * P));
-    mfft<R, Q, RL, true>(v, lds, idx, q, P, pd);
+    mfft<R, Q, RL, true, X4>(v, lds, idx, q, P, pd);
     if (!active) return;
     cx<R>* dst = (cx<R>*)pd.buf + row * pd.ostride + q;
 #pragma unroll
@@ -654,23 +657,23 @@ __device__ __forceinline__ int batch_find_m(const BatchItem* it, int n, uint32_t
 template <typename R, int KIND, int Q>
 constexpr int mrow_waves() { return (sizeof(R) == 4 && Q == 10 && KIND != ROW_MIDR && KIND != ROW_MIDC) ? 6 : 1; }
 
-template <typename R, int KIND, int Q, int RL>
+template <typename R, int KIND, int Q, int RL, bool X4 = false>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, kMRowThreads), amdgpu_waves_per_eu(mrow_waves<R, KIND, Q>())))
 void k_mrow(PassDesc pd, SymParams sp) {
     if constexpr (KIND >= ROW_R2C_ODD) mrow_odd_tile<R, KIND, Q, RL>(pd, sp, blockIdx.x);
-    else if constexpr (KIND == ROW_MIDC) mrow_c2c_tile<R, Q, RL>(pd, sp, blockIdx.x);
-    else mrow_tile<R, KIND, Q, RL>(pd, sp, blockIdx.x);
+    else if constexpr (KIND == ROW_MIDC) mrow_c2c_tile<R, Q, RL, X4>(pd, sp, blockIdx.x);
+    else mrow_tile<R, KIND, Q, RL, X4>(pd, sp, blockIdx.x);
 }
-template <typename R, int KIND, int Q, int RL>
+template <typename R, int KIND, int Q, int RL, bool X4 = false>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, kMRowThreads), amdgpu_waves_per_eu(mrow_waves<R, KIND, Q>())))
 void k_mrow_b(const BatchItem* it, int n, const SymParams* sy) {
     const int i = batch_find_m(it, n, blockIdx.x);
     if constexpr (KIND >= ROW_R2C_ODD)
         mrow_odd_tile<R, KIND, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
     else if constexpr (KIND == ROW_MIDC)
-        mrow_c2c_tile<R, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
+        mrow_c2c_tile<R, Q, RL, X4>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
     else
-        mrow_tile<R, KIND, Q, RL>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
+        mrow_tile<R, KIND, Q, RL, X4>(it[i].pd, sy[it[i].sym], (uint32_t)(blockIdx.x - it[i].first));
 }
 // The 20- and 25-point FP32 fused middle passes take about 190 VGPRs unconstrained
 // (two waves per SIMD); three waves per SIMD fit one more workgroup per CU.
@@ -708,6 +711,20 @@ hipError_t launch_q(const PassDesc& pd, const SymParams& sp, size_t lds, hipStre
 #define SFFT_MROW(K)                                                                               \
     if (ba) hipLaunchKernelGGL((k_mrow_b<R, K, Q, RL>), g, b, lds, st, ba->items, ba->n, ba->syms);     \
     else hipLaunchKernelGGL((k_mrow<R, K, Q, RL>), g, b, lds, st, pd, sp);
+            if constexpr (Q == 10 && RL == 10) {
+                bool x4 = false;
+                for (int s = 1; s + 1 < pd.nst; ++s) x4 = x4 || mixed_radix_at(pd.mrad, s) == 4;
+                if (x4) {
+#define SFFT_MROW4(K)                                                                                \
+    if (ba) hipLaunchKernelGGL((k_mrow_b<R, K, Q, RL, true>), g, b, lds, st, ba->items, ba->n, ba->syms); \
+    else hipLaunchKernelGGL((k_mrow<R, K, Q, RL, true>), g, b, lds, st, pd, sp);
+                    // (the planner gives radix-4 stages to first-pass rows only)
+                    if (pd.fast_kind != ROW_R2C) return hipErrorInvalidValue;
+                    SFFT_MROW4(ROW_R2C)
+#undef SFFT_MROW4
+                    return hipGetLastError();
+                }
+            }
             switch (pd.fast_kind) {
                 case ROW_R2C: SFFT_MROW(ROW_R2C) break;
                 case ROW_C2R: SFFT_MROW(ROW_C2R) break;
@@ -746,6 +763,19 @@ template <typename R>
 hipError_t launch_m(const PassDesc& pd, const SymParams& sp, size_t lds, hipStream_t st, const MBatch* ba) {
     if (pd.nst < 2) return hipErrorInvalidValue;
     const int rl = mixed_radix_at(pd.mrad, pd.nst - 1);
+    // every middle radix must have a stage in the kernel variant chosen below (a
+    // radix without one would be skipped, not reported)
+    const int Q = pd.mq;
+    const bool guarded = Q == 7 || Q == 9 || Q == 12 || Q == 14 || Q == 15 || Q == 21;
+    const bool x4 = Q == 10 && rl == 10 && pd.kind == PASS_ROW && pd.fast_kind == ROW_R2C;
+    for (int s = 1; s < pd.nst - (Q % rl ? 0 : 1); ++s) {
+        const int rad = mixed_radix_at(pd.mrad, s);
+        const bool small = rad == 2 || rad == 3 || rad == 4 || rad == 5 || rad == 7;
+        const bool listed = rad == 6 || rad == 9 || rad == 10 || rad == 12 || rad == 14 || rad == 15 ||
+                            rad == 20 || rad == 21 || rad == 25;
+        const bool ok = (Q % rad == 0 && (small || listed)) || (guarded && small) || (x4 && rad == 4);
+        if (!ok) return hipErrorInvalidValue;
+    }
     // (Q, last radix) pairs the planner's canonical order produces
     // (FP32 only for 20 and 25 points per thread: FP64 would hold one wave per SIMD)
     // last radix not dividing Q: the gather form (families 7, 9, 12, 14, 15, 21)

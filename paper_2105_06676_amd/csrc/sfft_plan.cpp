@@ -379,6 +379,28 @@ static PassPlan make_row(const Ctx& c, int64_t rows, int L, int rowtrans, int mo
         // at most ~48 KB of LDS per workgroup, so that three fit a compute unit
         while (ntr > 1 && bytes(ntr) > 48 * 1024) --ntr;
         if (bytes(ntr) <= 128 * 1024) {
+            if (mq == 10 && mode == MODE_FWD && rowtrans == RT_HALF && mixed_radix_at(mrad, mst - 1) == 10) {
+                // first-pass 10-point rows: two radix-2 middle stages become one guarded
+                // radix-4 stage (one LDS exchange fewer; measured faster there, slower in
+                // the last pass, whose variant keeps the radix-2 stages)
+                std::vector<int> rs, keep;
+                int twos = 0;
+                for (int i = 1; i + 1 < mst; ++i) {
+                    const int x = mixed_radix_at(mrad, i);
+                    if (x == 2) ++twos;
+                    else keep.push_back(x);
+                }
+                if (twos >= 2) {
+                    rs.push_back(10);
+                    rs.insert(rs.end(), keep.begin(), keep.end());
+                    for (; twos >= 2; twos -= 2) rs.push_back(4);
+                    if (twos) rs.push_back(2);
+                    rs.push_back(10);
+                    mrad = 0;
+                    for (size_t i = 0; i < rs.size(); ++i) mrad |= (int64_t)rs[i] << (kMRadBits * i);
+                    mst = (int)rs.size();
+                }
+            }
             pd.mq = mq;
             pd.mrad = mrad;
             pd.nst = mst;

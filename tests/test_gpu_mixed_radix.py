@@ -51,6 +51,10 @@ SHAPES = [
     (125,),           # 1-D whole solve, odd
     (343,),           # 1-D whole solve, 7^3
     (945,),           # 1-D whole solve, 3^3 5 7
+    # 10-point rows with a guarded radix-4 middle stage (the rows' own kernel variant)
+    (16, 8000),       # rows 4000 = 10 10 4 10
+    (6, 800),         # rows 400 = 10 4 10
+    (8000,),          # 1-D whole solve, L = 4000
     # long 1-D axes: strided levels, then a complex row middle pass on these kernels
     (100000,),        # 25 x 4000
     (62500,),         # 20 x 3125
