@@ -389,11 +389,12 @@ def cpu_baseline(w, budget_s: float = 12.0):
     dt = time.perf_counter() - t0
     cells = int(np.prod(w.dims))
     rec = {"value": cells * steps / dt, "unit": "cell-updates/s", "cores": nthr, "kind": "oracle",
-           "sample": f"full {w.dims[0]}x{w.dims[1]} grid, {steps} of the {w.T} steps "
+           "sample": f"full {'x'.join(map(str, w.dims))} grid, {steps} of the {w.T} steps "
                      f"(FP64 nested loop, OpenMP, {dt:.1f} s)"}
     # one thread on a shortened problem (the first rows of the grid, periodic on
     # that crop), and the host it ran on
-    rows = max(1, min(w.dims[0], (1 << 23) // w.dims[1]))
+    inner = int(np.prod(w.dims[1:])) if len(w.dims) > 1 else 1
+    rows = max(1, min(w.dims[0], (1 << 23) // inner))
     crop = np.ascontiguousarray(a0[:rows])
     t0 = time.perf_counter()
     oracle.periodic(crop, w.coeffs, 1, nthreads=1)
@@ -404,7 +405,7 @@ def cpu_baseline(w, budget_s: float = 12.0):
     dt1 = time.perf_counter() - t0
     one = crop.size * s1 / dt1
     rec["one_thread"] = {"value": one, "unit": "cell-updates/s",
-                         "sample": f"{rows}x{w.dims[1]} crop, {s1} steps ({dt1:.1f} s)",
+                         "sample": f"{'x'.join(map(str, crop.shape))} crop, {s1} steps ({dt1:.1f} s)",
                          "parallel_speedup": rec["value"] / one}
     rec["host"] = host_info()
     return rec, a0, steps, ref
